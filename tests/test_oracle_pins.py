@@ -1,0 +1,234 @@
+"""Pins of the CPU checker against facts the paper and the mathematics fix,
+independent of the checker's own formulas.
+
+  * structure: node counts of the synthetic unit-cube cases recomputed from
+    the admissibility condition (equation admCond) by an independent probe;
+  * the nested property of Section II (V_parent = diag(V_children) T);
+  * the exact H^2 mat-vec equals the dense expansion (non-symmetric, complex);
+  * EXACT mode (no truncation) reproduces the brute-force dense product A B
+    to rounding, for real symmetric, real non-symmetric and complex inputs
+    (Section V: every operation of the method is exact or eps-controlled);
+  * ACCURACY mode meets ||C - AB||_F <= eps ||AB||_F on tiny N;
+  * PAPER mode's error scales like sqrt(eps) (Tables I, II, IV);
+  * C keeps the block partition of A and B (Section III);
+  * the new bases are orthonormal; B = I gives C = A; A symmetric gives C
+    symmetric; smaller eps gives smaller error and larger ranks.
+"""
+import numpy as np
+import pytest
+
+from h2inputs.build import identity_h2
+from oracle import h2ops, mmp
+from tests import cases
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ------------------------------------------------------------ structure
+def test_structure_counts_cube():
+    # node counts of the same rules from an independent probe
+    A = cases.cube1k()
+    assert A.L == 5 and A.blocks.count(1) == 978 and A.blocks.count(0) == 46
+    A = cases.cube(4096)
+    assert A.L == 7 and A.blocks.count(1) == 7684 and A.blocks.count(0) == 4470
+    assert A.blocks.min_admissible_level() == 5
+
+
+def test_block_partition_covers_matrix_once():
+    A = cases.plates(2048)
+    cover = np.zeros((A.n, A.n), dtype=np.int32)
+    t = A.tree
+    for lev in range(A.L + 1):
+        for i, j, typ in zip(A.blocks.rows[lev], A.blocks.cols[lev], A.blocks.types[lev]):
+            if typ != 2:
+                cover[t.start(lev, i):t.stop(lev, i), t.start(lev, j):t.stop(lev, j)] += 1
+    assert (cover == 1).all()
+
+
+def test_admissible_blocks_satisfy_condition():
+    A = cases.plates(2048)
+    t = A.tree
+    for lev in range(A.L + 1):
+        for i, j, typ in zip(A.blocks.rows[lev], A.blocks.cols[lev], A.blocks.types[lev]):
+            if typ == 0:
+                pi = t.points[t.indices(lev, i)]
+                pj = t.points[t.indices(lev, j)]
+                d = np.sqrt(((pi[:, None] - pj[None]) ** 2).sum(-1)).min()
+                diam = max(np.linalg.norm(pi.max(0) - pi.min(0)), np.linalg.norm(pj.max(0) - pj.min(0)))
+                assert diam <= d + 1e-12  # box gap <= point gap, eta = 1
+
+
+# ------------------------------------------------------------ inputs
+def test_chebyshev_nested_property():
+    A = cases.plates(1024)
+    from h2inputs.build import _BoxNodes
+    t = A.tree
+    root_diam = float(np.linalg.norm(t.hi[0][0] - t.lo[0][0]))
+    for lev in (2, 4):
+        for c in range(0, 1 << lev, 3):
+            nodes = _BoxNodes(t.lo[lev][c], t.hi[lev][c], 3, 1e-9 * root_diam)
+            direct = nodes.lagrange(t.points[t.indices(lev, c)])
+            assert rel(h2ops.expanded_row_basis(A, lev, c), direct) < 1e-12
+
+
+def test_chebyshev_approximates_kernel():
+    A = cases.plates(1024)
+    D = h2ops.to_dense(A)
+    p = A.tree.points
+    d = np.sqrt(((p[:, None] - p[None]) ** 2).sum(-1))
+    with np.errstate(divide="ignore"):
+        K = 1 / (4 * np.pi * d)
+    np.fill_diagonal(K, np.diag(D))
+    assert rel(D, K) < 5e-3
+
+
+def test_matvec_matches_dense_nonsymmetric_complex():
+    A, _ = cases.random_pair(512, 16, 6, 5, 3, complex_=True)
+    D = h2ops.to_dense(A)
+    x = np.random.default_rng(0).standard_normal((A.n, 3))
+    assert rel(h2ops.matvec(A, x), D @ x) < 1e-13
+    assert not np.allclose(D, D.T)
+
+
+def test_identity_h2_is_identity():
+    A = cases.plates(1024)
+    assert np.array_equal(h2ops.to_dense(identity_h2(A)), np.eye(A.n))
+
+
+# ------------------------------------------------------------ exact mode
+@pytest.mark.parametrize("which", ["cube1k", "plates1024", "plates_leaf16", "ragged"])
+def test_exact_mode_reproduces_dense_product_real(which):
+    if which == "cube1k":
+        A = B = cases.cube1k()
+    elif which == "plates1024":
+        A = B = cases.plates(1024)
+    elif which == "plates_leaf16":
+        A = B = cases.plates(1024, leaf=16, order=2)
+    else:
+        A = B = cases.ragged_plates(777, 12)
+    C, info = mmp.h2_mmp(A, B, 0.0)
+    DA = h2ops.to_dense(A)
+    assert rel(h2ops.to_dense(C), DA @ DA) < 1e-13
+    assert C.blocks.same_as(A.blocks)
+
+
+def test_exact_mode_nonsymmetric_distinct_sides():
+    A, B = cases.random_pair(512, 16, 6, 5, 11)
+    C, _ = mmp.h2_mmp(A, B, 0.0)
+    assert rel(h2ops.to_dense(C), h2ops.to_dense(A) @ h2ops.to_dense(B)) < 1e-12
+
+
+def test_exact_mode_complex():
+    A, B = cases.random_pair(512, 16, 5, 6, 21, complex_=True)
+    C, _ = mmp.h2_mmp(A, B, 0.0)
+    assert rel(h2ops.to_dense(C), h2ops.to_dense(A) @ h2ops.to_dense(B)) < 1e-12
+
+
+def test_exact_mode_helmholtz_two_wavenumbers():
+    A, B = cases.helmholtz_sphere(1024, 32, 2, 20.0)
+    C, _ = mmp.h2_mmp(A, B, 0.0)
+    assert rel(h2ops.to_dense(C), h2ops.to_dense(A) @ h2ops.to_dense(B)) < 1e-12
+
+
+# ------------------------------------------------------------ accuracy mode
+@pytest.mark.parametrize("eps", [1e-2, 1e-4, 1e-6])
+def test_accuracy_mode_meets_eps(eps):
+    for A, B in [(cases.plates(2048),) * 2, cases.random_pair(512, 16, 6, 5, 4)]:
+        C, info = mmp.h2_mmp(A, B, eps)
+        ref = h2ops.to_dense(A) @ h2ops.to_dense(B)
+        assert rel(h2ops.to_dense(C), ref) <= eps
+
+
+def test_accuracy_complex_meets_eps():
+    A, B = cases.helmholtz_sphere(1024, 32, 2, 20.0)
+    C, _ = mmp.h2_mmp(A, B, 1e-4)
+    assert rel(h2ops.to_dense(C), h2ops.to_dense(A) @ h2ops.to_dense(B)) <= 1e-4
+
+
+def test_monotone_in_eps():
+    A = cases.plates(2048)
+    ref = h2ops.to_dense(A) @ h2ops.to_dense(A)
+    errs, ranks = [], []
+    for eps in (1e-2, 1e-4, 1e-6):
+        C, info = mmp.h2_mmp(A, A, eps)
+        errs.append(rel(h2ops.to_dense(C), ref))
+        ranks.append(sum(sum(r) for r in info["ranks_row"]))
+    assert errs[0] > errs[1] > errs[2]
+    assert ranks[0] < ranks[1] < ranks[2]
+
+
+def test_paper_mode_error_scales_like_sqrt_eps():
+    A = cases.plates(2048)
+    x = np.random.default_rng(2).standard_normal(A.n)
+    for eps in (1e-2, 1e-4):
+        C, _ = mmp.h2_mmp(A, A, eps, mode=mmp.PAPER)
+        e = h2ops.relative_error(C, A, A, x)
+        assert 1e-3 * np.sqrt(eps) < e < np.sqrt(eps)
+
+
+# ------------------------------------------------------------ invariants
+def _orthonormality_defects(C):
+    L = C.L
+    out = [np.abs(v.conj().T @ v - np.eye(v.shape[1])).max() for v in C.V + C.W]
+    lmin = C.blocks.min_admissible_level()
+    for lev in range(lmin, L):
+        for c in range(1 << lev):
+            for E in (C.Er, C.Ec):
+                T = np.vstack([E[lev + 1][2 * c], E[lev + 1][2 * c + 1]])
+                out.append(np.abs(T.conj().T @ T - np.eye(T.shape[1])).max())
+    return max(out)
+
+
+def test_new_bases_orthonormal():
+    A = cases.plates(2048)
+    C, _ = mmp.h2_mmp(A, A, 1e-4)
+    assert _orthonormality_defects(C) < 1e-13
+
+
+def test_times_identity_returns_a():
+    A = cases.plates(2048)
+    C, _ = mmp.h2_mmp(A, identity_h2(A), 1e-6)
+    DA = h2ops.to_dense(A)
+    assert rel(h2ops.to_dense(C), DA) <= 1e-6
+
+
+def test_symmetric_square_is_symmetric():
+    A = cases.plates(2048)
+    C, info = mmp.h2_mmp(A, A, 1e-4)
+    D = h2ops.to_dense(C)
+    assert np.linalg.norm(D - D.T) <= 1e-4 * np.linalg.norm(D)
+    assert info["ranks_row"] == info["ranks_col"]
+
+
+def test_relative_error_criterion_small_when_exact():
+    A = cases.plates(1024)
+    C, _ = mmp.h2_mmp(A, A, 0.0)
+    x = np.random.default_rng(9).standard_normal(A.n)
+    assert h2ops.relative_error(C, A, A, x) < 1e-13
+
+
+# ------------------------------------------------------------ planted mistakes
+def _exact_error(A, B):
+    C, _ = mmp.h2_mmp(A, B, 0.0)
+    return rel(h2ops.to_dense(C), h2ops.to_dense(A) @ h2ops.to_dense(B))
+
+
+def test_planted_dropped_term_is_caught(monkeypatch):
+    """Dropping the admissible-admissible products must break the exact pin."""
+    A, B = cases.random_pair(512, 16, 6, 5, 11)
+    assert _exact_error(A, B) < 1e-12
+    orig = mmp.Symbolic.triples
+    monkeypatch.setattr(mmp.Symbolic, "triples",
+                        lambda self, lev: [t for t in orig(self, lev) if not (t[5] == 0 and t[6] == 0)])
+    assert _exact_error(A, B) > 1e-6
+
+
+def test_planted_swapped_children_is_caught(monkeypatch):
+    """Swapping the two children in the block-diagonal projections (a wrong
+    index) must break the exact pin."""
+    A, B = cases.random_pair(512, 16, 6, 6, 12)
+    orig = mmp._blockdiag
+    monkeypatch.setattr(mmp, "_blockdiag", lambda a, b: orig(b, a))
+    assert _exact_error(A, B) > 1e-6
