@@ -1,0 +1,188 @@
+/*
+ * h2mmp: accuracy-controlled, structure-preserving H^2 matrix-matrix product
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. Ma and D. Jiao, "Accuracy Controlled Structure-Preserving
+ * H^2-Matrix-Matrix Product in Linear Complexity with Change of Cluster
+ * Bases" (arXiv 1908.05218).  C = A B is computed level by level from the
+ * leaves up (Sections III and IV): leaf dense-block products, coupling
+ * products through the cluster-basis products, and for every cluster a new
+ * basis of C found from normalised Gram sums truncated at eps, followed by a
+ * top-down split of couplings attached to non-leaf blocks.
+ *
+ * Conventions for every entry point:
+ *  - Functions return H2_OK or an error code; on error no output handle is
+ *    written, nothing leaks, and h2_last_error() returns a message
+ *    (thread-local, valid until the next call on the same thread).
+ *  - Host pointers are read during the call only; the library copies what it
+ *    keeps.  Device pointers are arguments only where a name says "_dev".
+ *  - Matrices are column-major.  Real FP64 only in this version
+ *    (is_complex != 0 is rejected with H2_ERR_UNSUPPORTED).
+ *  - All work runs on the context's own HIP stream (default priority); every
+ *    entry point returns after that stream has finished its work.
+ */
+#ifndef H2MMP_H
+#define H2MMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  H2_OK = 0,
+  H2_ERR_ARG = 1,         /* invalid argument (null pointer, negative size, bad mode) */
+  H2_ERR_DEVICE = 2,      /* HIP runtime failure or no usable device */
+  H2_ERR_OOM = 3,         /* device allocation failed or over the context's budget */
+  H2_ERR_STRUCTURE = 4,   /* A and B do not share tree and block partition */
+  H2_ERR_NUMERIC = 5,     /* non-finite input or result */
+  H2_ERR_UNSUPPORTED = 6, /* a size or feature this build does not handle */
+  H2_ERR_INTERNAL = 7
+} h2_status;
+
+typedef struct h2_ctx_s* h2_ctx;
+typedef struct h2_mat_s* h2_mat;
+
+/* Truncation rule for the eigenvalues lambda_1 >= lambda_2 ... of a cluster's
+ * summed normalised Gram matrix (Section III-C "singular vectors whose
+ * normalized singular values are greater than eps_trunc"):
+ *  ACCURACY: keep lambda_m > eps^2 lambda_1 (normalised singular values of
+ *            the stacked contributions above eps; aims at ||C-AB||_F <= eps ||AB||_F)
+ *  PAPER:    keep lambda_m > eps lambda_1 (the Gram's own singular values)
+ *  EXACT:    keep every eigenvector (no truncation; eps ignored) */
+typedef enum { H2_TRUNC_ACCURACY = 0, H2_TRUNC_PAPER = 1, H2_TRUNC_EXACT = 2 } h2_trunc_mode;
+
+/* Arithmetic of the bulk products.  FP64: everything in double.
+ * FP32_BULK: block products in float on the matrix cores, Gram sums,
+ * eigen-decompositions and bases in double. */
+typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32_BULK = 1 } h2_precision;
+
+/* Create a context on HIP device `device`.  hbm_budget (bytes) bounds the
+ * device memory the context may hold; 0 means no bound.  Errors:
+ * H2_ERR_DEVICE (no such device), H2_ERR_ARG (out == NULL). */
+h2_status h2_ctx_create(int device, size_t hbm_budget, h2_ctx* out);
+void h2_ctx_destroy(h2_ctx ctx);
+
+/* Host description of an H^2 matrix in the flat interchange layout
+ * (Section II: nested cluster bases V_t = diag(V_t1, V_t2)[E_t1; E_t2],
+ * coupling matrices of admissible blocks, dense leaf blocks):
+ *   n points, tree depth L (levels 0..L, 2^l clusters at level l);
+ *   leaf_off[2^L+1]: leaf c covers tree positions [leaf_off[c], leaf_off[c+1]);
+ *   perm[n]: original index of the point at tree position p;
+ *   node_off[L+2], node_row/col/type[]: block-tree nodes level by level,
+ *     type 0 = admissible, 1 = dense leaf, 2 = non-leaf;
+ *   krow/kcol[2^(L+1)-1]: rank of cluster (l,c) at index 2^l-1+c;
+ *   V/W: leaf bases (#leaf x rank), offsets V_off/W_off[2^L+1] in elements;
+ *   Er/Ec: transfer of cluster (l,c), l >= 1 (k(l,c) x k(l-1,c/2)), at the
+ *     flat cluster index, offsets Er_off/Ec_off[2^(L+1)];
+ *   S: coupling of every admissible node, offsets S_off[nnodes+1];
+ *   F: dense block of every dense node, offsets F_off[nnodes+1].
+ * Entries not used by a node have zero length. */
+typedef struct {
+  int64_t n, L, is_complex;
+  const int64_t* leaf_off;
+  const int64_t* perm;
+  const int64_t* node_off;
+  const int32_t* node_row;
+  const int32_t* node_col;
+  const int32_t* node_type;
+  const int64_t* krow;
+  const int64_t* kcol;
+  const double *V, *W, *Er, *Ec, *S, *F;
+  const int64_t *V_off, *W_off, *Er_off, *Ec_off, *S_off, *F_off;
+} h2_host_matrix;
+
+/* Upload an H^2 matrix to the device (padded per-level layout, FP64).
+ * Errors: H2_ERR_ARG (inconsistent offsets, sizes or types),
+ * H2_ERR_UNSUPPORTED (complex), H2_ERR_OOM. */
+h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out);
+
+/* C = A B (Sections III and IV).  A and B must have been loaded with the
+ * same tree (leaf_off, perm) and block partition; C shares them (the
+ * product keeps A's partition).  eps >= 0; eps == 0 selects EXACT.
+ * Errors: H2_ERR_STRUCTURE, H2_ERR_ARG (eps < 0, bad mode/precision),
+ * H2_ERR_UNSUPPORTED (a cluster whose Gram dimension exceeds the on-chip
+ * eigensolver limit, reported in the message), H2_ERR_OOM, H2_ERR_NUMERIC. */
+h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int precision,
+                 h2_mat* C_out);
+
+/* y = M x for nrhs right-hand sides, x and y n x nrhs column-major in the
+ * original point order, host memory (x_on_device = 0) or device memory
+ * (x_on_device = 1, both pointers device).  Exact H^2 mat-vec: forward
+ * transform up the column tree, couplings, backward transform down the row
+ * tree, dense near field (the reference solution of equation `error`). */
+h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nrhs,
+                    int x_on_device);
+
+/* Dense M (original order) into host memory `out` (column-major, ld >= n).
+ * Only for n <= 16384 (H2_ERR_UNSUPPORTED above). */
+h2_status h2_to_dense(h2_ctx ctx, h2_mat M, double* out, int64_t ld);
+
+/* Sizes of M in the flat layout, for h2_export. */
+typedef struct {
+  int64_t n, L, nnodes;
+  int64_t len_V, len_W, len_Er, len_Ec, len_S, len_F;
+} h2_export_sizes;
+h2_status h2_export_size(h2_mat M, h2_export_sizes* sz);
+
+/* Copy M to host in the flat layout (ranks stripped of padding).  Every
+ * pointer must hold the number of elements h2_export_size reports:
+ * leaf_off[2^L+1], perm[n], node_off[L+2], node_row/col/type[nnodes],
+ * krow/kcol[2^(L+1)-1], V_off/W_off[2^L+1], Er_off/Ec_off[2^(L+1)],
+ * S_off/F_off[nnodes+1], V[len_V] ... F[len_F]. */
+typedef struct {
+  int64_t *leaf_off, *perm, *node_off;
+  int32_t *node_row, *node_col, *node_type;
+  int64_t *krow, *kcol;
+  double *V, *W, *Er, *Ec, *S, *F;
+  int64_t *V_off, *W_off, *Er_off, *Ec_off, *S_off, *F_off;
+} h2_export_buffers;
+h2_status h2_export(h2_mat M, const h2_export_buffers* out);
+
+/* Statistics of the last h2_mmp that produced M (zeros for loaded
+ * matrices).  rank_max/rank_mean per level for the row (r) and column (c)
+ * bases; canonical flops (2 r1 r2 r3 per block product, Grams, 9 d^3 per
+ * eigen-decomposition); device time of the numeric phase in ms; the
+ * triple-contraction kernels' summed device time and launch count. */
+#define H2_MAX_LEVELS 40
+typedef struct {
+  int64_t L, lmin;
+  int64_t rank_max_r[H2_MAX_LEVELS], rank_max_c[H2_MAX_LEVELS];
+  double rank_mean_r[H2_MAX_LEVELS], rank_mean_c[H2_MAX_LEVELS];
+  double flops;
+  double mmp_ms;
+  double symbolic_ms;
+  int64_t n_triples;
+  int64_t sparsity_constant;
+  double contraction_ms;
+  int64_t contraction_launches;
+  double contraction_flops;
+  double eig_ms;
+  int64_t bytes_device;
+} h2_stats_t;
+h2_status h2_stats(h2_mat M, h2_stats_t* out);
+
+/* Symbolic phase of C = A A' for the structure in m (block tree only; no
+ * device work, callable without a GPU).  Fills per level l (0..L): the
+ * number of evaluated block products ("triples": an A node (I,J) and a B node
+ * (J,K) of level l, not both non-leaf; Sections III-IV), of temporary
+ * couplings of targets that lie inside an upper-level admissible block
+ * ("blue" blocks of Fig. 3(c)) and of merged targets (equation nonleafA).
+ * Arrays have max_levels entries; *lmin receives the lowest level with an
+ * admissible block.  Errors: H2_ERR_ARG (invalid structure, max_levels <= L). */
+h2_status h2_plan_info(const h2_host_matrix* m, int64_t max_levels, int64_t* triples,
+                       int64_t* blue, int64_t* merged, int64_t* lmin);
+
+/* Enable (1) or disable (0) per-kernel event timing inside h2_mmp. */
+h2_status h2_set_profiling(h2_ctx ctx, int on);
+
+void h2_free(h2_mat M);
+const char* h2_last_error(void);
+int h2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2MMP_H */

@@ -1,0 +1,272 @@
+"""ctypes binding of libh2mmp.so (include/h2mmp.h).  Argument marshalling
+only: every step of the product runs in the library's HIP kernels.  The
+library must be built (paper_1908_05218_amd/build.py); a missing library is
+an error, there is no fallback."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libh2mmp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "h2mmp.h")
+
+H2_OK = 0
+STATUS_NAMES = {0: "H2_OK", 1: "H2_ERR_ARG", 2: "H2_ERR_DEVICE", 3: "H2_ERR_OOM",
+                4: "H2_ERR_STRUCTURE", 5: "H2_ERR_NUMERIC", 6: "H2_ERR_UNSUPPORTED",
+                7: "H2_ERR_INTERNAL"}
+TRUNC = {"accuracy": 0, "paper": 1, "exact": 2}
+PREC = {"fp64": 0, "fp32_bulk": 1}
+MAX_LEVELS = 40
+
+
+class H2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _HostMatrix(C.Structure):
+    _fields_ = [("n", C.c_int64), ("L", C.c_int64), ("is_complex", C.c_int64)] + \
+        [(k, C.c_void_p) for k in ("leaf_off", "perm", "node_off", "node_row", "node_col",
+                                   "node_type", "krow", "kcol", "V", "W", "Er", "Ec", "S", "F",
+                                   "V_off", "W_off", "Er_off", "Ec_off", "S_off", "F_off")]
+
+
+class _ExportSizes(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("n", "L", "nnodes", "len_V", "len_W", "len_Er",
+                                          "len_Ec", "len_S", "len_F")]
+
+
+class _ExportBuffers(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("leaf_off", "perm", "node_off", "node_row", "node_col",
+                                          "node_type", "krow", "kcol", "V", "W", "Er", "Ec", "S",
+                                          "F", "V_off", "W_off", "Er_off", "Ec_off", "S_off",
+                                          "F_off")]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("L", C.c_int64), ("lmin", C.c_int64),
+                ("rank_max_r", C.c_int64 * MAX_LEVELS), ("rank_max_c", C.c_int64 * MAX_LEVELS),
+                ("rank_mean_r", C.c_double * MAX_LEVELS), ("rank_mean_c", C.c_double * MAX_LEVELS),
+                ("flops", C.c_double), ("mmp_ms", C.c_double), ("symbolic_ms", C.c_double),
+                ("n_triples", C.c_int64), ("sparsity_constant", C.c_int64),
+                ("contraction_ms", C.c_double), ("contraction_launches", C.c_int64),
+                ("contraction_flops", C.c_double), ("eig_ms", C.c_double),
+                ("bytes_device", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1908_05218_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.h2_ctx_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(vp)]
+        L.h2_ctx_destroy.argtypes = [vp]
+        L.h2_load.argtypes = [vp, C.POINTER(_HostMatrix), C.POINTER(vp)]
+        L.h2_mmp.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.c_int, C.POINTER(vp)]
+        L.h2_matvec.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int]
+        L.h2_to_dense.argtypes = [vp, vp, vp, C.c_int64]
+        L.h2_export_size.argtypes = [vp, C.POINTER(_ExportSizes)]
+        L.h2_export.argtypes = [vp, C.POINTER(_ExportBuffers)]
+        L.h2_stats.argtypes = [vp, C.POINTER(_Stats)]
+        L.h2_set_profiling.argtypes = [vp, C.c_int]
+        L.h2_free.argtypes = [vp]
+        L.h2_plan_info.argtypes = [C.POINTER(_HostMatrix), C.c_int64, vp, vp, vp, vp]
+        L.h2_last_error.restype = C.c_char_p
+        L.h2_version.restype = C.c_int
+        for f in ("h2_ctx_create", "h2_load", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
+                  "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def declared_functions():
+    """Function names declared in include/h2mmp.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(h2_[a-z_]+)\s*\(", text)))
+
+
+def _check(code):
+    if code != H2_OK:
+        raise H2Error(code, lib().h2_last_error().decode())
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+class Context:
+    def __init__(self, device=0, hbm_budget=0):
+        h = C.c_void_p()
+        _check(lib().h2_ctx_create(device, hbm_budget, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().h2_ctx_destroy(self.h)
+            self.h = None
+
+    def set_profiling(self, on):
+        _check(lib().h2_set_profiling(self.h, 1 if on else 0))
+
+
+class Matrix:
+    def __init__(self, ctx, h):
+        self.ctx = ctx
+        self.h = h
+
+    def free(self):
+        if self.h:
+            lib().h2_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+_I64 = ("leaf_off", "perm", "node_off", "krow", "kcol", "V_off", "W_off", "Er_off", "Ec_off",
+        "S_off", "F_off")
+_I32 = ("node_row", "node_col", "node_type")
+_F64 = ("V", "W", "Er", "Ec", "S", "F")
+
+
+def _host_matrix(flat, keep):
+    hm = _HostMatrix()
+    hm.n = int(flat["n"])
+    hm.L = int(flat["L"])
+    hm.is_complex = int(flat.get("is_complex", 0))
+    for k in _I64:
+        keep[k] = np.ascontiguousarray(flat[k], dtype=np.int64)
+        setattr(hm, k, keep[k].ctypes.data)
+    for k in _I32:
+        keep[k] = np.ascontiguousarray(flat[k], dtype=np.int32)
+        setattr(hm, k, keep[k].ctypes.data)
+    for k in _F64:
+        keep[k] = np.ascontiguousarray(flat[k], dtype=np.float64)
+        setattr(hm, k, keep[k].ctypes.data if keep[k].size else None)
+    return hm
+
+
+def plan_info(flat):
+    """Symbolic-phase counts per level (host only)."""
+    keep = {}
+    hm = _host_matrix(flat, keep)
+    n = MAX_LEVELS
+    t, b, m = (np.zeros(n, np.int64) for _ in range(3))
+    lmin = C.c_int64()
+    _check(lib().h2_plan_info(C.byref(hm), n, _ptr(t), _ptr(b), _ptr(m), C.byref(lmin)))
+    L = int(flat["L"])
+    return dict(triples=t[:L + 1].tolist(), blue=b[:L + 1].tolist(), merged=m[:L + 1].tolist(),
+                lmin=lmin.value)
+
+
+def load(ctx, flat):
+    """Upload an H^2 matrix given in the flat interchange layout (a dict of
+    arrays as described in include/h2mmp.h)."""
+    keep = {}
+    hm = _HostMatrix()
+    hm.n = int(flat["n"])
+    hm.L = int(flat["L"])
+    hm.is_complex = int(flat.get("is_complex", 0))
+    for k in _I64:
+        keep[k] = np.ascontiguousarray(flat[k], dtype=np.int64)
+        setattr(hm, k, keep[k].ctypes.data)
+    for k in _I32:
+        keep[k] = np.ascontiguousarray(flat[k], dtype=np.int32)
+        setattr(hm, k, keep[k].ctypes.data)
+    for k in _F64:
+        keep[k] = np.ascontiguousarray(flat[k], dtype=np.float64)
+        setattr(hm, k, keep[k].ctypes.data if keep[k].size else None)
+    h = C.c_void_p()
+    _check(lib().h2_load(ctx.h, C.byref(hm), C.byref(h)))
+    return Matrix(ctx, h)
+
+
+def mmp(ctx, A, B, eps, mode="accuracy", precision="fp64"):
+    h = C.c_void_p()
+    _check(lib().h2_mmp(ctx.h, A.h, B.h, float(eps), TRUNC[mode], PREC[precision], C.byref(h)))
+    return Matrix(ctx, h)
+
+
+def matvec(ctx, M, x):
+    """y = M x.  x: numpy array (host) or a torch tensor on the GPU
+    (float64, n or n x nrhs, column-major for nrhs > 1 means x.T contiguous)."""
+    try:
+        import torch
+        is_t = isinstance(x, torch.Tensor)
+    except ImportError:
+        is_t = False
+    if is_t:
+        vec = x.dim() == 1
+        xx = x.reshape(x.shape[0], -1)
+        nrhs = xx.shape[1]
+        xc = xx.t().contiguous()  # column-major
+        yc = torch.empty_like(xc)
+        _check(lib().h2_matvec(ctx.h, M.h, C.c_void_p(xc.data_ptr()), C.c_void_p(yc.data_ptr()),
+                               nrhs, 1))
+        y = yc.t()
+        return y[:, 0] if vec else y
+    x = np.asarray(x, dtype=np.float64)
+    vec = x.ndim == 1
+    X = np.asfortranarray(x.reshape(x.shape[0], -1))
+    Y = np.empty_like(X, order="F")
+    _check(lib().h2_matvec(ctx.h, M.h, X.ctypes.data_as(C.c_void_p), Y.ctypes.data_as(C.c_void_p),
+                           X.shape[1], 0))
+    return Y[:, 0] if vec else Y
+
+
+def to_dense(ctx, M, n):
+    out = np.empty((n, n), dtype=np.float64, order="F")
+    _check(lib().h2_to_dense(ctx.h, M.h, out.ctypes.data_as(C.c_void_p), n))
+    return out
+
+
+def export(M):
+    """Copy M to host in the flat interchange layout."""
+    sz = _ExportSizes()
+    _check(lib().h2_export_size(M.h, C.byref(sz)))
+    nleaf = 1 << sz.L
+    ncl = (2 << sz.L) - 1
+    out = dict(
+        leaf_off=np.zeros(nleaf + 1, np.int64), perm=np.zeros(sz.n, np.int64),
+        node_off=np.zeros(sz.L + 2, np.int64), node_row=np.zeros(sz.nnodes, np.int32),
+        node_col=np.zeros(sz.nnodes, np.int32), node_type=np.zeros(sz.nnodes, np.int32),
+        krow=np.zeros(ncl, np.int64), kcol=np.zeros(ncl, np.int64),
+        V=np.zeros(sz.len_V), W=np.zeros(sz.len_W), Er=np.zeros(sz.len_Er),
+        Ec=np.zeros(sz.len_Ec), S=np.zeros(sz.len_S), F=np.zeros(sz.len_F),
+        V_off=np.zeros(nleaf + 1, np.int64), W_off=np.zeros(nleaf + 1, np.int64),
+        Er_off=np.zeros(ncl + 1, np.int64), Ec_off=np.zeros(ncl + 1, np.int64),
+        S_off=np.zeros(sz.nnodes + 1, np.int64), F_off=np.zeros(sz.nnodes + 1, np.int64))
+    eb = _ExportBuffers()
+    for k, v in out.items():
+        setattr(eb, k, v.ctypes.data if v.size else None)
+    _check(lib().h2_export(M.h, C.byref(eb)))
+    out["n"] = np.int64(sz.n)
+    out["L"] = np.int64(sz.L)
+    out["is_complex"] = np.int64(0)
+    return out
+
+
+def stats(M):
+    s = _Stats()
+    _check(lib().h2_stats(M.h, C.byref(s)))
+    L = s.L
+    return dict(L=L, lmin=s.lmin,
+                rank_max_r=list(s.rank_max_r[:L + 1]), rank_max_c=list(s.rank_max_c[:L + 1]),
+                rank_mean_r=list(s.rank_mean_r[:L + 1]), rank_mean_c=list(s.rank_mean_c[:L + 1]),
+                flops=s.flops, mmp_ms=s.mmp_ms, symbolic_ms=s.symbolic_ms,
+                n_triples=s.n_triples, sparsity_constant=s.sparsity_constant,
+                contraction_ms=s.contraction_ms, contraction_launches=s.contraction_launches,
+                contraction_flops=s.contraction_flops, eig_ms=s.eig_ms,
+                bytes_device=s.bytes_device)

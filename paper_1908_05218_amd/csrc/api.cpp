@@ -1,0 +1,804 @@
+// C-ABI of the h2mmp library: contexts, device memory pool, loading and
+// exporting H^2 matrices, the exact H^2 mat-vec and dense expansion.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "internal.h"
+
+namespace h2 {
+
+static thread_local std::string g_last_error;
+
+h2_status set_error(h2_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+void Profiler::begin(int kind, double flops, hipEvent_t* out_a) {
+  (void)kind;
+  (void)flops;
+  if (!on) return;
+  hipEventCreate(out_a);
+  hipEventRecord(*out_a, stream);
+}
+
+void Profiler::end(hipEvent_t a, int kind, double flops) {
+  if (!on) return;
+  hipEvent_t b;
+  hipEventCreate(&b);
+  hipEventRecord(b, stream);
+  recs.push_back({a, b, kind, flops});
+}
+
+void Profiler::collect(double* ms, long long* launches, double* flops) {
+  for (int k = 0; k < kKindCount; ++k) {
+    ms[k] = 0;
+    launches[k] = 0;
+    flops[k] = 0;
+  }
+  for (auto& r : recs) {
+    float t = 0;
+    hipEventElapsedTime(&t, r.a, r.b);
+    ms[r.kind] += t;
+    launches[r.kind] += 1;
+    flops[r.kind] += r.flops;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  recs.clear();
+}
+
+thread_local h2_ctx g_active_ctx = nullptr;
+
+void scan_limits(const TaskList& t, DevList& d) {
+  for (int v : t.a) d.max_a[(v >> 2) & 1] = std::max(d.max_a[(v >> 2) & 1], v >> 3);
+  for (int v : t.b) d.max_b[(v >> 2) & 1] = std::max(d.max_b[(v >> 2) & 1], v >> 3);
+  for (int v : t.out) d.max_out = std::max(d.max_out, v >> 3);
+}
+
+// Every block a launch can touch must lie inside the allocation its base
+// pointer starts: checked on the host before the launch.
+static void check_extent(const void* base, long long stride, int maxtile, long long sub_r,
+                         long long sub_c, long long rows, long long cols, long long ld, size_t elt,
+                         const char* what) {
+  if (maxtile < 0) return;
+  if (!base) throw Error(H2_ERR_INTERNAL, std::string(what) + ": null operand");
+  if (ld < rows) throw Error(H2_ERR_INTERNAL, std::string(what) + ": leading dimension too small");
+  if (!g_active_ctx) return;
+  auto it = g_active_ctx->live.find(const_cast<void*>(base));
+  if (it == g_active_ctx->live.end())
+    throw Error(H2_ERR_INTERNAL, std::string(what) + ": operand is not a live allocation");
+  const long long need = (long long)maxtile * stride + sub_r + sub_c + (rows - 1) + (cols - 1) * ld + 1;
+  if ((size_t)need * elt > it->second)
+    throw Error(H2_ERR_INTERNAL, std::string(what) + ": block extent beyond its allocation (" +
+                                     std::to_string(need * elt) + " > " +
+                                     std::to_string(it->second) + " bytes)");
+}
+
+static h2k::Opnd to_opnd(const Op& o) {
+  h2k::Opnd r;
+  r.base[0] = o.base0;
+  r.base[1] = o.base1 ? o.base1 : o.base0;
+  r.stride[0] = o.stride0;
+  r.stride[1] = o.base1 ? o.stride1 : o.stride0;
+  r.ld = o.ld;
+  r.sub_r = o.sub_r;
+  r.sub_c = o.sub_c;
+  return r;
+}
+
+void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int n, int k,
+          const Op& A, bool tA, const Op& B, bool tB, double* C, long long cstride, int ldc,
+          long long csub_r, long long csub_c, double alpha, double beta) {
+  if (tl.nout == 0) return;
+  if (k % 16 != 0 || m <= 0 || n <= 0) throw Error(H2_ERR_INTERNAL, "gemm shape");
+  {
+    const long long ar = tA ? k : m, ac = tA ? m : k, br = tB ? n : k, bc = tB ? k : n;
+    check_extent(A.base0, A.stride0, tl.max_a[0], A.sub_r, A.sub_c, ar, ac, A.ld, 8, "gemm A");
+    check_extent(A.base1 ? A.base1 : A.base0, A.base1 ? A.stride1 : A.stride0, tl.max_a[1], A.sub_r,
+                 A.sub_c, ar, ac, A.ld, 8, "gemm A(sel)");
+    check_extent(B.base0, B.stride0, tl.max_b[0], B.sub_r, B.sub_c, br, bc, B.ld, 8, "gemm B");
+    check_extent(B.base1 ? B.base1 : B.base0, B.base1 ? B.stride1 : B.stride0, tl.max_b[1], B.sub_r,
+                 B.sub_c, br, bc, B.ld, 8, "gemm B(sel)");
+    check_extent(C, cstride, tl.max_out, csub_r, csub_c, m, n, ldc, 8, "gemm C");
+  }
+  h2k::BgemmArgs<double> a{};
+  a.m = m;
+  a.n = n;
+  a.k = k;
+  a.nout = tl.nout;
+  a.transA = tA;
+  a.transB = tB;
+  a.A = to_opnd(A);
+  a.B = to_opnd(B);
+  a.C = C;
+  a.cstride = cstride;
+  a.ldc = ldc;
+  a.csub_r = csub_r;
+  a.csub_c = csub_c;
+  a.out_idx = tl.out;
+  a.seg = tl.seg;
+  a.a_idx = tl.a;
+  a.b_idx = tl.b;
+  a.alpha = alpha;
+  a.beta = beta;
+  hipEvent_t ev = nullptr;
+  const double fl = 2.0 * m * n * (double)k * tl.ntask;
+  if (prof) prof->begin(kind, fl, &ev);
+  H2_HIP(h2k::launch_bgemm<double>(a, s));
+  if (prof) prof->end(ev, kind, fl);
+}
+
+void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, double* C,
+            long long cstride, int ldc, long long csub_r, long long csub_c, double beta) {
+  if (tl.nout == 0) return;
+  check_extent(A.base0, A.stride0, tl.max_a[0], A.sub_r, A.sub_c, m, n, A.ld, 8, "segsum A");
+  check_extent(C, cstride, tl.max_out, csub_r, csub_c, m, n, ldc, 8, "segsum C");
+  h2k::SegsumArgs<double> a{};
+  a.m = m;
+  a.n = n;
+  a.nout = tl.nout;
+  a.A = to_opnd(A);
+  a.C = C;
+  a.cstride = cstride;
+  a.ldc = ldc;
+  a.csub_r = csub_r;
+  a.csub_c = csub_c;
+  a.out_idx = tl.out;
+  a.seg = tl.seg;
+  a.a_idx = tl.a;
+  a.beta = beta;
+  H2_HIP(h2k::launch_segsum<double>(a, s));
+}
+
+void zero(hipStream_t s, double* p, long long n) {
+  if (n > 0) H2_HIP(hipMemsetAsync(p, 0, (size_t)n * sizeof(double), s));
+}
+
+std::unique_ptr<DevPlan> upload_plan(h2_ctx ctx, const Plan& p) {
+  std::vector<const TaskList*> all;
+  auto addl = [&](const TaskList& t) { all.push_back(&t); };
+  const LeafPlan& L = p.leaf;
+  for (const TaskList* t :
+       {&L.H, &L.X1, &L.G1, &L.G2, &L.G3, &L.Hc, &L.X1c, &L.G1c, &L.G2c, &L.G3c, &L.Z, &L.Zc,
+        &L.gB, &L.hA, &L.PA, &L.PB, &L.LA_F, &L.PS, &L.LA_R, &L.RB_F, &L.SP, &L.RB_R, &L.Ahat,
+        &L.Bhat, &L.adm_R, &L.adm_B, &L.dense, &L.densA1, &L.densA2, &L.densB1, &L.densB2})
+    addl(*t);
+  for (const LevelPlan& Q : p.lev)
+    for (const TaskList* t :
+         {&Q.G1, &Q.G1c, &Q.Y, &Q.G2, &Q.Yc, &Q.G2c, &Q.D, &Q.G3, &Q.Q, &Q.G3c, &Q.PA, &Q.PB,
+          &Q.AhatNL, &Q.PAS, &Q.AhatR, &Q.BhatNL, &Q.SBP, &Q.BhatR, &Q.c1X, &Q.c1_R, &Q.c1_B,
+          &Q.t_nl_R, &Q.t_nl_B, &Q.t_nl_NL, &Q.t_r_R, &Q.t_r_B, &Q.t_r_NL})
+      addl(*t);
+  for (const SplitPlan& S : p.split)
+    for (const TaskList* t : {&S.X, &S.toR, &S.toNL, &S.toF, &S.F1, &S.F2}) addl(*t);
+  addl(p.pi.leaf);
+  for (const TaskList& t : p.pi.X) addl(t);
+  for (const TaskList& t : p.pi.S) addl(t);
+  size_t total = 0;
+  for (const TaskList* t : all) total += t->out.size() + t->seg.size() + t->a.size() + t->b.size();
+  std::vector<int> host(total + 1);
+  auto dp = std::make_unique<DevPlan>();
+  dp->mem = Buf(ctx, (total + 1) * sizeof(int));
+  int* base = dp->mem.as<int>();
+  size_t off = 0;
+  for (const TaskList* t : all) {
+    DevList d;
+    d.nout = t->nout();
+    d.ntask = t->ntask();
+    auto put = [&](const std::vector<int>& v) -> const int* {
+      std::copy(v.begin(), v.end(), host.begin() + off);
+      const int* r = base + off;
+      off += v.size();
+      return r;
+    };
+    d.out = put(t->out);
+    d.seg = put(t->seg);
+    d.a = put(t->a);
+    d.b = put(t->b);
+    scan_limits(*t, d);
+    dp->lists[t] = d;
+  }
+  H2_HIP(hipMemcpy(base, host.data(), total * sizeof(int), hipMemcpyHostToDevice));
+  return dp;
+}
+
+static inline long long cidx(int l, int c) { return (1LL << l) - 1 + c; }
+
+// ------------------------------------------------------------------ mat-vec
+// Exact H^2 mat-vec (the reference solution of equation `error`): forward
+// transform up the column tree, couplings, backward transform down the row
+// tree, dense near field.
+void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64_t nrhs) {
+  g_active_ctx = ctx;
+  const Structure& s = M->st();
+  Shape& sh = *M->shape;
+  hipStream_t st = ctx->stream;
+  const int L = s.L, np = s.npad, nleaf = 1 << L;
+  const int lo = M->product ? s.lmin : s.lmin;  // no admissible block above lmin
+  const long long nt = (long long)nleaf * np;
+  const int R = (int)nrhs;
+  Buf xt(ctx, nt * R * sizeof(double)), yt(ctx, nt * R * sizeof(double));
+  H2_HIP(h2k::launch_gather_rows(x_dev, xt.d(), sh.d_perm.as<long long>(),
+                                 sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R, st));
+  // identity task lists built on the fly (small)
+  std::vector<Buf> xh(L + 1), yh(L + 1);
+  for (int l = lo; l <= L; ++l) {
+    xh[l] = Buf(ctx, (size_t)(1 << l) * M->rc[l] * R * sizeof(double));
+    yh[l] = Buf(ctx, (size_t)(1 << l) * M->rr[l] * R * sizeof(double));
+    zero(st, yh[l].d(), (long long)(1 << l) * M->rr[l] * R);
+  }
+  // temporary device task lists
+  struct TmpList {
+    Buf mem;
+    DevList d;
+  };
+  auto mk = [&](const TaskList& t) {
+    TmpList r;
+    std::vector<int> h;
+    h.insert(h.end(), t.out.begin(), t.out.end());
+    h.insert(h.end(), t.seg.begin(), t.seg.end());
+    h.insert(h.end(), t.a.begin(), t.a.end());
+    h.insert(h.end(), t.b.begin(), t.b.end());
+    r.mem = Buf(ctx, (h.size() + 1) * sizeof(int));
+    H2_HIP(hipMemcpyAsync(r.mem.as<int>(), h.data(), h.size() * sizeof(int),
+                          hipMemcpyHostToDevice, st));
+    int* b = r.mem.as<int>();
+    r.d.nout = t.nout();
+    r.d.ntask = t.ntask();
+    r.d.out = b;
+    r.d.seg = b + t.out.size();
+    r.d.a = r.d.seg + t.seg.size();
+    r.d.b = r.d.a + t.a.size();
+    scan_limits(t, r.d);
+    H2_HIP(hipStreamSynchronize(st));
+    return r;
+  };
+  const LevelNodes& lf = s.lev[L];
+  const long long ldx = nt;
+  // forward
+  {
+    TaskList t;
+    for (int c = 0; c < nleaf; ++c) {
+      t.add_task(enc(c), enc(c));
+      t.close(enc(c));
+    }
+    TmpList d = mk(t);
+    Op A{M->W.d(), nullptr, M->W_stride, 0, np, 0, 0};
+    Op B{xt.d(), nullptr, np, 0, (int)ldx, 0, 0};
+    gemm(st, nullptr, 0, d.d, M->rc[L], R, np, A, true, B, false, xh[L].d(),
+         (long long)M->rc[L] * R, M->rc[L], 0, 0, 1.0, 0.0);
+  }
+  for (int l = L - 1; l >= lo; --l) {
+    TaskList t;
+    for (int J = 0; J < (1 << l); ++J) {
+      for (int a = 0; a < 2; ++a) t.add_task(enc(J, a), enc(2 * J + a));
+      t.close(enc(J));
+    }
+    TmpList d = mk(t);
+    Op A{M->Tc[l].d(), nullptr, M->Tc_stride[l], 0, 2 * M->rc[l + 1], M->rc[l + 1], 0};
+    Op B{xh[l + 1].d(), nullptr, (long long)M->rc[l + 1] * R, 0, M->rc[l + 1], 0, 0};
+    gemm(st, nullptr, 0, d.d, M->rc[l], R, M->rc[l + 1], A, true, B, false, xh[l].d(),
+         (long long)M->rc[l] * R, M->rc[l], 0, 0, 1.0, 0.0);
+  }
+  // couplings
+  for (int l = lo; l <= L; ++l) {
+    const LevelNodes& ln = s.lev[l];
+    TaskList t;
+    std::vector<std::vector<int>> byrow(1 << l);
+    for (int q = 0; q < ln.size(); ++q)
+      if (ln.type[q] == kR) byrow[ln.row[q]].push_back(q);
+    for (int I = 0; I < (1 << l); ++I) {
+      if (byrow[I].empty()) continue;
+      for (int q : byrow[I]) t.add_task(enc(q), enc(ln.col[q]));
+      t.close(enc(I));
+    }
+    if (t.nout() == 0) continue;
+    TmpList d = mk(t);
+    Op A{M->S[l].d(), nullptr, (long long)M->rr[l] * M->rc[l], 0, M->rr[l], 0, 0};
+    Op B{xh[l].d(), nullptr, (long long)M->rc[l] * R, 0, M->rc[l], 0, 0};
+    gemm(st, nullptr, 0, d.d, M->rr[l], R, M->rc[l], A, false, B, false, yh[l].d(),
+         (long long)M->rr[l] * R, M->rr[l], 0, 0, 1.0, 1.0);
+  }
+  // backward
+  for (int l = lo; l < L; ++l) {
+    TaskList t;
+    for (int c = 0; c < (2 << l); ++c) {
+      t.add_task(enc(c >> 1, c & 1), enc(c >> 1));
+      t.close(enc(c));
+    }
+    TmpList d = mk(t);
+    Op A{M->Tr[l].d(), nullptr, M->Tr_stride[l], 0, 2 * M->rr[l + 1], M->rr[l + 1], 0};
+    Op B{yh[l].d(), nullptr, (long long)M->rr[l] * R, 0, M->rr[l], 0, 0};
+    gemm(st, nullptr, 0, d.d, M->rr[l + 1], R, M->rr[l], A, false, B, false, yh[l + 1].d(),
+         (long long)M->rr[l + 1] * R, M->rr[l + 1], 0, 0, 1.0, 1.0);
+  }
+  {
+    TaskList t;
+    for (int c = 0; c < nleaf; ++c) {
+      t.add_task(enc(c), enc(c));
+      t.close(enc(c));
+    }
+    TmpList d = mk(t);
+    Op A{M->V.d(), nullptr, M->V_stride, 0, np, 0, 0};
+    Op B{yh[L].d(), nullptr, (long long)M->rr[L] * R, 0, M->rr[L], 0, 0};
+    gemm(st, nullptr, 0, d.d, np, R, M->rr[L], A, false, B, false, yt.d(), np, (int)ldx, 0, 0,
+         1.0, 0.0);
+  }
+  {
+    TaskList t;
+    std::vector<std::vector<int>> byrow(nleaf);
+    for (int q = 0; q < lf.size(); ++q)
+      if (lf.type[q] == kF) byrow[lf.row[q]].push_back(q);
+    for (int I = 0; I < nleaf; ++I) {
+      if (byrow[I].empty()) continue;
+      for (int q : byrow[I]) t.add_task(enc(q), enc(lf.col[q]));
+      t.close(enc(I));
+    }
+    TmpList d = mk(t);
+    Op A{M->F.d(), nullptr, (long long)np * np, 0, np, 0, 0};
+    Op B{xt.d(), nullptr, np, 0, (int)ldx, 0, 0};
+    gemm(st, nullptr, 0, d.d, np, R, np, A, false, B, false, yt.d(), np, (int)ldx, 0, 0, 1.0,
+         1.0);
+  }
+  H2_HIP(h2k::launch_scatter_rows(yt.d(), y_dev, sh.d_perm.as<long long>(),
+                                  sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R, st));
+  H2_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace h2
+
+// ------------------------------------------------------------------ context
+void* h2_ctx_s::alloc(size_t bytes) {
+  bytes = (bytes + 4095) & ~(size_t)4095;
+  auto it = pool.find(bytes);
+  if (it != pool.end()) {
+    void* p = it->second;
+    pool.erase(it);
+    live[p] = bytes;
+    return p;
+  }
+  if (budget && used + bytes > budget) {
+    // release cached blocks first
+    for (auto& kv : pool) {
+      hipFree(kv.second);
+      used -= kv.first;
+    }
+    pool.clear();
+    if (used + bytes > budget)
+      throw h2::Error(H2_ERR_OOM, "device memory budget exceeded (" + std::to_string(used + bytes) +
+                                      " > " + std::to_string(budget) + " bytes)");
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    for (auto& kv : pool) {
+      hipFree(kv.second);
+      used -= kv.first;
+    }
+    pool.clear();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw h2::Error(H2_ERR_OOM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+    }
+  }
+  used += bytes;
+  live[p] = bytes;
+  return p;
+}
+
+void h2_ctx_s::release(void* p) {
+  auto it = live.find(p);
+  if (it == live.end()) return;
+  pool.emplace(it->second, p);
+  live.erase(it);
+}
+
+h2_ctx_s::~h2_ctx_s() {
+  if (stream) hipStreamSynchronize(stream);
+  for (auto& kv : pool) hipFree(kv.second);
+  for (auto& kv : live) hipFree(kv.first);
+  if (stream) hipStreamDestroy(stream);
+}
+
+extern "C" {
+
+const char* h2_last_error(void) { return h2::g_last_error.c_str(); }
+int h2_version(void) { return 1; }
+
+h2_status h2_ctx_create(int device, size_t hbm_budget, h2_ctx* out) {
+  if (!out) return h2::set_error(H2_ERR_ARG, "out is null");
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return h2::set_error(H2_ERR_DEVICE, "no HIP device " + std::to_string(device));
+  }
+  if (hipSetDevice(device) != hipSuccess) return h2::set_error(H2_ERR_DEVICE, "hipSetDevice failed");
+  auto* c = new h2_ctx_s();
+  c->device = device;
+  c->budget = hbm_budget;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return h2::set_error(H2_ERR_DEVICE, "hipStreamCreate failed");
+  }
+  *out = c;
+  return H2_OK;
+}
+
+void h2_ctx_destroy(h2_ctx ctx) { delete ctx; }
+
+h2_status h2_set_profiling(h2_ctx ctx, int on) {
+  if (!ctx) return h2::set_error(H2_ERR_ARG, "null context");
+  ctx->profiling = on != 0;
+  return H2_OK;
+}
+
+h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out) {
+  using namespace h2;
+  if (!ctx || !m || !out) return set_error(H2_ERR_ARG, "null argument");
+  if (m->is_complex) return set_error(H2_ERR_UNSUPPORTED, "complex matrices are not supported");
+  try {
+    hipSetDevice(ctx->device);
+    auto shape = std::make_shared<Shape>();
+    std::string err = build_structure(shape->s, m->n, m->L, m->leaf_off, m->perm, m->node_off,
+                                      m->node_row, m->node_col, m->node_type);
+    if (!err.empty()) return set_error(H2_ERR_ARG, err);
+    const Structure& s = shape->s;
+    const int L = s.L, np = s.npad, nleaf = 1 << L;
+    if (!m->krow || !m->kcol || !m->V || !m->W || !m->V_off || !m->W_off || !m->Er_off ||
+        !m->Ec_off || !m->S_off || !m->F_off)
+      return set_error(H2_ERR_ARG, "null matrix array");
+    const long long ncl = (2LL << L) - 1;
+    auto M = std::make_unique<h2_mat_s>();
+    M->ctx = ctx;
+    M->shape = shape;
+    M->krow.assign(m->krow, m->krow + ncl);
+    M->kcol.assign(m->kcol, m->kcol + ncl);
+    M->rr.assign(L + 1, 16);
+    M->rc.assign(L + 1, 16);
+    for (int l = 0; l <= L; ++l)
+      for (int c = 0; c < (1 << l); ++c) {
+        const int64_t kr = M->krow[cidx(l, c)], kc = M->kcol[cidx(l, c)];
+        if (kr < 0 || kc < 0 || kr > 4096 || kc > 4096) return set_error(H2_ERR_ARG, "bad rank");
+        M->rr[l] = std::max(M->rr[l], pad16(kr));
+        M->rc[l] = std::max(M->rc[l], pad16(kc));
+      }
+    // element count checks
+    auto need = [&](const int64_t* off, long long i, long long len, const char* what) {
+      if (off[i + 1] - off[i] != len)
+        throw Error(H2_ERR_ARG, std::string("size mismatch in ") + what + " entry " + std::to_string(i));
+    };
+    // leaf bases
+    auto upload_leaf = [&](const double* src, const int64_t* off, const std::vector<int64_t>& kk,
+                           int rpad, Buf& dst, long long& stride, const char* what) {
+      stride = (long long)np * rpad;
+      std::vector<double> h((size_t)stride * nleaf, 0.0);
+      for (int c = 0; c < nleaf; ++c) {
+        const int nc = s.leaf_size[c];
+        const int k = (int)kk[cidx(L, c)];
+        need(off, c, (long long)nc * k, what);
+        for (int j = 0; j < k; ++j)
+          for (int i = 0; i < nc; ++i) h[(size_t)c * stride + i + (size_t)j * np] = src[off[c] + i + (size_t)j * nc];
+      }
+      dst = Buf(ctx, h.size() * sizeof(double));
+      H2_HIP(hipMemcpy(dst.d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    };
+    upload_leaf(m->V, m->V_off, M->krow, M->rr[L], M->V, M->V_stride, "V");
+    upload_leaf(m->W, m->W_off, M->kcol, M->rc[L], M->W, M->W_stride, "W");
+    auto upload_tr = [&](const double* src, const int64_t* off, const std::vector<int64_t>& kk,
+                         const std::vector<int>& rp, std::vector<Buf>& dst,
+                         std::vector<long long>& stride, const char* what) {
+      dst.clear();
+      dst.resize(L);
+      stride.assign(L, 0);
+      for (int l = 0; l < L; ++l) {
+        const int ld = 2 * rp[l + 1];
+        stride[l] = (long long)ld * rp[l];
+        std::vector<double> h((size_t)stride[l] * (1 << l), 0.0);
+        for (int I = 0; I < (1 << l); ++I)
+          for (int a = 0; a < 2; ++a) {
+            const int c = 2 * I + a;
+            const long long fi = cidx(l + 1, c);
+            const int kc_ = (int)kk[fi], kp = (int)kk[cidx(l, I)];
+            need(off, fi, (long long)kc_ * kp, what);
+            if (kc_ * kp && !src) throw Error(H2_ERR_ARG, "null transfer array");
+            for (int j = 0; j < kp; ++j)
+              for (int i = 0; i < kc_; ++i)
+                h[(size_t)I * stride[l] + a * rp[l + 1] + i + (size_t)j * ld] =
+                    src[off[fi] + i + (size_t)j * kc_];
+          }
+        dst[l] = Buf(ctx, h.size() * sizeof(double));
+        H2_HIP(hipMemcpy(dst[l].d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+      }
+    };
+    upload_tr(m->Er, m->Er_off, M->krow, M->rr, M->Tr, M->Tr_stride, "Er");
+    upload_tr(m->Ec, m->Ec_off, M->kcol, M->rc, M->Tc, M->Tc_stride, "Ec");
+    M->S.resize(L + 1);
+    for (int l = 0; l <= L; ++l) {
+      const LevelNodes& ln = s.lev[l];
+      const long long bs = (long long)M->rr[l] * M->rc[l];
+      std::vector<double> h((size_t)bs * std::max(1, ln.size()), 0.0);
+      for (int q = 0; q < ln.size(); ++q) {
+        const long long g = s.node_base[l] + q;
+        if (ln.type[q] != kR) {
+          need(m->S_off, g, 0, "S");
+          continue;
+        }
+        const int kr = (int)M->krow[cidx(l, ln.row[q])], kc = (int)M->kcol[cidx(l, ln.col[q])];
+        need(m->S_off, g, (long long)kr * kc, "S");
+        for (int j = 0; j < kc; ++j)
+          for (int i = 0; i < kr; ++i)
+            h[(size_t)q * bs + i + (size_t)j * M->rr[l]] = m->S[m->S_off[g] + i + (size_t)j * kr];
+      }
+      M->S[l] = Buf(ctx, h.size() * sizeof(double));
+      H2_HIP(hipMemcpy(M->S[l].d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    {
+      const LevelNodes& ln = s.lev[L];
+      const long long bs = (long long)np * np;
+      std::vector<double> h((size_t)bs * ln.size(), 0.0);
+      for (int q = 0; q < ln.size(); ++q) {
+        const long long g = s.node_base[L] + q;
+        if (ln.type[q] != kF) {
+          need(m->F_off, g, 0, "F");
+          continue;
+        }
+        const int ni = s.leaf_size[ln.row[q]], nj = s.leaf_size[ln.col[q]];
+        need(m->F_off, g, (long long)ni * nj, "F");
+        if (!m->F) throw Error(H2_ERR_ARG, "null F");
+        for (int j = 0; j < nj; ++j)
+          for (int i = 0; i < ni; ++i) {
+            const double v = m->F[m->F_off[g] + i + (size_t)j * ni];
+            if (!std::isfinite(v)) throw Error(H2_ERR_NUMERIC, "non-finite dense entry");
+            h[(size_t)q * bs + i + (size_t)j * np] = v;
+          }
+      }
+      M->F = Buf(ctx, h.size() * sizeof(double));
+      H2_HIP(hipMemcpy(M->F.d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    shape->d_perm = Buf(ctx, s.n * sizeof(long long));
+    shape->d_leaf_off = Buf(ctx, (nleaf + 1) * sizeof(long long));
+    H2_HIP(hipMemcpy(shape->d_perm.as<long long>(), s.perm.data(), s.n * sizeof(long long),
+                     hipMemcpyHostToDevice));
+    H2_HIP(hipMemcpy(shape->d_leaf_off.as<long long>(), s.leaf_off.data(),
+                     (nleaf + 1) * sizeof(long long), hipMemcpyHostToDevice));
+    M->stats.L = L;
+    M->stats.lmin = s.lmin;
+    M->stats.sparsity_constant = s.sparsity_constant();
+    *out = M.release();
+    return H2_OK;
+  } catch (const Error& e) {
+    return set_error(e.code, e.msg);
+  } catch (const std::exception& e) {
+    return set_error(H2_ERR_INTERNAL, e.what());
+  }
+}
+
+h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int precision,
+                 h2_mat* C_out) {
+  using namespace h2;
+  if (!ctx || !A || !B || !C_out) return set_error(H2_ERR_ARG, "null argument");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return set_error(H2_ERR_ARG, "eps must be finite and >= 0");
+  if (trunc_mode < 0 || trunc_mode > 2) return set_error(H2_ERR_ARG, "bad truncation mode");
+  if (precision < 0 || precision > 1) return set_error(H2_ERR_ARG, "bad precision");
+  if (A->shape != B->shape && !A->st().same_as(B->st()))
+    return set_error(H2_ERR_STRUCTURE, "A and B differ in tree or block partition");
+  try {
+    hipSetDevice(ctx->device);
+    return mmp_impl(ctx, A, B, eps, trunc_mode, precision, C_out);
+  } catch (const Error& e) {
+    (void)hipGetLastError();
+    return set_error(e.code, e.msg);
+  } catch (const std::exception& e) {
+    return set_error(H2_ERR_INTERNAL, e.what());
+  }
+}
+
+h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nrhs,
+                    int x_on_device) {
+  using namespace h2;
+  if (!ctx || !M || !x || !y || nrhs < 1) return set_error(H2_ERR_ARG, "bad argument");
+  try {
+    hipSetDevice(ctx->device);
+    const long long n = M->st().n;
+    if (x_on_device) {
+      matvec_impl(ctx, M, x, y, nrhs);
+    } else {
+      Buf xd(ctx, n * nrhs * sizeof(double)), yd(ctx, n * nrhs * sizeof(double));
+      H2_HIP(hipMemcpy(xd.d(), x, n * nrhs * sizeof(double), hipMemcpyHostToDevice));
+      matvec_impl(ctx, M, xd.d(), yd.d(), nrhs);
+      H2_HIP(hipMemcpy(y, yd.d(), n * nrhs * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return H2_OK;
+  } catch (const Error& e) {
+    return set_error(e.code, e.msg);
+  }
+}
+
+h2_status h2_to_dense(h2_ctx ctx, h2_mat M, double* out, int64_t ld) {
+  using namespace h2;
+  if (!ctx || !M || !out) return set_error(H2_ERR_ARG, "null argument");
+  const long long n = M->st().n;
+  if (ld < n) return set_error(H2_ERR_ARG, "ld < n");
+  if (n > 16384) return set_error(H2_ERR_UNSUPPORTED, "to_dense is limited to n <= 16384");
+  try {
+    hipSetDevice(ctx->device);
+    std::vector<double> eye((size_t)n * n, 0.0);
+    for (long long i = 0; i < n; ++i) eye[(size_t)i * n + i] = 1.0;
+    Buf xd(ctx, n * n * sizeof(double)), yd(ctx, n * n * sizeof(double));
+    H2_HIP(hipMemcpy(xd.d(), eye.data(), n * n * sizeof(double), hipMemcpyHostToDevice));
+    matvec_impl(ctx, M, xd.d(), yd.d(), n);
+    H2_HIP(hipMemcpy(eye.data(), yd.d(), n * n * sizeof(double), hipMemcpyDeviceToHost));
+    for (long long j = 0; j < n; ++j) memcpy(out + j * ld, eye.data() + j * n, n * sizeof(double));
+    return H2_OK;
+  } catch (const Error& e) {
+    return set_error(e.code, e.msg);
+  }
+}
+
+h2_status h2_export_size(h2_mat M, h2_export_sizes* sz) {
+  using namespace h2;
+  if (!M || !sz) return set_error(H2_ERR_ARG, "null argument");
+  const Structure& s = M->st();
+  const int L = s.L;
+  memset(sz, 0, sizeof(*sz));
+  sz->n = s.n;
+  sz->L = L;
+  sz->nnodes = s.node_base[L + 1];
+  for (int c = 0; c < (1 << L); ++c) {
+    sz->len_V += (int64_t)s.leaf_size[c] * M->krow[cidx(L, c)];
+    sz->len_W += (int64_t)s.leaf_size[c] * M->kcol[cidx(L, c)];
+  }
+  for (int l = 1; l <= L; ++l)
+    for (int c = 0; c < (1 << l); ++c) {
+      sz->len_Er += M->krow[cidx(l, c)] * M->krow[cidx(l - 1, c >> 1)];
+      sz->len_Ec += M->kcol[cidx(l, c)] * M->kcol[cidx(l - 1, c >> 1)];
+    }
+  for (int l = 0; l <= L; ++l) {
+    const LevelNodes& ln = s.lev[l];
+    for (int q = 0; q < ln.size(); ++q) {
+      if (ln.type[q] == kR) sz->len_S += M->krow[cidx(l, ln.row[q])] * M->kcol[cidx(l, ln.col[q])];
+      if (ln.type[q] == kF) sz->len_F += (int64_t)s.leaf_size[ln.row[q]] * s.leaf_size[ln.col[q]];
+    }
+  }
+  return H2_OK;
+}
+
+h2_status h2_export(h2_mat M, const h2_export_buffers* o) {
+  using namespace h2;
+  if (!M || !o) return set_error(H2_ERR_ARG, "null argument");
+  try {
+    hipSetDevice(M->ctx->device);
+    H2_HIP(hipStreamSynchronize(M->ctx->stream));
+    const Structure& s = M->st();
+    const int L = s.L, np = s.npad, nleaf = 1 << L;
+    const long long ncl = (2LL << L) - 1;
+    memcpy(o->leaf_off, s.leaf_off.data(), (nleaf + 1) * sizeof(int64_t));
+    memcpy(o->perm, s.perm.data(), s.n * sizeof(int64_t));
+    for (int l = 0; l <= L + 1; ++l) o->node_off[l] = s.node_base[l];
+    for (int l = 0; l <= L; ++l)
+      for (int q = 0; q < s.lev[l].size(); ++q) {
+        const long long g = s.node_base[l] + q;
+        o->node_row[g] = s.lev[l].row[q];
+        o->node_col[g] = s.lev[l].col[q];
+        o->node_type[g] = s.lev[l].type[q];
+      }
+    memcpy(o->krow, M->krow.data(), ncl * sizeof(int64_t));
+    memcpy(o->kcol, M->kcol.data(), ncl * sizeof(int64_t));
+    auto fetch = [&](const Buf& b) {
+      std::vector<double> h(b.bytes() / sizeof(double));
+      if (!h.empty())
+        H2_HIP(hipMemcpy(h.data(), b.d(), h.size() * sizeof(double), hipMemcpyDeviceToHost));
+      return h;
+    };
+    auto leaf = [&](const Buf& b, long long stride, const std::vector<int64_t>& kk, double* dst,
+                    int64_t* off) {
+      std::vector<double> h = fetch(b);
+      int64_t p = 0;
+      for (int c = 0; c < nleaf; ++c) {
+        off[c] = p;
+        const int nc = s.leaf_size[c], k = (int)kk[cidx(L, c)];
+        for (int j = 0; j < k; ++j)
+          for (int i = 0; i < nc; ++i) dst[p++] = h[(size_t)c * stride + i + (size_t)j * np];
+      }
+      off[nleaf] = p;
+    };
+    leaf(M->V, M->V_stride, M->krow, o->V, o->V_off);
+    leaf(M->W, M->W_stride, M->kcol, o->W, o->W_off);
+    auto trans = [&](const std::vector<Buf>& T, const std::vector<long long>& stride,
+                     const std::vector<int>& rp, const std::vector<int64_t>& kk, double* dst,
+                     int64_t* off) {
+      int64_t p = 0;
+      off[0] = 0;
+      for (int l = 0; l < L; ++l) {
+        const bool live = T[l].bytes() > 0;
+        std::vector<double> h = live ? fetch(T[l]) : std::vector<double>();
+        const int ld = 2 * rp[l + 1];
+        for (int c = 0; c < (2 << l); ++c) {
+          const long long fi = cidx(l + 1, c);
+          off[fi] = p;
+          const int kc_ = (int)kk[fi], kp = (int)kk[cidx(l, c >> 1)];
+          for (int j = 0; j < kp; ++j)
+            for (int i = 0; i < kc_; ++i)
+              dst[p++] = h[(size_t)(c >> 1) * stride[l] + (c & 1) * rp[l + 1] + i + (size_t)j * ld];
+        }
+      }
+      off[ncl] = p;
+    };
+    trans(M->Tr, M->Tr_stride, M->rr, M->krow, o->Er, o->Er_off);
+    trans(M->Tc, M->Tc_stride, M->rc, M->kcol, o->Ec, o->Ec_off);
+    int64_t ps = 0, pf = 0;
+    for (int l = 0; l <= L; ++l) {
+      const LevelNodes& ln = s.lev[l];
+      std::vector<double> hs = M->S[l].bytes() ? fetch(M->S[l]) : std::vector<double>();
+      const long long bs = (long long)M->rr[l] * M->rc[l];
+      for (int q = 0; q < ln.size(); ++q) {
+        const long long g = s.node_base[l] + q;
+        o->S_off[g] = ps;
+        if (ln.type[q] == kR) {
+          const int kr = (int)M->krow[cidx(l, ln.row[q])], kc = (int)M->kcol[cidx(l, ln.col[q])];
+          for (int j = 0; j < kc; ++j)
+            for (int i = 0; i < kr; ++i) o->S[ps++] = hs[(size_t)q * bs + i + (size_t)j * M->rr[l]];
+        }
+      }
+    }
+    o->S_off[s.node_base[L + 1]] = ps;
+    {
+      const LevelNodes& ln = s.lev[L];
+      std::vector<double> hf = fetch(M->F);
+      for (int l = 0; l < L; ++l)
+        for (int q = 0; q < s.lev[l].size(); ++q) o->F_off[s.node_base[l] + q] = 0;
+      for (int q = 0; q < ln.size(); ++q) {
+        const long long g = s.node_base[L] + q;
+        o->F_off[g] = pf;
+        if (ln.type[q] == kF) {
+          const int ni = s.leaf_size[ln.row[q]], nj = s.leaf_size[ln.col[q]];
+          for (int j = 0; j < nj; ++j)
+            for (int i = 0; i < ni; ++i) o->F[pf++] = hf[(size_t)q * np * np + i + (size_t)j * np];
+        }
+      }
+      o->F_off[s.node_base[L + 1]] = pf;
+    }
+    return H2_OK;
+  } catch (const Error& e) {
+    return set_error(e.code, e.msg);
+  }
+}
+
+h2_status h2_stats(h2_mat M, h2_stats_t* out) {
+  if (!M || !out) return h2::set_error(H2_ERR_ARG, "null argument");
+  *out = M->stats;
+  return H2_OK;
+}
+
+void h2_free(h2_mat M) { delete M; }
+
+h2_status h2_plan_info(const h2_host_matrix* m, int64_t max_levels, int64_t* triples,
+                       int64_t* blue, int64_t* merged, int64_t* lmin) {
+  using namespace h2;
+  if (!m || !triples || !blue || !merged || !lmin) return set_error(H2_ERR_ARG, "null argument");
+  try {
+    Structure s;
+    std::string err = build_structure(s, m->n, m->L, m->leaf_off, m->perm, m->node_off,
+                                      m->node_row, m->node_col, m->node_type);
+    if (!err.empty()) return set_error(H2_ERR_ARG, err);
+    if (max_levels <= s.L) return set_error(H2_ERR_ARG, "max_levels <= L");
+    Plan p;
+    err = build_plan(s, p);
+    if (!err.empty()) return set_error(H2_ERR_INTERNAL, err);
+    for (int l = 0; l <= s.L; ++l) {
+      triples[l] = p.triples_per_level[l];
+      blue[l] = p.n_blue[l];
+      merged[l] = p.n_case1[l];
+    }
+    *lmin = s.lmin;
+    return H2_OK;
+  } catch (const std::exception& e) {
+    return set_error(H2_ERR_INTERNAL, e.what());
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// Internal types of the h2mmp library (not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "h2mmp.h"
+#include "kernels.h"
+#include "structure.h"
+
+namespace h2 {
+
+h2_status set_error(h2_status s, const std::string& msg);
+
+#define H2_HIP(call)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::h2::Error(H2_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Error {
+  h2_status code;
+  std::string msg;
+  Error(h2_status c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+inline int pad16(long long x) { return (int)(x <= 16 ? 16 : ((x + 15) / 16) * 16); }
+
+}  // namespace h2
+
+struct h2_ctx_s {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+  hipStream_t stream = nullptr;
+  bool profiling = false;
+  std::multimap<size_t, void*> pool;
+  std::unordered_map<void*, size_t> live;
+  void* alloc(size_t bytes);
+  void release(void* p);
+  ~h2_ctx_s();
+};
+
+namespace h2 {
+
+// Device buffer owned by a context's pool.
+class Buf {
+ public:
+  Buf() = default;
+  Buf(h2_ctx c, size_t bytes) : ctx_(c), bytes_(bytes) { p_ = bytes ? c->alloc(bytes) : nullptr; }
+  ~Buf() { reset(); }
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  Buf(Buf&& o) noexcept { *this = std::move(o); }
+  Buf& operator=(Buf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      ctx_ = o.ctx_;
+      p_ = o.p_;
+      bytes_ = o.bytes_;
+      o.p_ = nullptr;
+      o.bytes_ = 0;
+    }
+    return *this;
+  }
+  void reset() {
+    if (p_ && ctx_) ctx_->release(p_);
+    p_ = nullptr;
+    bytes_ = 0;
+  }
+  template <typename T>
+  T* as() const { return (T*)p_; }
+  double* d() const { return (double*)p_; }
+  size_t bytes() const { return bytes_; }
+
+ private:
+  h2_ctx ctx_ = nullptr;
+  void* p_ = nullptr;
+  size_t bytes_ = 0;
+};
+
+struct DevList {
+  int nout = 0;
+  int ntask = 0;
+  // largest tile index referenced per operand and selector (-1: none)
+  int max_a[2] = {-1, -1};
+  int max_b[2] = {-1, -1};
+  int max_out = -1;
+  const int* out = nullptr;
+  const int* seg = nullptr;
+  const int* a = nullptr;
+  const int* b = nullptr;
+};
+
+// All task lists of a plan uploaded to one device buffer.
+struct DevPlan {
+  Buf mem;
+  std::unordered_map<const TaskList*, DevList> lists;
+  const DevList& get(const TaskList& t) const { return lists.at(&t); }
+};
+
+struct Shape {
+  Structure s;
+  std::unique_ptr<Plan> plan;
+  std::unique_ptr<DevPlan> dplan;
+  Buf d_perm, d_leaf_off;
+};
+
+}  // namespace h2
+
+struct h2_mat_s {
+  h2_ctx ctx = nullptr;
+  std::shared_ptr<h2::Shape> shape;
+  bool product = false;            // produced by h2_mmp (levels above lmin carry no basis)
+  std::vector<int> rr, rc;         // padded ranks per level
+  std::vector<int64_t> krow, kcol; // actual ranks, flat cluster index 2^l-1+c
+  h2::Buf V, W;                    // leaf bases
+  long long V_stride = 0, W_stride = 0;
+  std::vector<h2::Buf> Tr, Tc;     // stacked transfers per parent cluster, level l < L
+  std::vector<long long> Tr_stride, Tc_stride;
+  std::vector<h2::Buf> S;          // per level, flat by node, rr[l] x rc[l]
+  h2::Buf F;                       // leaf level, flat by node, npad x npad
+  h2_stats_t stats{};
+  const h2::Structure& st() const { return shape->s; }
+};
+
+namespace h2 {
+
+// Operand description for the batched GEMM helpers.
+struct Op {
+  const double* base0 = nullptr;
+  const double* base1 = nullptr;
+  long long stride0 = 0, stride1 = 0;
+  int ld = 0;
+  long long sub_r = 0, sub_c = 0;
+};
+
+enum KernelKind { kKindOther = 0, kKindTriple = 1, kKindGram = 2, kKindEig = 3, kKindCount = 4 };
+
+struct Profiler {
+  bool on = false;
+  hipStream_t stream = nullptr;
+  struct Rec {
+    hipEvent_t a, b;
+    int kind;
+    double flops;
+  };
+  std::vector<Rec> recs;
+  void begin(int kind, double flops, hipEvent_t* out_a);
+  void end(hipEvent_t a, int kind, double flops);
+  void collect(double* ms, long long* launches, double* flops);
+};
+
+void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int n, int k,
+          const Op& A, bool tA, const Op& B, bool tB, double* C, long long cstride, int ldc,
+          long long csub_r, long long csub_c, double alpha, double beta);
+void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, double* C,
+            long long cstride, int ldc, long long csub_r, long long csub_c, double beta);
+void zero(hipStream_t s, double* p, long long n);
+
+std::unique_ptr<DevPlan> upload_plan(h2_ctx ctx, const Plan& p);
+void scan_limits(const TaskList& t, DevList& d);
+// context whose allocations bound-check the launches of the current call
+extern thread_local h2_ctx g_active_ctx;
+
+h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C);
+void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64_t nrhs);
+
+}  // namespace h2

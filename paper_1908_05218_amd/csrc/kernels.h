@@ -1,0 +1,100 @@
+// Internal launch interface of the HIP kernels (not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace h2k {
+
+// A batch of equally shaped column-major blocks.  Block index v encodes
+// (tile << 3) | (sel << 2) | (col_half << 1) | row_half; the block starts at
+// base[sel] + tile*stride[sel] + row_half*sub_r + col_half*sub_c.
+struct Opnd {
+  const void* base[2];
+  long long stride[2];
+  int ld;
+  long long sub_r;
+  long long sub_c;
+};
+
+template <typename T>
+struct BgemmArgs {
+  int m, n, k, nout, tiles_m, tiles_n;
+  int transA, transB;
+  Opnd A, B;
+  T* C;
+  long long cstride;
+  int ldc;
+  long long csub_r, csub_c;
+  const int* out_idx;  // [nout], encoded like operand indices (sel ignored)
+  const int* seg;      // [nout+1] task ranges
+  const int* a_idx;    // [ntask]
+  const int* b_idx;    // [ntask]
+  T alpha, beta;
+};
+
+template <typename T>
+struct SegsumArgs {
+  int m, n, nout;
+  Opnd A;
+  T* C;
+  long long cstride;
+  int ldc;
+  long long csub_r, csub_c;
+  const int* out_idx;
+  const int* seg;
+  const int* a_idx;
+  T beta;
+};
+
+struct GramNormArgs {
+  const double* G[3];
+  long long stride;
+  int D;
+  double* out;
+  int* status;
+};
+
+// Batched truncated eigen-decomposition of symmetric positive semi-definite
+// Gram matrices (FP64).  Cluster c: the D x D matrix at G + c*gstride (ld D)
+// restricted to rows/columns [0,k1[c]) and [half, half+k2[c]) (the children's
+// live coordinates); output orthonormal eigenvectors (descending) in
+// U + c*ustride (D x D, ld D) scattered back to the padded rows, zero columns
+// beyond the kept rank, rank[c] = kept count.
+struct EigArgs {
+  const double* G;
+  long long gstride;
+  int D;
+  double* U;
+  long long ustride;
+  int* rank;
+  const int* k1;   // k1[c*kstride]: live rows of the first child (or of the leaf)
+  const int* k2;   // k2[c*kstride]: live rows of the second child (null: none)
+  int kstride;
+  int half;
+  double* scratch;  // per cluster 5*D*D doubles
+  long long sstride;
+  double tau;
+  int exact;
+  int* status;  // [0] non-finite, [1] dimension over limit
+};
+
+constexpr int kEigNmax = 192;
+
+template <typename T>
+hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_segsum(const SegsumArgs<T>& a, hipStream_t s);
+hipError_t launch_gram_norm(const GramNormArgs& a, int nclusters, hipStream_t s);
+hipError_t launch_eig(const EigArgs& a, int nclusters, hipStream_t s);
+hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);
+hipError_t launch_fill_f(float* p, float v, long long n, hipStream_t s);
+hipError_t launch_d2f(const double* in, float* out, long long n, hipStream_t s);
+hipError_t launch_f2d(const float* in, double* out, long long n, hipStream_t s);
+hipError_t launch_gather_rows(const double* x, double* out, const long long* perm,
+                              const long long* leaf_off, int nleaf, int npad, long long n,
+                              int nrhs, hipStream_t s);
+hipError_t launch_scatter_rows(const double* in, double* y, const long long* perm,
+                               const long long* leaf_off, int nleaf, int npad, long long n,
+                               int nrhs, hipStream_t s);
+
+}  // namespace h2k

@@ -1,0 +1,309 @@
+// Batched kernels of the H^2 matrix-matrix product for gfx950.
+//
+// Every per-level step of the product (Sections III and IV of Ma & Jiao) is a
+// batch of small dense products of uniform shape within one launch: cluster
+// basis products (equation nonleafproduct), Gram sums (Gr1L..case3-ch-nl),
+// projections (leafproj, nonleafproj), collects (Fcollect, NLcollect),
+// coupling products (leafcoup_simple, nonleafcoup_simple) and the top-down
+// split.  They all run through one segmented batched GEMM:
+//
+//   C[out(o)] = alpha * sum_{t in seg(o)} op(A[a(t)]) op(B[b(t)]) + beta * C[out(o)]
+//
+// One workgroup owns one 32x32 tile of one output and loops over the tasks
+// of that output's segment, so every output is reduced in registers in a
+// fixed order (deterministic, no atomics).  Four wave64s each hold a 16x16
+// MFMA accumulator; operand tiles are staged through LDS so that transposed
+// and plain operands load coalesced.
+//
+// Operand addressing: an index v encodes (tile << 3) | (sel << 2) | (ch << 1) | rh.
+// The block lives at base[sel] + tile*stride[sel] + rh*sub_r + ch*sub_c, so a
+// child block inside its parent's 2x2 tile (the "collected" non-leaf blocks
+// of equations nonleafA and nonleafB) is addressed in place.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace h2k {
+
+__device__ __forceinline__ long long opnd_off(const Opnd& o, int v, int& sel) {
+  sel = (v >> 2) & 1;
+  return (long long)(v >> 3) * o.stride[sel] + ((v & 1) ? o.sub_r : 0LL) +
+         ((v & 2) ? o.sub_c : 0LL);
+}
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
+  typedef typename Mfma<T>::v4 v4;
+  const int ntile = p.tiles_m * p.tiles_n;
+  const int o = blockIdx.x / ntile;
+  const int tt = blockIdx.x - o * ntile;
+  const int tm = tt % p.tiles_m;
+  const int tn = tt / p.tiles_m;
+  __shared__ T As[16][33];
+  __shared__ T Bs[16][33];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = (wave & 1) * 16;
+  const int wc = (wave >> 1) * 16;
+  v4 acc = {0, 0, 0, 0};
+  const int s0 = p.seg[o];
+  const int s1 = p.seg[o + 1];
+  const int row0 = tm * 32;
+  const int col0 = tn * 32;
+  for (int t = s0; t < s1; ++t) {
+    int sa, sb;
+    const long long oa = opnd_off(p.A, p.a_idx[t], sa);
+    const long long ob = opnd_off(p.B, p.b_idx[t], sb);
+    const T* Ab = (const T*)p.A.base[sa] + oa;
+    const T* Bb = (const T*)p.B.base[sb] + ob;
+    const int lda = p.A.ld;
+    const int ldb = p.B.ld;
+    for (int kk = 0; kk < p.k; kk += 16) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int e = tid + r * 256;
+        int i, q;
+        if (!p.transA) { i = e & 31; q = e >> 5; } else { q = e & 15; i = e >> 4; }
+        const int gi = row0 + i;
+        T v = 0;
+        if (gi < p.m)
+          v = p.transA ? Ab[(kk + q) + (long long)gi * lda] : Ab[gi + (long long)(kk + q) * lda];
+        As[q][i] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int e = tid + r * 256;
+        int j, q;
+        if (!p.transB) { q = e & 15; j = e >> 4; } else { j = e & 31; q = e >> 5; }
+        const int gj = col0 + j;
+        T v = 0;
+        if (gj < p.n)
+          v = p.transB ? Bb[gj + (long long)(kk + q) * ldb] : Bb[(kk + q) + (long long)gj * ldb];
+        Bs[q][j] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const T a = As[q4 * 4 + (lane >> 4)][wr + (lane & 15)];
+        const T b = Bs[q4 * 4 + (lane >> 4)][wc + (lane & 15)];
+        acc = Mfma<T>::op(a, b, acc);
+      }
+      __syncthreads();
+    }
+  }
+  T* Cb = p.C + ((long long)(p.out_idx[o] >> 3) * p.cstride + ((p.out_idx[o] & 1) ? p.csub_r : 0LL) +
+                 ((p.out_idx[o] & 2) ? p.csub_c : 0LL));
+  const int gj = col0 + wc + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int gi = row0 + wr + 4 * (lane >> 4) + v;
+    if (gi < p.m && gj < p.n) {
+      T* c = Cb + gi + (long long)gj * p.ldc;
+      T val = p.alpha * acc[v];
+      if (p.beta != (T)0) val += p.beta * (*c);
+      *c = val;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_segsum(SegsumArgs<T> p) {
+  const int per = (p.m * p.n + 255) / 256;
+  const int o = blockIdx.x / per;
+  const int chunk = blockIdx.x - o * per;
+  const int e = chunk * 256 + threadIdx.x;
+  if (e >= p.m * p.n) return;
+  const int i = e % p.m;
+  const int j = e / p.m;
+  T s = 0;
+  for (int t = p.seg[o]; t < p.seg[o + 1]; ++t) {
+    int sel;
+    const long long off = opnd_off(p.A, p.a_idx[t], sel);
+    s += ((const T*)p.A.base[sel])[off + i + (long long)j * p.A.ld];
+  }
+  const int v = p.out_idx[o];
+  T* c = p.C + (long long)(v >> 3) * p.cstride + ((v & 1) ? p.csub_r : 0LL) +
+         ((v & 2) ? p.csub_c : 0LL) + i + (long long)j * p.ldc;
+  *c = (p.beta != (T)0) ? (*c) * p.beta + s : s;
+}
+
+// Normalised Gram sum of one cluster: sum over the non-empty components of
+// G_c / trace(G_c) (each component divided by its trace).
+__global__ __launch_bounds__(256) void k_gram_norm(GramNormArgs p) {
+  const int c = blockIdx.x;
+  const int D = p.D;
+  __shared__ double tr[3];
+  __shared__ double red[256];
+  for (int comp = 0; comp < 3; ++comp) {
+    const double* g = p.G[comp] + (long long)c * p.stride;
+    double s = 0;
+    for (int i = threadIdx.x; i < D; i += 256) s += g[i + (long long)i * D];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) tr[comp] = red[0];
+    __syncthreads();
+  }
+  const double w0 = tr[0] > 0 ? 1.0 / tr[0] : 0.0;
+  const double w1 = tr[1] > 0 ? 1.0 / tr[1] : 0.0;
+  const double w2 = tr[2] > 0 ? 1.0 / tr[2] : 0.0;
+  const long long base = (long long)c * p.stride;
+  int bad = 0;
+  for (int e = threadIdx.x; e < D * D; e += 256) {
+    const double v = w0 * p.G[0][base + e] + w1 * p.G[1][base + e] + w2 * p.G[2][base + e];
+    if (!(v == v) || v - v != 0.0) bad = 1;
+    p.out[base + e] = v;
+  }
+  if (bad) p.status[0] = 1;
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin* in, Tout* out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (Tout)in[i];
+}
+
+__global__ void k_fill(double* p, double v, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f(float* p, float v, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// x (n x nrhs, original order, ld = n) -> padded tree order
+// (leaf c, local row r) at out[(c*npad + r) + col*(nleaf*npad)].
+__global__ void k_gather_rows(const double* x, double* out, const long long* perm,
+                              const long long* leaf_off, int nleaf, int npad, long long n,
+                              int nrhs) {
+  const long long total = (long long)nleaf * npad;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total * nrhs) return;
+  const long long col = e / total;
+  const long long rr = e - col * total;
+  const int c = (int)(rr / npad);
+  const int r = (int)(rr - (long long)c * npad);
+  const long long pos = leaf_off[c] + r;
+  double v = 0;
+  if (pos < leaf_off[c + 1]) v = x[perm[pos] + col * n];
+  out[e] = v;
+}
+
+__global__ void k_scatter_rows(const double* in, double* y, const long long* perm,
+                               const long long* leaf_off, int nleaf, int npad, long long n,
+                               int nrhs) {
+  const long long total = (long long)nleaf * npad;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total * nrhs) return;
+  const long long col = e / total;
+  const long long rr = e - col * total;
+  const int c = (int)(rr / npad);
+  const int r = (int)(rr - (long long)c * npad);
+  const long long pos = leaf_off[c] + r;
+  if (pos < leaf_off[c + 1]) y[perm[pos] + col * n] = in[e];
+}
+
+// ---------------------------------------------------------------- launches
+static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+template <typename T>
+hipError_t launch_bgemm(const BgemmArgs<T>& a0, hipStream_t s) {
+  if (a0.nout <= 0) return hipSuccess;
+  BgemmArgs<T> a = a0;
+  a.tiles_m = cdiv(a.m, 32);
+  a.tiles_n = cdiv(a.n, 32);
+  const long long grid = (long long)a.nout * a.tiles_m * a.tiles_n;
+  hipLaunchKernelGGL(k_bgemm<T>, dim3((unsigned)grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_segsum(const SegsumArgs<T>& a, hipStream_t s) {
+  if (a.nout <= 0) return hipSuccess;
+  const long long per = (a.m * (long long)a.n + 255) / 256;
+  hipLaunchKernelGGL(k_segsum<T>, dim3((unsigned)(per * a.nout)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_norm(const GramNormArgs& a, int nclusters, hipStream_t s) {
+  if (nclusters <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram_norm, dim3(nclusters), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, double v, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(cdiv(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f(float* p, float v, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f, dim3(cdiv(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_d2f(const double* in, float* out, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_convert<double, float>), dim3(cdiv(n, 256)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_f2d(const float* in, double* out, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(cdiv(n, 256)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const double* x, double* out, const long long* perm,
+                              const long long* leaf_off, int nleaf, int npad, long long n,
+                              int nrhs, hipStream_t s) {
+  const long long tot = (long long)nleaf * npad * nrhs;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, dim3(cdiv(tot, 256)), dim3(256), 0, s, x, out, perm,
+                     leaf_off, nleaf, npad, n, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const double* in, double* y, const long long* perm,
+                               const long long* leaf_off, int nleaf, int npad, long long n,
+                               int nrhs, hipStream_t s) {
+  const long long tot = (long long)nleaf * npad * nrhs;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_rows, dim3(cdiv(tot, 256)), dim3(256), 0, s, in, y, perm,
+                     leaf_off, nleaf, npad, n, nrhs);
+  return hipGetLastError();
+}
+
+template hipError_t launch_bgemm<double>(const BgemmArgs<double>&, hipStream_t);
+template hipError_t launch_bgemm<float>(const BgemmArgs<float>&, hipStream_t);
+template hipError_t launch_segsum<double>(const SegsumArgs<double>&, hipStream_t);
+template hipError_t launch_segsum<float>(const SegsumArgs<float>&, hipStream_t);
+
+}  // namespace h2k

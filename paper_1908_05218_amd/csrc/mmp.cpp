@@ -1,0 +1,580 @@
+// Level scheduler of the H^2 matrix-matrix product C = A B (Ma & Jiao,
+// Sections III and IV).  Every step is a batch of uniform small products over
+// the task lists of the symbolic phase; ranks of C are data-dependent, so
+// after each level's eigen-decompositions the kept ranks are read back and the
+// next launches use the level's padded rank.
+//
+// Data layout (all column-major, FP64):
+//  * per-cluster blocks: flat by cluster index, fixed stride;
+//  * stacked transfers T_I = [E_I1; E_I2] per parent cluster;
+//  * per-node blocks: flat by node index within the level, except the
+//    collected blocks A^_l, B^_l (equations Fcollect / NLcollect) and the
+//    temporary couplings of blue targets, which are stored 2x2-grouped by the
+//    parent so the next level reads them as one (NL)_coll block in place.
+//
+// The leaf-level admissible-target products use the leaf-coordinate form
+//   S_ik += (V^C_i^T A_ij)(B_jk W^C_k)
+// with V^C_i^T A_ij equal to V^C_i^T F_ij (dense) or P^A_i S^A_ij W^A_j^T
+// (admissible) and B_jk W^C_k equal to F_jk W^C_k or V^B_j S^B_jk P^B_k: an
+// exact rewriting of the four cases of equation leafcoup_simple that gives
+// every leaf triple the same shape (one batched launch).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "internal.h"
+
+namespace h2 {
+
+namespace {
+
+inline long long cidx(int l, int c) { return (1LL << l) - 1 + c; }
+
+struct Dims {
+  int m, n, k;
+};
+
+double canonical_flops(const Structure& s, const h2_mat A, const h2_mat B, const h2_mat C) {
+  // 2 r1 r2 r3 per evaluated block product with the actual dimensions
+  double f = 0;
+  const int L = s.L;
+  for (int l = s.lmin; l <= L; ++l) {
+    const LevelNodes& ln = s.lev[l];
+    std::vector<std::vector<int>> byrow(1 << l);
+    for (int q = 0; q < ln.size(); ++q) byrow[ln.row[q]].push_back(q);
+    for (int qa = 0; qa < ln.size(); ++qa) {
+      const int i = ln.row[qa], j = ln.col[qa], ta = ln.type[qa];
+      for (int qb : byrow[j]) {
+        const int tb = ln.type[qb];
+        if (ta == kNL && tb == kNL) continue;
+        const int k = ln.col[qb];
+        const int qc = s.lev[l].find(i, k);
+        if (l == L) {
+          if (qc >= 0 && ln.type[qc] == kF)
+            f += 2.0 * s.leaf_size[i] * s.leaf_size[j] * s.leaf_size[k];
+          else
+            f += 2.0 * C->krow[cidx(l, i)] * s.leaf_size[j] * C->kcol[cidx(l, k)];
+        } else {
+          const double inner = ta == kNL ? B->krow[cidx(l, j)] : A->kcol[cidx(l, j)];
+          f += 2.0 * C->krow[cidx(l, i)] * inner * C->kcol[cidx(l, k)];
+        }
+      }
+    }
+  }
+  return f;
+}
+
+}  // namespace
+
+h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C_out) {
+  (void)prec;
+  g_active_ctx = ctx;
+  const auto t_sym0 = std::chrono::steady_clock::now();
+  Shape& sh = *A->shape;
+  const Structure& s = sh.s;
+  if (!sh.plan) {
+    sh.plan = std::make_unique<Plan>();
+    std::string err = build_plan(s, *sh.plan);
+    if (!err.empty()) {
+      sh.plan.reset();
+      throw Error(H2_ERR_INTERNAL, err);
+    }
+    sh.dplan = upload_plan(ctx, *sh.plan);
+  }
+  const double sym_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_sym0).count();
+  const Plan& P = *sh.plan;
+  const DevPlan& DP = *sh.dplan;
+  auto dl = [&](const TaskList& t) -> const DevList& { return DP.get(t); };
+  hipStream_t st = ctx->stream;
+  const int L = s.L, lmin = s.lmin, np = s.npad, nleaf = 1 << L;
+  const bool exact = (mode == H2_TRUNC_EXACT) || eps == 0.0;
+  const double tau = exact ? 0.0 : (mode == H2_TRUNC_PAPER ? eps : eps * eps);
+  Profiler prof;
+  prof.on = ctx->profiling;
+  prof.stream = st;
+  Profiler* pp = &prof;
+
+  hipEvent_t ev0, ev1;
+  H2_HIP(hipEventCreate(&ev0));
+  H2_HIP(hipEventCreate(&ev1));
+  H2_HIP(hipEventRecord(ev0, st));
+
+  const std::vector<int>&rrA = A->rr, &rcA = A->rc, &rrB = B->rr, &rcB = B->rc;
+  Buf status(ctx, 4 * sizeof(int));
+  H2_HIP(hipMemsetAsync(status.as<int>(), 0, 4 * sizeof(int), st));
+
+  // ---------------------------------------------------------- output C
+  auto C = std::make_unique<h2_mat_s>();
+  C->ctx = ctx;
+  C->shape = A->shape;
+  C->product = true;
+  C->rr.assign(L + 1, 16);
+  C->rc.assign(L + 1, 16);
+  C->krow.assign((2LL << L) - 1, 0);
+  C->kcol.assign((2LL << L) - 1, 0);
+  C->Tr.resize(L);
+  C->Tc.resize(L);
+  C->Tr_stride.assign(L, 0);
+  C->Tc_stride.assign(L, 0);
+  C->S.resize(L + 1);
+  std::vector<int> cpad(L + 1, 16);
+  std::vector<Buf> rank_r(L + 1), rank_c(L + 1);
+
+  // ---------------------------------------------------------- step 0: Pi
+  std::vector<Buf> Pi(L + 1);
+  Pi[L] = Buf(ctx, (size_t)nleaf * rcA[L] * rrB[L] * sizeof(double));
+  gemm(st, pp, kKindOther, dl(P.pi.leaf), rcA[L], rrB[L], np,
+       Op{A->W.d(), nullptr, A->W_stride, 0, np}, true, Op{B->V.d(), nullptr, B->V_stride, 0, np},
+       false, Pi[L].d(), (long long)rcA[L] * rrB[L], rcA[L], 0, 0, 1.0, 0.0);
+  for (int l = L - 1; l >= lmin; --l) {
+    const int ch = l + 1;
+    Buf X(ctx, (size_t)(2 << l) * rcA[ch] * rrB[l] * sizeof(double));
+    gemm(st, pp, kKindOther, dl(P.pi.X[l]), rcA[ch], rrB[l], rrB[ch],
+         Op{Pi[ch].d(), nullptr, (long long)rcA[ch] * rrB[ch], 0, rcA[ch]}, false,
+         Op{B->Tr[l].d(), nullptr, B->Tr_stride[l], 0, 2 * rrB[ch], rrB[ch], 0}, false, X.d(),
+         (long long)rcA[ch] * rrB[l], rcA[ch], 0, 0, 1.0, 0.0);
+    Pi[l] = Buf(ctx, (size_t)(1 << l) * rcA[l] * rrB[l] * sizeof(double));
+    gemm(st, pp, kKindOther, dl(P.pi.S[l]), rcA[l], rrB[l], rcA[ch],
+         Op{A->Tc[l].d(), nullptr, A->Tc_stride[l], 0, 2 * rcA[ch], rcA[ch], 0}, true,
+         Op{X.d(), nullptr, (long long)rcA[ch] * rrB[l], 0, rcA[ch]}, false, Pi[l].d(),
+         (long long)rcA[l] * rrB[l], rcA[l], 0, 0, 1.0, 0.0);
+  }
+
+  // truncated eigen-decomposition of a level's normalised Grams
+  auto eig_level = [&](int l, int D, Buf G[3], Buf& Ug, Buf& rank, const int* k1, const int* k2,
+                       int kstride, int half) {
+    const int ncl = 1 << l;
+    Buf Gn(ctx, (size_t)ncl * D * D * sizeof(double));
+    h2k::GramNormArgs ga{};
+    for (int c = 0; c < 3; ++c) ga.G[c] = G[c].d();
+    ga.stride = (long long)D * D;
+    ga.D = D;
+    ga.out = Gn.d();
+    ga.status = status.as<int>();
+    H2_HIP(h2k::launch_gram_norm(ga, ncl, st));
+    Ug = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
+    rank = Buf(ctx, (size_t)ncl * sizeof(int));
+    Buf scratch(ctx, (size_t)ncl * 5 * D * D * sizeof(double));
+    h2k::EigArgs ea{};
+    ea.G = Gn.d();
+    ea.gstride = (long long)D * D;
+    ea.D = D;
+    ea.U = Ug.d();
+    ea.ustride = (long long)D * D;
+    ea.rank = rank.as<int>();
+    ea.k1 = k1;
+    ea.k2 = k2;
+    ea.kstride = kstride;
+    ea.half = half;
+    ea.scratch = scratch.d();
+    ea.sstride = 5LL * D * D;
+    ea.tau = tau;
+    ea.exact = exact ? 1 : 0;
+    ea.status = status.as<int>();
+    hipEvent_t e = nullptr;
+    prof.begin(kKindEig, 0, &e);
+    H2_HIP(h2k::launch_eig(ea, ncl, st));
+    prof.end(e, kKindEig, 0);
+  };
+  auto read_ranks = [&](int l, Buf& rr_, Buf& rc_) {
+    const int ncl = 1 << l;
+    std::vector<int> hr(ncl), hc(ncl), stv(4);
+    H2_HIP(hipMemcpyAsync(hr.data(), rr_.as<int>(), ncl * sizeof(int), hipMemcpyDeviceToHost, st));
+    H2_HIP(hipMemcpyAsync(hc.data(), rc_.as<int>(), ncl * sizeof(int), hipMemcpyDeviceToHost, st));
+    H2_HIP(hipMemcpyAsync(stv.data(), status.as<int>(), 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    H2_HIP(hipStreamSynchronize(st));
+    if (stv[0]) throw Error(H2_ERR_NUMERIC, "non-finite Gram matrix at level " + std::to_string(l));
+    if (stv[1])
+      throw Error(H2_ERR_UNSUPPORTED, "a Gram matrix at level " + std::to_string(l) +
+                                          " exceeds the eigensolver limit of " +
+                                          std::to_string(h2k::kEigNmax));
+    int mx = 1;
+    for (int c = 0; c < ncl; ++c) {
+      C->krow[cidx(l, c)] = hr[c];
+      C->kcol[cidx(l, c)] = hc[c];
+      mx = std::max(mx, std::max(hr[c], hc[c]));
+    }
+    return pad16(mx);
+  };
+
+  // ============================================================== leaf level
+  const LeafPlan& LP = P.leaf;
+  const int nnL = s.lev[L].size();
+  const long long nn2 = (long long)np * np;
+  Buf leaf_sizes(ctx, nleaf * sizeof(int));
+  H2_HIP(hipMemcpyAsync(leaf_sizes.as<int>(), s.leaf_size.data(), nleaf * sizeof(int),
+                        hipMemcpyHostToDevice, st));
+  Buf Ur_L, Uc_L;
+  Buf PA_L, PB_L;       // projections at the leaves
+  Buf Ahat_L, Bhat_L;   // collected leaf blocks, 2x2 grouped
+  Buf Acc_L;            // blue accumulators of the leaf level
+  Buf FC;
+  int c = 16;
+  {
+    Buf G[3], Gc[3];
+    for (int k = 0; k < 3; ++k) {
+      G[k] = Buf(ctx, (size_t)nleaf * nn2 * sizeof(double));
+      Gc[k] = Buf(ctx, (size_t)nleaf * nn2 * sizeof(double));
+    }
+    {
+      Buf b1(ctx, nnL * nn2 * sizeof(double)), b2(ctx, nnL * nn2 * sizeof(double)),
+          b3(ctx, nnL * nn2 * sizeof(double));
+      const Op FA{A->F.d(), nullptr, nn2, 0, np}, FB{B->F.d(), nullptr, nn2, 0, np};
+      const Op o1{b1.d(), nullptr, nn2, 0, np}, o2{b2.d(), nullptr, nn2, 0, np},
+          o3{b3.d(), nullptr, nn2, 0, np};
+      // row Gram, case 1: sum_j F^A_ij (sum_k F^B_jk F^B_jk^T) F^A_ij^T over
+      // dense products with an admissible or blue target (equation Gr1L)
+      gemm(st, pp, kKindGram, dl(LP.gB), np, np, np, FB, false, FB, true, b1.d(), nn2, np, 0, 0, 1, 0);
+      segsum(st, dl(LP.H), np, np, o1, b2.d(), nn2, np, 0, 0, 0.0);
+      gemm(st, pp, kKindGram, dl(LP.X1), np, np, np, FA, false, o2, false, b3.d(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G1), np, np, np, o3, false, FA, true, G[0].d(), nn2, np, 0, 0, 1, 0);
+      // column Gram, case 1 (equation case1-ch)
+      gemm(st, pp, kKindGram, dl(LP.hA), np, np, np, FA, true, FA, false, b1.d(), nn2, np, 0, 0, 1, 0);
+      segsum(st, dl(LP.Hc), np, np, o1, b2.d(), nn2, np, 0, 0, 0.0);
+      gemm(st, pp, kKindGram, dl(LP.X1c), np, np, np, FB, true, o2, false, b3.d(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G1c), np, np, np, o3, false, FB, false, Gc[0].d(), nn2, np, 0, 0, 1, 0);
+      // case 2: F^A_ij V^B_j (Gr2L) and (W^A_j^T F^B_jk)^T (case2-ch)
+      Buf Z(ctx, (size_t)nnL * np * std::max(rrB[L], rcA[L]) * sizeof(double));
+      const long long zs = (long long)np * rrB[L], zcs = (long long)np * rcA[L];
+      gemm(st, pp, kKindGram, dl(LP.Z), np, rrB[L], np, FA, false,
+           Op{B->V.d(), nullptr, B->V_stride, 0, np}, false, Z.d(), zs, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G2), np, np, rrB[L], Op{Z.d(), nullptr, zs, 0, np}, false,
+           Op{Z.d(), nullptr, zs, 0, np}, true, G[1].d(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.Zc), np, rcA[L], np, FB, true,
+           Op{A->W.d(), nullptr, A->W_stride, 0, np}, false, Z.d(), zcs, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G2c), np, np, rcA[L], Op{Z.d(), nullptr, zcs, 0, np}, false,
+           Op{Z.d(), nullptr, zcs, 0, np}, true, Gc[1].d(), nn2, np, 0, 0, 1, 0);
+      // case 3/4: the old bases V^A_i V^A_i^T (Gr3L) and W^B_k W^B_k^T (case3-ch)
+      gemm(st, pp, kKindGram, dl(LP.G3), np, np, rrA[L], Op{A->V.d(), nullptr, A->V_stride, 0, np},
+           false, Op{A->V.d(), nullptr, A->V_stride, 0, np}, true, G[2].d(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G3c), np, np, rcB[L], Op{B->W.d(), nullptr, B->W_stride, 0, np},
+           false, Op{B->W.d(), nullptr, B->W_stride, 0, np}, true, Gc[2].d(), nn2, np, 0, 0, 1, 0);
+    }
+    eig_level(L, np, G, Ur_L, rank_r[L], leaf_sizes.as<int>(), nullptr, 1, np);
+    eig_level(L, np, Gc, Uc_L, rank_c[L], leaf_sizes.as<int>(), nullptr, 1, np);
+  }
+  c = read_ranks(L, rank_r[L], rank_c[L]);
+  cpad[L] = c;
+  {
+    const Op VC{Ur_L.d(), nullptr, nn2, 0, np}, WC{Uc_L.d(), nullptr, nn2, 0, np};
+    const Op FA{A->F.d(), nullptr, nn2, 0, np}, FB{B->F.d(), nullptr, nn2, 0, np};
+    // projections (leafproj)
+    PA_L = Buf(ctx, (size_t)nleaf * c * rrA[L] * sizeof(double));
+    PB_L = Buf(ctx, (size_t)nleaf * rcB[L] * c * sizeof(double));
+    gemm(st, pp, kKindOther, dl(LP.PA), c, rrA[L], np, VC, true,
+         Op{A->V.d(), nullptr, A->V_stride, 0, np}, false, PA_L.d(), (long long)c * rrA[L], c, 0, 0, 1, 0);
+    gemm(st, pp, kKindOther, dl(LP.PB), rcB[L], c, np, Op{B->W.d(), nullptr, B->W_stride, 0, np},
+         true, WC, false, PB_L.d(), (long long)rcB[L] * c, rcB[L], 0, 0, 1, 0);
+    // leaf-coordinate left / right operands of every leaf block
+    const long long las = (long long)c * np;
+    Buf LA(ctx, (size_t)nnL * las * sizeof(double)), RB(ctx, (size_t)nnL * las * sizeof(double));
+    {
+      Buf PS(ctx, (size_t)nnL * c * rcA[L] * sizeof(double));
+      Buf SP(ctx, (size_t)nnL * rrB[L] * c * sizeof(double));
+      gemm(st, pp, kKindOther, dl(LP.LA_F), c, np, np, VC, true, FA, false, LA.d(), las, c, 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.PS), c, rcA[L], rrA[L],
+           Op{PA_L.d(), nullptr, (long long)c * rrA[L], 0, c}, false,
+           Op{A->S[L].d(), nullptr, (long long)rrA[L] * rcA[L], 0, rrA[L]}, false, PS.d(),
+           (long long)c * rcA[L], c, 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.LA_R), c, np, rcA[L],
+           Op{PS.d(), nullptr, (long long)c * rcA[L], 0, c}, false,
+           Op{A->W.d(), nullptr, A->W_stride, 0, np}, true, LA.d(), las, c, 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.RB_F), np, c, np, FB, false, WC, false, RB.d(), las, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.SP), rrB[L], c, rcB[L],
+           Op{B->S[L].d(), nullptr, (long long)rrB[L] * rcB[L], 0, rrB[L]}, false,
+           Op{PB_L.d(), nullptr, (long long)rcB[L] * c, 0, rcB[L]}, false, SP.d(),
+           (long long)rrB[L] * c, rrB[L], 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.RB_R), np, c, rrB[L], Op{B->V.d(), nullptr, B->V_stride, 0, np},
+           false, Op{SP.d(), nullptr, (long long)rrB[L] * c, 0, rrB[L]}, false, RB.d(), las, np, 0,
+           0, 1, 0);
+    }
+    // collected leaf blocks for the level above (Fcollect; 2x2 grouped)
+    if (L >= 1) {
+      const int ntile = s.lev[L - 1].n_nl;
+      Ahat_L = Buf(ctx, (size_t)ntile * 4 * c * rrB[L] * sizeof(double));
+      Bhat_L = Buf(ctx, (size_t)ntile * 4 * rcA[L] * c * sizeof(double));
+      gemm(st, pp, kKindOther, dl(LP.Ahat), c, rrB[L], np, Op{LA.d(), nullptr, las, 0, c}, false,
+           Op{B->V.d(), nullptr, B->V_stride, 0, np}, false, Ahat_L.d(), 4LL * c * rrB[L], 2 * c,
+           c, (long long)rrB[L] * 2 * c, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.Bhat), rcA[L], c, np, Op{A->W.d(), nullptr, A->W_stride, 0, np},
+           true, Op{RB.d(), nullptr, las, 0, np}, false, Bhat_L.d(), 4LL * rcA[L] * c, 2 * rcA[L],
+           rcA[L], (long long)c * 2 * rcA[L], 1, 0);
+    }
+    // products into admissible and blue targets (leafcoup_simple)
+    C->S[L] = Buf(ctx, (size_t)nnL * c * c * sizeof(double));
+    zero(st, C->S[L].d(), (long long)nnL * c * c);
+    const int nbt = std::max(1, LP.n_blue_tiles);
+    Acc_L = Buf(ctx, (size_t)nbt * 4 * c * c * sizeof(double));
+    zero(st, Acc_L.d(), (long long)nbt * 4 * c * c);
+    gemm(st, pp, kKindTriple, dl(LP.adm_R), c, c, np, Op{LA.d(), nullptr, las, 0, c}, false,
+         Op{RB.d(), nullptr, las, 0, np}, false, C->S[L].d(), (long long)c * c, c, 0, 0, 1, 1);
+    gemm(st, pp, kKindTriple, dl(LP.adm_B), c, c, np, Op{LA.d(), nullptr, las, 0, c}, false,
+         Op{RB.d(), nullptr, las, 0, np}, false, Acc_L.d(), 4LL * c * c, 2 * c, c,
+         (long long)c * 2 * c, 1, 1);
+  }
+  {
+    // dense targets: exact leaf products with admissible factors densified
+    FC = Buf(ctx, (size_t)nnL * nn2 * sizeof(double));
+    zero(st, FC.d(), nnL * nn2);
+    Buf DA(ctx, (size_t)nnL * nn2 * sizeof(double)), DB(ctx, (size_t)nnL * nn2 * sizeof(double));
+    {
+      Buf T(ctx, (size_t)nnL * np * std::max(rcA[L], rcB[L]) * sizeof(double));
+      gemm(st, pp, kKindOther, dl(LP.densA1), np, rcA[L], rrA[L],
+           Op{A->V.d(), nullptr, A->V_stride, 0, np}, false,
+           Op{A->S[L].d(), nullptr, (long long)rrA[L] * rcA[L], 0, rrA[L]}, false, T.d(),
+           (long long)np * rcA[L], np, 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.densA2), np, np, rcA[L],
+           Op{T.d(), nullptr, (long long)np * rcA[L], 0, np}, false,
+           Op{A->W.d(), nullptr, A->W_stride, 0, np}, true, DA.d(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.densB1), np, rcB[L], rrB[L],
+           Op{B->V.d(), nullptr, B->V_stride, 0, np}, false,
+           Op{B->S[L].d(), nullptr, (long long)rrB[L] * rcB[L], 0, rrB[L]}, false, T.d(),
+           (long long)np * rcB[L], np, 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.densB2), np, np, rcB[L],
+           Op{T.d(), nullptr, (long long)np * rcB[L], 0, np}, false,
+           Op{B->W.d(), nullptr, B->W_stride, 0, np}, true, DB.d(), nn2, np, 0, 0, 1, 0);
+    }
+    gemm(st, pp, kKindTriple, dl(LP.dense), np, np, np, Op{A->F.d(), DA.d(), nn2, nn2, np}, false,
+         Op{B->F.d(), DB.d(), nn2, nn2, np}, false, FC.d(), nn2, np, 0, 0, 1, 1);
+  }
+
+  // ========================================================= non-leaf levels
+  std::vector<Buf> Ur(L + 1), Uc(L + 1), SNL(L + 1);
+  Ur[L] = std::move(Ur_L);
+  Uc[L] = std::move(Uc_L);
+  Buf PA_ch = std::move(PA_L), PB_ch = std::move(PB_L);
+  Buf Ahat_ch = std::move(Ahat_L), Bhat_ch = std::move(Bhat_L), Acc_ch = std::move(Acc_L);
+  for (int l = L - 1; l >= lmin; --l) {
+    const int ch = l + 1;
+    const int cc = cpad[ch];
+    const int K = 2 * cc;
+    const long long K2 = (long long)K * K;
+    const LevelPlan& Q = P.lev[l];
+    const int ncl = 1 << l;
+    const int nn = s.lev[l].size();
+    const Op AccT{Acc_ch.d(), nullptr, 4LL * cc * cc, 0, K};
+    Buf G[3], Gc[3];
+    for (int k = 0; k < 3; ++k) {
+      G[k] = Buf(ctx, (size_t)ncl * K2 * sizeof(double));
+      Gc[k] = Buf(ctx, (size_t)ncl * K2 * sizeof(double));
+    }
+    // case 1: merged children couplings M_IK (nonleafA; case1-ch-nl)
+    gemm(st, pp, kKindGram, dl(Q.G1), K, K, K, AccT, false, AccT, true, G[0].d(), K2, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G1c), K, K, K, AccT, true, AccT, false, Gc[0].d(), K2, K, 0, 0, 1, 0);
+    // case 2: (NL^A)_coll T^B_J (case2-ch-nl) and its column mirror
+    const long long ys = (long long)K * rrB[l], ycs = (long long)rcA[l] * K;
+    Buf Y(ctx, (size_t)std::max(1, nn) * ys * sizeof(double));
+    Buf Yc(ctx, (size_t)std::max(1, nn) * ycs * sizeof(double));
+    gemm(st, pp, kKindGram, dl(Q.Y), K, rrB[l], 2 * rrB[ch],
+         Op{Ahat_ch.d(), nullptr, 4LL * cc * rrB[ch], 0, K}, false,
+         Op{B->Tr[l].d(), nullptr, B->Tr_stride[l], 0, 2 * rrB[ch]}, false, Y.d(), ys, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G2), K, K, rrB[l], Op{Y.d(), nullptr, ys, 0, K}, false,
+         Op{Y.d(), nullptr, ys, 0, K}, true, G[1].d(), K2, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.Yc), rcA[l], K, 2 * rcA[ch],
+         Op{A->Tc[l].d(), nullptr, A->Tc_stride[l], 0, 2 * rcA[ch]}, true,
+         Op{Bhat_ch.d(), nullptr, 4LL * rcA[ch] * cc, 0, 2 * rcA[ch]}, false, Yc.d(), ycs, rcA[l],
+         0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G2c), K, K, rcA[l], Op{Yc.d(), nullptr, ycs, 0, rcA[l]}, true,
+         Op{Yc.d(), nullptr, ycs, 0, rcA[l]}, false, Gc[1].d(), K2, K, 0, 0, 1, 0);
+    // cases 3/4: old bases projected on the children's new bases (case3-ch-nl)
+    const long long ds = (long long)K * rrA[l], qs = (long long)K * rcB[l];
+    Buf Dm(ctx, (size_t)ncl * ds * sizeof(double)), Qm(ctx, (size_t)ncl * qs * sizeof(double));
+    gemm(st, pp, kKindGram, dl(Q.D), cc, rrA[l], rrA[ch],
+         Op{PA_ch.d(), nullptr, (long long)cc * rrA[ch], 0, cc}, false,
+         Op{A->Tr[l].d(), nullptr, A->Tr_stride[l], 0, 2 * rrA[ch], rrA[ch], 0}, false, Dm.d(), ds,
+         K, cc, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G3), K, K, rrA[l], Op{Dm.d(), nullptr, ds, 0, K}, false,
+         Op{Dm.d(), nullptr, ds, 0, K}, true, G[2].d(), K2, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.Q), cc, rcB[l], rcB[ch],
+         Op{PB_ch.d(), nullptr, (long long)rcB[ch] * cc, 0, rcB[ch]}, true,
+         Op{B->Tc[l].d(), nullptr, B->Tc_stride[l], 0, 2 * rcB[ch], rcB[ch], 0}, false, Qm.d(), qs,
+         K, cc, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G3c), K, K, rcB[l], Op{Qm.d(), nullptr, qs, 0, K}, false,
+         Op{Qm.d(), nullptr, qs, 0, K}, true, Gc[2].d(), K2, K, 0, 0, 1, 0);
+    // new transfer matrices
+    eig_level(l, K, G, Ur[l], rank_r[l], rank_r[ch].as<int>(), rank_r[ch].as<int>() + 1, 2, cc);
+    eig_level(l, K, Gc, Uc[l], rank_c[l], rank_c[ch].as<int>(), rank_c[ch].as<int>() + 1, 2, cc);
+    for (int k = 0; k < 3; ++k) {
+      G[k].reset();
+      Gc[k].reset();
+    }
+    const int cl = read_ranks(l, rank_r[l], rank_c[l]);
+    cpad[l] = cl;
+    const Op TCr{Ur[l].d(), nullptr, K2, 0, K}, TCc{Uc[l].d(), nullptr, K2, 0, K};
+    // projections (nonleafproj)
+    Buf PA_l(ctx, (size_t)ncl * cl * rrA[l] * sizeof(double));
+    Buf PB_l(ctx, (size_t)ncl * rcB[l] * cl * sizeof(double));
+    gemm(st, pp, kKindOther, dl(Q.PA), cl, rrA[l], K, TCr, true, Op{Dm.d(), nullptr, ds, 0, K},
+         false, PA_l.d(), (long long)cl * rrA[l], cl, 0, 0, 1, 0);
+    gemm(st, pp, kKindOther, dl(Q.PB), rcB[l], cl, K, Op{Qm.d(), nullptr, qs, 0, K}, true, TCc,
+         false, PB_l.d(), (long long)rcB[l] * cl, rcB[l], 0, 0, 1, 0);
+    // collected blocks of this level (NLcollect; admissible ones projected)
+    const int ntile = l >= 1 ? s.lev[l - 1].n_nl : 1;
+    Buf Ahat_l(ctx, (size_t)std::max(1, ntile) * 4 * cl * rrB[l] * sizeof(double));
+    Buf Bhat_l(ctx, (size_t)std::max(1, ntile) * 4 * rcA[l] * cl * sizeof(double));
+    const long long pas_s = (long long)cl * rcA[l], sbp_s = (long long)rrB[l] * cl;
+    Buf PAS(ctx, (size_t)std::max(1, nn) * pas_s * sizeof(double));
+    Buf SBP(ctx, (size_t)std::max(1, nn) * sbp_s * sizeof(double));
+    const long long at_s = 4LL * cl * rrB[l], bt_s = 4LL * rcA[l] * cl;
+    gemm(st, pp, kKindOther, dl(Q.AhatNL), cl, rrB[l], K, TCr, true, Op{Y.d(), nullptr, ys, 0, K},
+         false, Ahat_l.d(), at_s, 2 * cl, cl, (long long)rrB[l] * 2 * cl, 1, 0);
+    gemm(st, pp, kKindOther, dl(Q.PAS), cl, rcA[l], rrA[l],
+         Op{PA_l.d(), nullptr, (long long)cl * rrA[l], 0, cl}, false,
+         Op{A->S[l].d(), nullptr, (long long)rrA[l] * rcA[l], 0, rrA[l]}, false, PAS.d(), pas_s,
+         cl, 0, 0, 1, 0);
+    gemm(st, pp, kKindOther, dl(Q.AhatR), cl, rrB[l], rcA[l], Op{PAS.d(), nullptr, pas_s, 0, cl},
+         false, Op{Pi[l].d(), nullptr, (long long)rcA[l] * rrB[l], 0, rcA[l]}, false, Ahat_l.d(),
+         at_s, 2 * cl, cl, (long long)rrB[l] * 2 * cl, 1, 0);
+    gemm(st, pp, kKindOther, dl(Q.BhatNL), rcA[l], cl, K, Op{Yc.d(), nullptr, ycs, 0, rcA[l]},
+         false, TCc, false, Bhat_l.d(), bt_s, 2 * rcA[l], rcA[l], (long long)cl * 2 * rcA[l], 1, 0);
+    gemm(st, pp, kKindOther, dl(Q.SBP), rrB[l], cl, rcB[l],
+         Op{B->S[l].d(), nullptr, (long long)rrB[l] * rcB[l], 0, rrB[l]}, false,
+         Op{PB_l.d(), nullptr, (long long)rcB[l] * cl, 0, rcB[l]}, false, SBP.d(), sbp_s, rrB[l],
+         0, 0, 1, 0);
+    gemm(st, pp, kKindOther, dl(Q.BhatR), rcA[l], cl, rrB[l],
+         Op{Pi[l].d(), nullptr, (long long)rcA[l] * rrB[l], 0, rcA[l]}, false,
+         Op{SBP.d(), nullptr, sbp_s, 0, rrB[l]}, false, Bhat_l.d(), bt_s, 2 * rcA[l], rcA[l],
+         (long long)cl * 2 * rcA[l], 1, 0);
+    // targets of this level
+    C->S[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * sizeof(double));
+    zero(st, C->S[l].d(), (long long)std::max(1, nn) * cl * cl);
+    SNL[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * sizeof(double));
+    zero(st, SNL[l].d(), (long long)std::max(1, nn) * cl * cl);
+    const int nbt = std::max(1, Q.n_blue_tiles);
+    Buf Acc_l(ctx, (size_t)nbt * 4 * cl * cl * sizeof(double));
+    zero(st, Acc_l.d(), (long long)nbt * 4 * cl * cl);
+    const long long cs = (long long)cl * cl, acs = 4LL * cl * cl;
+    // case 1: T^C_I^T M_IK T^C_K (nonleafcoup_simple, first case)
+    {
+      Buf X1(ctx, (size_t)std::max(1, Q.n_case1) * cl * K * sizeof(double));
+      gemm(st, pp, kKindOther, dl(Q.c1X), cl, K, K, TCr, true, AccT, false, X1.d(),
+           (long long)cl * K, cl, 0, 0, 1, 0);
+      const Op X1o{X1.d(), nullptr, (long long)cl * K, 0, cl};
+      gemm(st, pp, kKindTriple, dl(Q.c1_R), cl, cl, K, X1o, false, TCc, false, C->S[l].d(), cs, cl,
+           0, 0, 1, 1);
+      gemm(st, pp, kKindTriple, dl(Q.c1_B), cl, cl, K, X1o, false, TCc, false, Acc_l.d(), acs,
+           2 * cl, cl, (long long)cl * 2 * cl, 1, 1);
+    }
+    // cases 2-4 (nonleafcoup_simple)
+    const Op AhatT{Ahat_l.d(), nullptr, at_s, 0, 2 * cl, cl, (long long)rrB[l] * 2 * cl};
+    const Op BhatT{Bhat_l.d(), nullptr, bt_s, 0, 2 * rcA[l], rcA[l], (long long)cl * 2 * rcA[l]};
+    const Op SBPo{SBP.d(), nullptr, sbp_s, 0, rrB[l]}, PASo{PAS.d(), nullptr, pas_s, 0, cl};
+    gemm(st, pp, kKindTriple, dl(Q.t_nl_R), cl, cl, rrB[l], AhatT, false, SBPo, false, C->S[l].d(),
+         cs, cl, 0, 0, 1, 1);
+    gemm(st, pp, kKindTriple, dl(Q.t_nl_B), cl, cl, rrB[l], AhatT, false, SBPo, false, Acc_l.d(),
+         acs, 2 * cl, cl, (long long)cl * 2 * cl, 1, 1);
+    gemm(st, pp, kKindTriple, dl(Q.t_nl_NL), cl, cl, rrB[l], AhatT, false, SBPo, false,
+         SNL[l].d(), cs, cl, 0, 0, 1, 1);
+    gemm(st, pp, kKindTriple, dl(Q.t_r_R), cl, cl, rcA[l], PASo, false, BhatT, false, C->S[l].d(),
+         cs, cl, 0, 0, 1, 1);
+    gemm(st, pp, kKindTriple, dl(Q.t_r_B), cl, cl, rcA[l], PASo, false, BhatT, false, Acc_l.d(),
+         acs, 2 * cl, cl, (long long)cl * 2 * cl, 1, 1);
+    gemm(st, pp, kKindTriple, dl(Q.t_r_NL), cl, cl, rcA[l], PASo, false, BhatT, false, SNL[l].d(),
+         cs, cl, 0, 0, 1, 1);
+    PA_ch = std::move(PA_l);
+    PB_ch = std::move(PB_l);
+    Ahat_ch = std::move(Ahat_l);
+    Bhat_ch = std::move(Bhat_l);
+    Acc_ch = std::move(Acc_l);
+  }
+
+  // ===================================================== top-down split
+  for (int l = lmin; l < L; ++l) {
+    const int ch = l + 1;
+    const int cl = cpad[l], cc = cpad[ch];
+    const int K = 2 * cc;
+    const SplitPlan& SP = P.split[l];
+    const int nn = s.lev[l].size();
+    if (SP.X.nout() == 0) continue;
+    const long long xs = (long long)K * cl;
+    Buf XS(ctx, (size_t)nn * xs * sizeof(double));
+    gemm(st, pp, kKindOther, dl(SP.X), K, cl, cl, Op{Ur[l].d(), nullptr, (long long)K * K, 0, K},
+         false, Op{SNL[l].d(), nullptr, (long long)cl * cl, 0, cl}, false, XS.d(), xs, K, 0, 0, 1, 0);
+    const Op XSo{XS.d(), nullptr, xs, 0, K, cc, 0};
+    const Op TCc{Uc[l].d(), nullptr, (long long)K * K, 0, K, cc, 0};
+    gemm(st, pp, kKindOther, dl(SP.toR), cc, cc, cl, XSo, false, TCc, true, C->S[ch].d(),
+         (long long)cc * cc, cc, 0, 0, 1, 1);
+    if (ch < L)
+      gemm(st, pp, kKindOther, dl(SP.toNL), cc, cc, cl, XSo, false, TCc, true, SNL[ch].d(),
+           (long long)cc * cc, cc, 0, 0, 1, 1);
+    if (ch == L && SP.toF.nout() > 0) {
+      Buf YF(ctx, (size_t)nnL * cc * cc * sizeof(double));
+      Buf ZF(ctx, (size_t)nnL * np * cc * sizeof(double));
+      gemm(st, pp, kKindOther, dl(SP.toF), cc, cc, cl, XSo, false, TCc, true, YF.d(),
+           (long long)cc * cc, cc, 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(SP.F1), np, cc, cc, Op{Ur[L].d(), nullptr, nn2, 0, np}, false,
+           Op{YF.d(), nullptr, (long long)cc * cc, 0, cc}, false, ZF.d(), (long long)np * cc, np,
+           0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(SP.F2), np, np, cc, Op{ZF.d(), nullptr, (long long)np * cc, 0, np},
+           false, Op{Uc[L].d(), nullptr, nn2, 0, np}, true, FC.d(), nn2, np, 0, 0, 1, 1);
+    }
+  }
+  H2_HIP(hipEventRecord(ev1, st));
+  H2_HIP(hipStreamSynchronize(st));
+  float ms = 0;
+  H2_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+  hipEventDestroy(ev0);
+  hipEventDestroy(ev1);
+  {
+    std::vector<int> stv(4);
+    H2_HIP(hipMemcpy(stv.data(), status.as<int>(), 4 * sizeof(int), hipMemcpyDeviceToHost));
+    if (stv[0]) throw Error(H2_ERR_NUMERIC, "non-finite value in a Gram matrix");
+  }
+
+  // ---------------------------------------------------------- assemble C
+  for (int l = lmin; l <= L; ++l) {
+    C->rr[l] = cpad[l];
+    C->rc[l] = cpad[l];
+  }
+  C->V = std::move(Ur[L]);
+  C->W = std::move(Uc[L]);
+  C->V_stride = nn2;
+  C->W_stride = nn2;
+  for (int l = lmin; l < L; ++l) {
+    C->Tr[l] = std::move(Ur[l]);
+    C->Tc[l] = std::move(Uc[l]);
+    C->Tr_stride[l] = 4LL * cpad[l + 1] * cpad[l + 1];
+    C->Tc_stride[l] = C->Tr_stride[l];
+  }
+  C->F = std::move(FC);
+  // stats
+  h2_stats_t& S = C->stats;
+  S.L = L;
+  S.lmin = lmin;
+  for (int l = 0; l <= L && l < H2_MAX_LEVELS; ++l) {
+    long long mr = 0, mc = 0;
+    double sr = 0, sc = 0;
+    for (int c2 = 0; c2 < (1 << l); ++c2) {
+      mr = std::max<long long>(mr, C->krow[cidx(l, c2)]);
+      mc = std::max<long long>(mc, C->kcol[cidx(l, c2)]);
+      sr += C->krow[cidx(l, c2)];
+      sc += C->kcol[cidx(l, c2)];
+    }
+    S.rank_max_r[l] = mr;
+    S.rank_max_c[l] = mc;
+    S.rank_mean_r[l] = sr / (1 << l);
+    S.rank_mean_c[l] = sc / (1 << l);
+  }
+  S.mmp_ms = ms;
+  S.symbolic_ms = sym_ms;
+  S.n_triples = P.n_triples;
+  S.sparsity_constant = s.sparsity_constant();
+  S.flops = canonical_flops(s, A, B, C.get());
+  S.bytes_device = (int64_t)ctx->used;
+  if (prof.on) {
+    double pms[kKindCount], pfl[kKindCount];
+    long long pl[kKindCount];
+    prof.collect(pms, pl, pfl);
+    S.contraction_ms = pms[kKindTriple];
+    S.contraction_launches = pl[kKindTriple];
+    S.contraction_flops = pfl[kKindTriple];
+    S.eig_ms = pms[kKindEig];
+  }
+  *C_out = C.release();
+  return H2_OK;
+}
+
+}  // namespace h2
