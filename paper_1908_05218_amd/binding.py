@@ -5,6 +5,7 @@ an error, there is no fallback."""
 import ctypes as C
 import os
 import re
+import weakref
 
 import numpy as np
 
@@ -108,11 +109,21 @@ class Context:
         h = C.c_void_p()
         _check(lib().h2_ctx_create(device, hbm_budget, C.byref(h)))
         self.h = h
+        self._mats = weakref.WeakSet()
 
     def close(self):
+        """Frees every matrix of this context, then the context."""
         if self.h:
+            for m in list(self._mats):
+                m.free()
             lib().h2_ctx_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def set_profiling(self, on):
         _check(lib().h2_set_profiling(self.h, 1 if on else 0))
@@ -122,11 +133,12 @@ class Matrix:
     def __init__(self, ctx, h):
         self.ctx = ctx
         self.h = h
+        ctx._mats.add(self)
 
     def free(self):
-        if self.h:
+        if self.h and self.ctx.h:
             lib().h2_free(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:

@@ -60,6 +60,150 @@ __device__ __forceinline__ int sturm_count(const double* dd, const double* e2, i
   return cnt;
 }
 
+
+__device__ __forceinline__ double start_vec(int r, int m) {
+  return cos(0.7548776662 * r + 0.5698402909 * m) + 0.1;
+}
+
+// Gaussian elimination with partial pivoting of (T - lambda I), T tridiagonal
+// (diagonal dd, off-diagonal ee); factors of vector m interleaved by m.
+__device__ void tri_factor(const double* dd, const double* ee, int n, double lm, double tiny,
+                           double* sd, double* sl, double* su, double* su2, double* spv, int D,
+                           int m) {
+  for (int i = 0; i < n; ++i) {
+    sd[i * D + m] = dd[i] - lm;
+    spv[i * D + m] = 0.0;
+    if (i < n - 1) {
+      sl[i * D + m] = ee[i];
+      su[i * D + m] = ee[i];
+    }
+    if (i < n - 2) su2[i * D + m] = 0.0;
+  }
+  for (int i = 0; i < n - 1; ++i) {
+    double di = sd[i * D + m];
+    const double li = sl[i * D + m];
+    if (fabs(di) >= fabs(li)) {
+      if (fabs(di) < tiny) {
+        di = di < 0.0 ? -tiny : tiny;
+        sd[i * D + m] = di;
+      }
+      const double fact = li / di;
+      sl[i * D + m] = fact;
+      sd[(i + 1) * D + m] -= fact * su[i * D + m];
+    } else {
+      const double fact = di / li;
+      sd[i * D + m] = li;
+      sl[i * D + m] = fact;
+      const double temp = su[i * D + m];
+      const double dn = sd[(i + 1) * D + m];
+      su[i * D + m] = dn;
+      sd[(i + 1) * D + m] = temp - fact * dn;
+      if (i < n - 2) {
+        const double un = su[(i + 1) * D + m];
+        su2[i * D + m] = un;
+        su[(i + 1) * D + m] = -fact * un;
+      }
+      spv[i * D + m] = 1.0;
+    }
+  }
+  if (fabs(sd[(n - 1) * D + m]) < tiny) sd[(n - 1) * D + m] = sd[(n - 1) * D + m] < 0.0 ? -tiny : tiny;
+}
+
+// Z[:, m] <- (T - lambda_m I)^{-1} Z[:, m] with the stored factors.
+__device__ void tri_solve(int n, const double* sd, const double* sl, const double* su,
+                          const double* su2, const double* spv, int D, int m, double* Z) {
+  for (int i = 0; i < n - 1; ++i) {
+    const double f = sl[i * D + m];
+    if (spv[i * D + m] == 0.0) {
+      Z[(i + 1) * D + m] -= f * Z[i * D + m];
+    } else {
+      const double t0 = Z[i * D + m];
+      const double t1 = Z[(i + 1) * D + m];
+      Z[i * D + m] = t1;
+      Z[(i + 1) * D + m] = t0 - f * t1;
+    }
+  }
+  Z[(n - 1) * D + m] /= sd[(n - 1) * D + m];
+  if (n >= 2)
+    Z[(n - 2) * D + m] =
+        (Z[(n - 2) * D + m] - su[(n - 2) * D + m] * Z[(n - 1) * D + m]) / sd[(n - 2) * D + m];
+  for (int i = n - 3; i >= 0; --i) {
+    Z[i * D + m] = (Z[i * D + m] - su[i * D + m] * Z[(i + 1) * D + m] -
+                    su2[i * D + m] * Z[(i + 2) * D + m]) /
+                   sd[i * D + m];
+    // near-singular shifts make the solution grow: rescale the whole system
+    // (solved and unsolved parts alike) before it can overflow
+    if (fabs(Z[i * D + m]) > 1e150)
+      for (int r = 0; r < n; ++r) Z[r * D + m] *= 1e-150;
+  }
+}
+
+// Scale-safe normalisation of column m by one thread.
+__device__ void normalize_serial(double* Z, int D, int n, int m) {
+  double amax = 0.0;
+  for (int r = 0; r < n; ++r) amax = fmax(amax, fabs(Z[r * D + m]));
+  if (!(amax > 0.0) || !(amax < 1e308)) return;
+  double s = 0.0;
+  for (int r = 0; r < n; ++r) {
+    const double v = Z[r * D + m] / amax;
+    s += v * v;
+  }
+  const double inv = 1.0 / (amax * sqrt(s));
+  for (int r = 0; r < n; ++r) Z[r * D + m] *= inv;
+}
+
+__device__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0;
+#pragma unroll
+  for (int w = 0; w < kEigWaves; ++w) s = fmax(s, red[w]);
+  return s;
+}
+
+// Scale-safe normalisation of column m by the whole workgroup.
+__device__ void normalize_col(double* Z, int D, int n, int m, double* red) {
+  double amax = 0.0;
+  for (int r = threadIdx.x; r < n; r += kEigThreads) amax = fmax(amax, fabs(Z[r * D + m]));
+  amax = block_max(amax, red);
+  double part = 0.0;
+  if (amax > 0.0 && amax < 1e308)
+    for (int r = threadIdx.x; r < n; r += kEigThreads) {
+      const double v = Z[r * D + m] / amax;
+      part += v * v;
+    }
+  const double nrm = block_sum(part, red);
+  const double inv = nrm > 0.0 ? 1.0 / (amax * sqrt(nrm)) : 0.0;
+  for (int r = threadIdx.x; r < n; r += kEigThreads) Z[r * D + m] *= inv;
+  __syncthreads();
+}
+
+// Z[:, m] -= sum_{q0 <= q < m} (Z[:,q] . Z[:,m]) Z[:,q] twice (classical Gram-Schmidt
+// with one re-orthogonalisation), then normalise (whole workgroup).
+__device__ void mgs_step(double* Z, int D, int n, int m, int q0, double* dots, double* red) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int pass = 0; pass < 2 && m > q0; ++pass) {
+    for (int q = q0 + wave; q < m; q += kEigWaves) {
+      double s = 0.0;
+      for (int r = lane; r < n; r += 64) s += Z[r * D + q] * Z[r * D + m];
+      s = wave_sum(s);
+      if (lane == 0) dots[q] = s;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += kEigThreads) {
+      double s = Z[r * D + m];
+      for (int q = q0; q < m; ++q) s -= dots[q] * Z[r * D + q];
+      Z[r * D + m] = s;
+    }
+    __syncthreads();
+  }
+  normalize_col(Z, D, n, m, red);
+}
+
 __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p) {
   extern __shared__ double sm[];
   const int c = blockIdx.x;
@@ -218,103 +362,44 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p) {
   double* sl = S + (long long)D * D;
   double* su = S + 2LL * D * D;
   double* su2 = S + 3LL * D * D;
-  double* Z = S + 4LL * D * D;  // Z[r*D + m]
+  double* Z = S + 4LL * D * D;    // Z[r*D + m]
+  double* spv = S + 5LL * D * D;  // pivot flags of the factorisation of vector m
+  const double tiny = 1e-16 * fmax(bnd, 1e-300);
   if (tid < k) {
     const int m = tid;
-    const double lm = lam[m];
-    const double tiny = 1e-16 * fmax(bnd, 1e-300);
-    unsigned long long piv[3] = {0ULL, 0ULL, 0ULL};
-    for (int i = 0; i < n; ++i) {
-      sd[i * D + m] = dd[i] - lm;
-      if (i < n - 1) {
-        sl[i * D + m] = ee[i];
-        su[i * D + m] = ee[i];
-      }
-      if (i < n - 2) su2[i * D + m] = 0.0;
-    }
-    for (int i = 0; i < n - 1; ++i) {
-      double di = sd[i * D + m];
-      const double li = sl[i * D + m];
-      if (fabs(di) >= fabs(li)) {
-        if (di == 0.0) {
-          di = tiny;
-          sd[i * D + m] = di;
-        }
-        const double fact = li / di;
-        sl[i * D + m] = fact;
-        sd[(i + 1) * D + m] -= fact * su[i * D + m];
-      } else {
-        const double fact = di / li;
-        sd[i * D + m] = li;
-        sl[i * D + m] = fact;
-        const double temp = su[i * D + m];
-        const double dn = sd[(i + 1) * D + m];
-        su[i * D + m] = dn;
-        sd[(i + 1) * D + m] = temp - fact * dn;
-        if (i < n - 2) {
-          const double un = su[(i + 1) * D + m];
-          su2[i * D + m] = un;
-          su[(i + 1) * D + m] = -fact * un;
-        }
-        piv[i >> 6] |= 1ULL << (i & 63);
-      }
-    }
-    if (sd[(n - 1) * D + m] == 0.0) sd[(n - 1) * D + m] = tiny;
-    for (int r = 0; r < n; ++r) Z[r * D + m] = cos(0.7548776662 * r + 0.5698402909 * m) + 0.1;
+    tri_factor(dd, ee, n, lam[m], tiny, sd, sl, su, su2, spv, D, m);
+    for (int r = 0; r < n; ++r) Z[r * D + m] = start_vec(r, m);
     for (int it = 0; it < 2; ++it) {
-      for (int i = 0; i < n - 1; ++i) {
-        const double f = sl[i * D + m];
-        if (!((piv[i >> 6] >> (i & 63)) & 1ULL)) {
-          Z[(i + 1) * D + m] -= f * Z[i * D + m];
-        } else {
-          const double t0 = Z[i * D + m];
-          const double t1 = Z[(i + 1) * D + m];
-          Z[i * D + m] = t1;
-          Z[(i + 1) * D + m] = t0 - f * t1;
-        }
-      }
-      Z[(n - 1) * D + m] /= sd[(n - 1) * D + m];
-      if (n >= 2)
-        Z[(n - 2) * D + m] =
-            (Z[(n - 2) * D + m] - su[(n - 2) * D + m] * Z[(n - 1) * D + m]) / sd[(n - 2) * D + m];
-      for (int i = n - 3; i >= 0; --i)
-        Z[i * D + m] = (Z[i * D + m] - su[i * D + m] * Z[(i + 1) * D + m] -
-                        su2[i * D + m] * Z[(i + 2) * D + m]) /
-                       sd[i * D + m];
-      double s = 0.0;
-      for (int r = 0; r < n; ++r) s += Z[r * D + m] * Z[r * D + m];
-      const double inv = 1.0 / sqrt(s);
-      for (int r = 0; r < n; ++r) Z[r * D + m] *= inv;
+      tri_solve(n, sd, sl, su, su2, spv, D, m, Z);
+      normalize_serial(Z, D, n, m);
     }
   }
   __syncthreads();
 
-  // 5b. two passes of modified Gram-Schmidt, descending order
-  for (int m = 0; m < k; ++m) {
-    for (int pass = 0; pass < 2; ++pass) {
-      if (m > 0) {
-        for (int q = wave; q < m; q += kEigWaves) {
-          double s = 0.0;
-          for (int r = lane; r < n; r += 64) s += Z[r * D + q] * Z[r * D + m];
-          s = wave_sum(s);
-          if (lane == 0) pv[q] = s;
-        }
-        __syncthreads();
-        for (int r = tid; r < n; r += kEigThreads) {
-          double s = Z[r * D + m];
-          for (int q = 0; q < m; ++q) s -= pv[q] * Z[r * D + q];
-          Z[r * D + m] = s;
-        }
-        __syncthreads();
-      }
-      double part = 0.0;
-      for (int r = tid; r < n; r += kEigThreads) part += Z[r * D + m] * Z[r * D + m];
-      const double nrm = block_sum(part, red);
-      const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-      for (int r = tid; r < n; r += kEigThreads) Z[r * D + m] *= inv;
-      __syncthreads();
+  // 5b. eigenvalues closer than delta form a cluster: independent inverse
+  // iterations cannot separate them, so each further member restarts from a
+  // fresh vector and alternates orthogonalisation against the earlier
+  // members with solves (the cluster handling of classical inverse iteration)
+  const double delta = 1e-10 * bnd;
+  int c0 = 0;
+  for (int m = 1; m < k; ++m) {
+    if (lam[m - 1] - lam[m] > delta) {
+      c0 = m;
+      continue;
     }
+    for (int r = tid; r < n; r += kEigThreads) Z[r * D + m] = start_vec(r, m + 7919);
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+      mgs_step(Z, D, n, m, c0, pv, red);
+      if (tid == 0) tri_solve(n, sd, sl, su, su2, spv, D, m, Z);
+      __syncthreads();
+      normalize_col(Z, D, n, m, red);
+    }
+    mgs_step(Z, D, n, m, c0, pv, red);
   }
+
+  // 5c. Gram-Schmidt (with re-orthogonalisation) over all kept vectors
+  for (int m = 0; m < k; ++m) mgs_step(Z, D, n, m, 0, pv, red);
 
   // 6. back-transformation, one wave per vector, scatter to padded rows
   for (int m = wave; m < k; m += kEigWaves) {

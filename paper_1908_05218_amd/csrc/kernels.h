@@ -71,7 +71,7 @@ struct EigArgs {
   const int* k2;   // k2[c*kstride]: live rows of the second child (null: none)
   int kstride;
   int half;
-  double* scratch;  // per cluster 5*D*D doubles
+  double* scratch;  // per cluster 6*D*D doubles
   long long sstride;
   double tau;
   int exact;

@@ -35,9 +35,12 @@ __device__ __forceinline__ long long opnd_off(const Opnd& o, int v, int& sel) {
 template <typename T>
 struct Mfma;
 
+// Output lane layout of the 16x16x4 MFMAs (verified on gfx950): column
+// lane % 16; row (lane/16) + 4*v for the f64 form, 4*(lane/16) + v for f32.
 template <>
 struct Mfma<double> {
   typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
   static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -46,6 +49,7 @@ struct Mfma<double> {
 template <>
 struct Mfma<float> {
   typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
   static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
   const int gj = col0 + wc + (lane & 15);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int gi = row0 + wr + 4 * (lane >> 4) + v;
+    const int gi = row0 + wr + Mfma<T>::row(lane, v);
     if (gi < p.m && gj < p.n) {
       T* c = Cb + gi + (long long)gj * p.ldc;
       T val = p.alpha * acc[v];

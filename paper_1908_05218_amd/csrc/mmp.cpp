@@ -23,6 +23,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -157,7 +159,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     H2_HIP(h2k::launch_gram_norm(ga, ncl, st));
     Ug = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
     rank = Buf(ctx, (size_t)ncl * sizeof(int));
-    Buf scratch(ctx, (size_t)ncl * 5 * D * D * sizeof(double));
+    Buf scratch(ctx, (size_t)ncl * 6 * D * D * sizeof(double));
     h2k::EigArgs ea{};
     ea.G = Gn.d();
     ea.gstride = (long long)D * D;
@@ -170,7 +172,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     ea.kstride = kstride;
     ea.half = half;
     ea.scratch = scratch.d();
-    ea.sstride = 5LL * D * D;
+    ea.sstride = 6LL * D * D;
     ea.tau = tau;
     ea.exact = exact ? 1 : 0;
     ea.status = status.as<int>();
@@ -178,6 +180,32 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     prof.begin(kKindEig, 0, &e);
     H2_HIP(h2k::launch_eig(ea, ncl, st));
     prof.end(e, kKindEig, 0);
+    // opt-in diagnostic dump of one level's eigen problems (H2MMP_DUMP_DIR)
+    if (const char* dir = getenv("H2MMP_DUMP_DIR")) {
+      if (D >= 96) {
+        H2_HIP(hipStreamSynchronize(st));
+        std::vector<double> g((size_t)ncl * D * D), u((size_t)ncl * D * D);
+        std::vector<int> rk(ncl), kk1(ncl * kstride + 1), kk2(ncl * kstride + 1, 0);
+        H2_HIP(hipMemcpy(g.data(), Gn.d(), g.size() * 8, hipMemcpyDeviceToHost));
+        H2_HIP(hipMemcpy(u.data(), Ug.d(), u.size() * 8, hipMemcpyDeviceToHost));
+        H2_HIP(hipMemcpy(rk.data(), rank.as<int>(), ncl * 4, hipMemcpyDeviceToHost));
+        H2_HIP(hipMemcpy(kk1.data(), k1, ((ncl - 1) * kstride + 1) * 4, hipMemcpyDeviceToHost));
+        if (k2) H2_HIP(hipMemcpy(kk2.data(), k2, ((ncl - 1) * kstride + 1) * 4, hipMemcpyDeviceToHost));
+        static int serial = 0;
+        const std::string base = std::string(dir) + "/eig_l" + std::to_string(l) + "_" +
+                                 std::to_string(serial++) + "_D" + std::to_string(D) + "_n" +
+                                 std::to_string(ncl) + "_h" + std::to_string(half);
+        FILE* f = fopen((base + ".bin").c_str(), "wb");
+        if (f) {
+          fwrite(g.data(), 8, g.size(), f);
+          fwrite(u.data(), 8, u.size(), f);
+          fwrite(rk.data(), 4, rk.size(), f);
+          for (int c2 = 0; c2 < ncl; ++c2) fwrite(&kk1[c2 * kstride], 4, 1, f);
+          for (int c2 = 0; c2 < ncl; ++c2) fwrite(&kk2[c2 * kstride], 4, 1, f);
+          fclose(f);
+        }
+      }
+    }
   };
   auto read_ranks = [&](int l, Buf& rr_, Buf& rc_) {
     const int ncl = 1 << l;
