@@ -161,6 +161,11 @@ typedef struct {
   double contraction_flops;
   double eig_ms;
   int64_t bytes_device;
+  /* per kernel class (with h2_set_profiling on): summed device ms and
+   * launches of the Gram-sum products and of all remaining batched products */
+  double gram_ms, other_ms;
+  int64_t eig_launches, gram_launches, other_launches;
+  double gram_flops, other_flops; /* executed (padded) flops of those launches */
 } h2_stats_t;
 h2_status h2_stats(h2_mat M, h2_stats_t* out);
 

@@ -55,7 +55,10 @@ class _Stats(C.Structure):
                 ("n_triples", C.c_int64), ("sparsity_constant", C.c_int64),
                 ("contraction_ms", C.c_double), ("contraction_launches", C.c_int64),
                 ("contraction_flops", C.c_double), ("eig_ms", C.c_double),
-                ("bytes_device", C.c_int64)]
+                ("bytes_device", C.c_int64), ("gram_ms", C.c_double), ("other_ms", C.c_double),
+                ("eig_launches", C.c_int64), ("gram_launches", C.c_int64),
+                ("other_launches", C.c_int64), ("gram_flops", C.c_double),
+                ("other_flops", C.c_double)]
 
 
 _lib = None
@@ -281,4 +284,7 @@ def stats(M):
                 n_triples=s.n_triples, sparsity_constant=s.sparsity_constant,
                 contraction_ms=s.contraction_ms, contraction_launches=s.contraction_launches,
                 contraction_flops=s.contraction_flops, eig_ms=s.eig_ms,
-                bytes_device=s.bytes_device)
+                bytes_device=s.bytes_device, gram_ms=s.gram_ms, other_ms=s.other_ms,
+                eig_launches=s.eig_launches, gram_launches=s.gram_launches,
+                other_launches=s.other_launches, gram_flops=s.gram_flops,
+                other_flops=s.other_flops)

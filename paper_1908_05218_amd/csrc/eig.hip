@@ -6,7 +6,8 @@
 //
 // One workgroup per cluster, FP64 throughout:
 //   1. gather the live rows/columns (the children's actual ranks) into a
-//      packed lower triangle in LDS (n <= 192: 148 KiB);
+//      packed lower triangle, in LDS for n <= 192 (148 KiB), else in the
+//      cluster's L2-resident scratch (n <= 256);
 //   2. Householder reduction to tridiagonal form in place, reflectors kept in
 //      the packed columns;
 //   3. all eigenvalues by Sturm-sequence bisection, one thread per eigenvalue;
@@ -224,8 +225,11 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p) {
     return;
   }
   const int np = n * (n + 1) / 2;
-  double* P = sm;
-  double* dd = P + np;
+  // packed triangle in LDS up to kEigLdsN, else in the cluster's scratch (L2)
+  const bool lds_p = n <= kEigLdsN;
+  double* S = p.scratch + (long long)c * p.sstride;
+  double* P = lds_p ? sm : S + 6LL * D * D;
+  double* dd = lds_p ? sm + np : sm;
   double* ee = dd + n;
   double* lam = ee + n;
   double* pv = lam + n;
@@ -357,7 +361,6 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p) {
   }
 
   // 5a. inverse iteration, thread m owns vector m; scratch interleaved by m
-  double* S = p.scratch + (long long)c * p.sstride;
   double* sd = S;
   double* sl = S + (long long)D * D;
   double* su = S + 2LL * D * D;
@@ -403,28 +406,28 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p) {
 
   // 6. back-transformation, one wave per vector, scatter to padded rows
   for (int m = wave; m < k; m += kEigWaves) {
-    double z[3];
+    double z[4];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < 4; ++s) {
       const int r = lane + 64 * s;
       z[s] = r < n ? Z[r * D + m] : 0.0;
     }
     for (int i = n - 3; i >= 0; --i) {
       double part = 0.0;
 #pragma unroll
-      for (int s = 0; s < 3; ++s) {
+      for (int s = 0; s < 4; ++s) {
         const int r = lane + 64 * s;
         if (r > i && r < n) part += P[pidx(r, i, n)] * z[s];
       }
       const double sum2 = 2.0 * wave_sum(part);
 #pragma unroll
-      for (int s = 0; s < 3; ++s) {
+      for (int s = 0; s < 4; ++s) {
         const int r = lane + 64 * s;
         if (r > i && r < n) z[s] -= sum2 * P[pidx(r, i, n)];
       }
     }
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < 4; ++s) {
       const int r = lane + 64 * s;
       if (r < n) {
         const int orow = r < k1 ? r : half + (r - k1);
@@ -435,14 +438,15 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p) {
   if (tid == 0) p.rank[c] = k;
 }
 
-static size_t eig_lds_bytes(int n) {
-  return sizeof(double) * ((size_t)n * (n + 1) / 2 + 5 * (size_t)n + kEigWaves);
+static size_t eig_lds_bytes(int D) {
+  const size_t nl = D < kEigLdsN ? D : kEigLdsN;
+  const size_t nv = D < kEigNmax ? D : kEigNmax;
+  return sizeof(double) * (nl * (nl + 1) / 2 + 5 * nv + kEigWaves);
 }
 
 hipError_t launch_eig(const EigArgs& a, int nclusters, hipStream_t s) {
   if (nclusters <= 0) return hipSuccess;
-  const int nmax = a.D < kEigNmax ? a.D : kEigNmax;
-  const size_t lds = eig_lds_bytes(nmax);
+  const size_t lds = eig_lds_bytes(a.D);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_eig,

@@ -78,7 +78,8 @@ struct EigArgs {
   int* status;  // [0] non-finite, [1] dimension over limit
 };
 
-constexpr int kEigNmax = 192;
+constexpr int kEigNmax = 256;  // largest Gram dimension
+constexpr int kEigLdsN = 192;  // largest dimension whose packed triangle stays in LDS
 
 template <typename T>
 hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s);

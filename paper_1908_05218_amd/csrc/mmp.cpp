@@ -159,7 +159,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     H2_HIP(h2k::launch_gram_norm(ga, ncl, st));
     Ug = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
     rank = Buf(ctx, (size_t)ncl * sizeof(int));
-    Buf scratch(ctx, (size_t)ncl * 6 * D * D * sizeof(double));
+    Buf scratch(ctx, (size_t)ncl * 7 * D * D * sizeof(double));
     h2k::EigArgs ea{};
     ea.G = Gn.d();
     ea.gstride = (long long)D * D;
@@ -172,7 +172,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     ea.kstride = kstride;
     ea.half = half;
     ea.scratch = scratch.d();
-    ea.sstride = 6LL * D * D;
+    ea.sstride = 7LL * D * D;
     ea.tau = tau;
     ea.exact = exact ? 1 : 0;
     ea.status = status.as<int>();
@@ -600,6 +600,13 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     S.contraction_launches = pl[kKindTriple];
     S.contraction_flops = pfl[kKindTriple];
     S.eig_ms = pms[kKindEig];
+    S.eig_launches = pl[kKindEig];
+    S.gram_ms = pms[kKindGram];
+    S.gram_launches = pl[kKindGram];
+    S.gram_flops = pfl[kKindGram];
+    S.other_ms = pms[kKindOther];
+    S.other_launches = pl[kKindOther];
+    S.other_flops = pfl[kKindOther];
   }
   *C_out = C.release();
   return H2_OK;
