@@ -67,75 +67,73 @@ __device__ __forceinline__ double start_vec(int r, int m) {
 }
 
 // Gaussian elimination with partial pivoting of (T - lambda I), T tridiagonal
-// (diagonal dd, off-diagonal ee); factors of vector m interleaved by m.
+// (diagonal dd, off-diagonal ee); factors of vector m interleaved by m.  The
+// running row is carried in registers, so the loop only stores.
 __device__ void tri_factor(const double* dd, const double* ee, int n, double lm, double tiny,
                            double* sd, double* sl, double* su, double* su2, double* spv, int D,
                            int m) {
-  for (int i = 0; i < n; ++i) {
-    sd[i * D + m] = dd[i] - lm;
-    spv[i * D + m] = 0.0;
-    if (i < n - 1) {
-      sl[i * D + m] = ee[i];
-      su[i * D + m] = ee[i];
-    }
-    if (i < n - 2) su2[i * D + m] = 0.0;
-  }
+  double di = dd[0] - lm;
+  double ui = n > 1 ? ee[0] : 0.0;
   for (int i = 0; i < n - 1; ++i) {
-    double di = sd[i * D + m];
-    const double li = sl[i * D + m];
+    const double li = ee[i];
+    const double dn = dd[i + 1] - lm;
+    const double un = i < n - 2 ? ee[i + 1] : 0.0;
     if (fabs(di) >= fabs(li)) {
-      if (fabs(di) < tiny) {
-        di = di < 0.0 ? -tiny : tiny;
-        sd[i * D + m] = di;
-      }
+      if (fabs(di) < tiny) di = di < 0.0 ? -tiny : tiny;
       const double fact = li / di;
+      sd[i * D + m] = di;
       sl[i * D + m] = fact;
-      sd[(i + 1) * D + m] -= fact * su[i * D + m];
+      su[i * D + m] = ui;
+      su2[i * D + m] = 0.0;
+      spv[i * D + m] = 0.0;
+      di = dn - fact * ui;
+      ui = un;
     } else {
       const double fact = di / li;
       sd[i * D + m] = li;
       sl[i * D + m] = fact;
-      const double temp = su[i * D + m];
-      const double dn = sd[(i + 1) * D + m];
       su[i * D + m] = dn;
-      sd[(i + 1) * D + m] = temp - fact * dn;
-      if (i < n - 2) {
-        const double un = su[(i + 1) * D + m];
-        su2[i * D + m] = un;
-        su[(i + 1) * D + m] = -fact * un;
-      }
+      su2[i * D + m] = un;
       spv[i * D + m] = 1.0;
+      di = ui - fact * dn;
+      ui = -fact * un;
     }
   }
-  if (fabs(sd[(n - 1) * D + m]) < tiny) sd[(n - 1) * D + m] = sd[(n - 1) * D + m] < 0.0 ? -tiny : tiny;
+  if (fabs(di) < tiny) di = di < 0.0 ? -tiny : tiny;
+  sd[(n - 1) * D + m] = di;
 }
 
-// Z[:, m] <- (T - lambda_m I)^{-1} Z[:, m] with the stored factors.
+// Z[:, m] <- (T - lambda_m I)^{-1} Z[:, m] with the stored factors; the
+// running entries are carried in registers.  Near-singular shifts make the
+// solution grow: the whole system is rescaled before it can overflow.
 __device__ void tri_solve(int n, const double* sd, const double* sl, const double* su,
                           const double* su2, const double* spv, int D, int m, double* Z) {
+  double zi = Z[m];
   for (int i = 0; i < n - 1; ++i) {
     const double f = sl[i * D + m];
+    const double zn = Z[(i + 1) * D + m];
     if (spv[i * D + m] == 0.0) {
-      Z[(i + 1) * D + m] -= f * Z[i * D + m];
+      Z[i * D + m] = zi;
+      zi = zn - f * zi;
     } else {
-      const double t0 = Z[i * D + m];
-      const double t1 = Z[(i + 1) * D + m];
-      Z[i * D + m] = t1;
-      Z[(i + 1) * D + m] = t0 - f * t1;
+      Z[i * D + m] = zn;
+      zi = zi - f * zn;
     }
   }
-  Z[(n - 1) * D + m] /= sd[(n - 1) * D + m];
-  if (n >= 2)
-    Z[(n - 2) * D + m] =
-        (Z[(n - 2) * D + m] - su[(n - 2) * D + m] * Z[(n - 1) * D + m]) / sd[(n - 2) * D + m];
-  for (int i = n - 3; i >= 0; --i) {
-    Z[i * D + m] = (Z[i * D + m] - su[i * D + m] * Z[(i + 1) * D + m] -
-                    su2[i * D + m] * Z[(i + 2) * D + m]) /
-                   sd[i * D + m];
-    // near-singular shifts make the solution grow: rescale the whole system
-    // (solved and unsolved parts alike) before it can overflow
-    if (fabs(Z[i * D + m]) > 1e150)
+  double x2 = 0.0;  // x_{i+2}
+  double x1 = zi / sd[(n - 1) * D + m];
+  Z[(n - 1) * D + m] = x1;
+  for (int i = n - 2; i >= 0; --i) {
+    const double xi = (Z[i * D + m] - su[i * D + m] * x1 - (i < n - 2 ? su2[i * D + m] * x2 : 0.0)) /
+                      sd[i * D + m];
+    x2 = x1;
+    x1 = xi;
+    Z[i * D + m] = xi;
+    if (fabs(xi) > 1e150) {
       for (int r = 0; r < n; ++r) Z[r * D + m] *= 1e-150;
+      x1 *= 1e-150;
+      x2 *= 1e-150;
+    }
   }
 }
 
@@ -184,10 +182,11 @@ __device__ void normalize_col(double* Z, int D, int n, int m, double* red) {
 
 // Z[:, m] -= sum_{q0 <= q < m} (Z[:,q] . Z[:,m]) Z[:,q] twice (classical Gram-Schmidt
 // with one re-orthogonalisation), then normalise (whole workgroup).
-__device__ void mgs_step(double* Z, int D, int n, int m, int q0, double* dots, double* red) {
+__device__ void mgs_step(double* Z, int D, int n, int m, int q0, double* dots, double* red,
+                         int passes = 2) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  for (int pass = 0; pass < 2 && m > q0; ++pass) {
+  for (int pass = 0; pass < passes && m > q0; ++pass) {
     for (int q = q0 + wave; q < m; q += kEigWaves) {
       double s = 0.0;
       for (int r = lane; r < n; r += 64) s += Z[r * D + q] * Z[r * D + m];
@@ -205,8 +204,9 @@ __device__ void mgs_step(double* Z, int D, int n, int m, int q0, double* dots, d
   normalize_col(Z, D, n, m, red);
 }
 
-__global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p) {
+__global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p0, EigArgs p1) {
   extern __shared__ double sm[];
+  const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p) {
   // iterations cannot separate them, so each further member restarts from a
   // fresh vector and alternates orthogonalisation against the earlier
   // members with solves (the cluster handling of classical inverse iteration)
-  const double delta = 1e-10 * bnd;
+  const double delta = 1e-12 * bnd;
   int c0 = 0;
   for (int m = 1; m < k; ++m) {
     if (lam[m - 1] - lam[m] > delta) {
@@ -401,8 +401,10 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p) {
     mgs_step(Z, D, n, m, c0, pv, red);
   }
 
-  // 5c. Gram-Schmidt (with re-orthogonalisation) over all kept vectors
-  for (int m = 0; m < k; ++m) mgs_step(Z, D, n, m, 0, pv, red);
+  // 5c. Gram-Schmidt with re-orthogonalisation over all kept vectors: a vector
+  // left with almost no component outside the earlier ones needs the second
+  // pass to come out orthogonal
+  for (int m = 0; m < k; ++m) mgs_step(Z, D, n, m, 0, pv, red, 2);
 
   // 6. back-transformation, one wave per vector, scatter to padded rows
   for (int m = wave; m < k; m += kEigWaves) {
@@ -444,9 +446,9 @@ static size_t eig_lds_bytes(int D) {
   return sizeof(double) * (nl * (nl + 1) / 2 + 5 * nv + kEigWaves);
 }
 
-hipError_t launch_eig(const EigArgs& a, int nclusters, hipStream_t s) {
+hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStream_t s) {
   if (nclusters <= 0) return hipSuccess;
-  const size_t lds = eig_lds_bytes(a.D);
+  const size_t lds = eig_lds_bytes(a.D > b.D ? a.D : b.D);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_eig,
@@ -455,7 +457,7 @@ hipError_t launch_eig(const EigArgs& a, int nclusters, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_eig, dim3(nclusters), dim3(kEigThreads), lds, s, a);
+  hipLaunchKernelGGL(k_eig, dim3(nclusters, 2), dim3(kEigThreads), lds, s, a, b);
   return hipGetLastError();
 }
 

@@ -86,7 +86,8 @@ hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_segsum(const SegsumArgs<T>& a, hipStream_t s);
 hipError_t launch_gram_norm(const GramNormArgs& a, int nclusters, hipStream_t s);
-hipError_t launch_eig(const EigArgs& a, int nclusters, hipStream_t s);
+// two problem sets (row and column bases of one level) in one launch
+hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStream_t s);
 hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);
 hipError_t launch_fill_f(float* p, float v, long long n, hipStream_t s);
 hipError_t launch_d2f(const double* in, float* out, long long n, hipStream_t s);

@@ -55,40 +55,51 @@ struct Mfma<float> {
   }
 };
 
-template <typename T>
+// One workgroup = 4 wave64 in a 2x2 grid computes a TM x TN output tile;
+// each wave holds (TM/32) x (TN/32) 16x16 MFMA accumulators.  Operands are
+// staged through LDS in k-chunks of 16 (plain and transposed operands both
+// load coalesced).
+template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
   typedef typename Mfma<T>::v4 v4;
+  constexpr int KC = 16;
+  constexpr int SM = TM / 32;  // 16-row subtiles per wave
+  constexpr int SN = TN / 32;
   const int ntile = p.tiles_m * p.tiles_n;
   const int o = blockIdx.x / ntile;
   const int tt = blockIdx.x - o * ntile;
   const int tm = tt % p.tiles_m;
   const int tn = tt / p.tiles_m;
-  __shared__ T As[16][33];
-  __shared__ T Bs[16][33];
+  __shared__ T As[KC][TM + 1];
+  __shared__ T Bs[KC][TN + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = (wave & 1) * 16;
-  const int wc = (wave >> 1) * 16;
-  v4 acc = {0, 0, 0, 0};
+  const int wr = (wave & 1) * (TM / 2);
+  const int wc = (wave >> 1) * (TN / 2);
+  v4 acc[SM][SN];
+#pragma unroll
+  for (int a = 0; a < SM; ++a)
+#pragma unroll
+    for (int b = 0; b < SN; ++b) acc[a][b] = v4{0, 0, 0, 0};
   const int s0 = p.seg[o];
   const int s1 = p.seg[o + 1];
-  const int row0 = tm * 32;
-  const int col0 = tn * 32;
+  const int row0 = tm * TM;
+  const int col0 = tn * TN;
+  const int lda = p.A.ld;
+  const int ldb = p.B.ld;
   for (int t = s0; t < s1; ++t) {
     int sa, sb;
     const long long oa = opnd_off(p.A, p.a_idx[t], sa);
     const long long ob = opnd_off(p.B, p.b_idx[t], sb);
     const T* Ab = (const T*)p.A.base[sa] + oa;
     const T* Bb = (const T*)p.B.base[sb] + ob;
-    const int lda = p.A.ld;
-    const int ldb = p.B.ld;
-    for (int kk = 0; kk < p.k; kk += 16) {
+    for (int kk = 0; kk < p.k; kk += KC) {
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
+      for (int r = 0; r < (TM * KC) / 256; ++r) {
         const int e = tid + r * 256;
         int i, q;
-        if (!p.transA) { i = e & 31; q = e >> 5; } else { q = e & 15; i = e >> 4; }
+        if (!p.transA) { i = e % TM; q = e / TM; } else { q = e % KC; i = e / KC; }
         const int gi = row0 + i;
         T v = 0;
         if (gi < p.m)
@@ -96,10 +107,10 @@ __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
         As[q][i] = v;
       }
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
+      for (int r = 0; r < (TN * KC) / 256; ++r) {
         const int e = tid + r * 256;
         int j, q;
-        if (!p.transB) { q = e & 15; j = e >> 4; } else { j = e & 31; q = e >> 5; }
+        if (!p.transB) { q = e % KC; j = e / KC; } else { j = e % TN; q = e / TN; }
         const int gj = col0 + j;
         T v = 0;
         if (gj < p.n)
@@ -108,27 +119,39 @@ __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
       }
       __syncthreads();
 #pragma unroll
-      for (int q4 = 0; q4 < 4; ++q4) {
-        const T a = As[q4 * 4 + (lane >> 4)][wr + (lane & 15)];
-        const T b = Bs[q4 * 4 + (lane >> 4)][wc + (lane & 15)];
-        acc = Mfma<T>::op(a, b, acc);
+      for (int q4 = 0; q4 < KC / 4; ++q4) {
+        T av[SM], bv[SN];
+#pragma unroll
+        for (int a = 0; a < SM; ++a) av[a] = As[q4 * 4 + (lane >> 4)][wr + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < SN; ++b) bv[b] = Bs[q4 * 4 + (lane >> 4)][wc + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < SM; ++a)
+#pragma unroll
+          for (int b = 0; b < SN; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
       }
       __syncthreads();
     }
   }
-  T* Cb = p.C + ((long long)(p.out_idx[o] >> 3) * p.cstride + ((p.out_idx[o] & 1) ? p.csub_r : 0LL) +
-                 ((p.out_idx[o] & 2) ? p.csub_c : 0LL));
-  const int gj = col0 + wc + (lane & 15);
+  const int ov = p.out_idx[o];
+  T* Cb = p.C + ((long long)(ov >> 3) * p.cstride + ((ov & 1) ? p.csub_r : 0LL) +
+                 ((ov & 2) ? p.csub_c : 0LL));
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int gi = row0 + wr + Mfma<T>::row(lane, v);
-    if (gi < p.m && gj < p.n) {
-      T* c = Cb + gi + (long long)gj * p.ldc;
-      T val = p.alpha * acc[v];
-      if (p.beta != (T)0) val += p.beta * (*c);
-      *c = val;
+  for (int a = 0; a < SM; ++a)
+#pragma unroll
+    for (int b = 0; b < SN; ++b) {
+      const int gj = col0 + wc + b * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = row0 + wr + a * 16 + Mfma<T>::row(lane, v);
+        if (gi < p.m && gj < p.n) {
+          T* c = Cb + gi + (long long)gj * p.ldc;
+          T val = p.alpha * acc[a][b][v];
+          if (p.beta != (T)0) val += p.beta * (*c);
+          *c = val;
+        }
+      }
     }
-  }
 }
 
 template <typename T>
@@ -236,15 +259,26 @@ __global__ void k_scatter_rows(const double* in, double* y, const long long* per
 // ---------------------------------------------------------------- launches
 static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
-template <typename T>
-hipError_t launch_bgemm(const BgemmArgs<T>& a0, hipStream_t s) {
-  if (a0.nout <= 0) return hipSuccess;
-  BgemmArgs<T> a = a0;
-  a.tiles_m = cdiv(a.m, 32);
-  a.tiles_n = cdiv(a.n, 32);
+template <typename T, int TM, int TN>
+static hipError_t launch_tile(BgemmArgs<T> a, hipStream_t s) {
+  a.tiles_m = cdiv(a.m, TM);
+  a.tiles_n = cdiv(a.n, TN);
   const long long grid = (long long)a.nout * a.tiles_m * a.tiles_n;
-  hipLaunchKernelGGL(k_bgemm<T>, dim3((unsigned)grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_bgemm<T, TM, TN>), dim3((unsigned)grid), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+// Workgroup tile: 96x96 when the whole output fits one, otherwise 32 or 64
+// per side.
+template <typename T>
+hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s) {
+  if (a.nout <= 0) return hipSuccess;
+  const int mx = a.m > a.n ? a.m : a.n;
+  if (mx > 64 && a.m <= 96 && a.n <= 96) return launch_tile<T, 96, 96>(a, s);
+  if (a.m <= 32 && a.n <= 32) return launch_tile<T, 32, 32>(a, s);
+  if (a.m <= 32) return launch_tile<T, 32, 64>(a, s);
+  if (a.n <= 32) return launch_tile<T, 64, 32>(a, s);
+  return launch_tile<T, 64, 64>(a, s);
 }
 
 template <typename T>

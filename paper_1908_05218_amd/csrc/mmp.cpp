@@ -145,67 +145,51 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
          (long long)rcA[l] * rrB[l], rcA[l], 0, 0, 1.0, 0.0);
   }
 
-  // truncated eigen-decomposition of a level's normalised Grams
-  auto eig_level = [&](int l, int D, Buf G[3], Buf& Ug, Buf& rank, const int* k1, const int* k2,
-                       int kstride, int half) {
+  // truncated eigen-decompositions of a level's normalised row and column
+  // Grams, both sets in one launch
+  auto eig_level = [&](int l, int D, Buf Gr[3], Buf Gc[3], Buf& Ur_, Buf& Uc_, Buf& rank_r_,
+                       Buf& rank_c_, const int* k1r, const int* k2r, const int* k1c,
+                       const int* k2c, int kstride, int half) {
     const int ncl = 1 << l;
-    Buf Gn(ctx, (size_t)ncl * D * D * sizeof(double));
-    h2k::GramNormArgs ga{};
-    for (int c = 0; c < 3; ++c) ga.G[c] = G[c].d();
-    ga.stride = (long long)D * D;
-    ga.D = D;
-    ga.out = Gn.d();
-    ga.status = status.as<int>();
-    H2_HIP(h2k::launch_gram_norm(ga, ncl, st));
-    Ug = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
-    rank = Buf(ctx, (size_t)ncl * sizeof(int));
-    Buf scratch(ctx, (size_t)ncl * 7 * D * D * sizeof(double));
-    h2k::EigArgs ea{};
-    ea.G = Gn.d();
-    ea.gstride = (long long)D * D;
-    ea.D = D;
-    ea.U = Ug.d();
-    ea.ustride = (long long)D * D;
-    ea.rank = rank.as<int>();
-    ea.k1 = k1;
-    ea.k2 = k2;
-    ea.kstride = kstride;
-    ea.half = half;
-    ea.scratch = scratch.d();
-    ea.sstride = 7LL * D * D;
-    ea.tau = tau;
-    ea.exact = exact ? 1 : 0;
-    ea.status = status.as<int>();
+    Buf Gnr(ctx, (size_t)ncl * D * D * sizeof(double)), Gnc(ctx, (size_t)ncl * D * D * sizeof(double));
+    for (int side = 0; side < 2; ++side) {
+      h2k::GramNormArgs ga{};
+      for (int c = 0; c < 3; ++c) ga.G[c] = (side ? Gc : Gr)[c].d();
+      ga.stride = (long long)D * D;
+      ga.D = D;
+      ga.out = (side ? Gnc : Gnr).d();
+      ga.status = status.as<int>();
+      H2_HIP(h2k::launch_gram_norm(ga, ncl, st));
+    }
+    Ur_ = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
+    Uc_ = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
+    rank_r_ = Buf(ctx, (size_t)ncl * sizeof(int));
+    rank_c_ = Buf(ctx, (size_t)ncl * sizeof(int));
+    Buf scratch(ctx, (size_t)2 * ncl * 7 * D * D * sizeof(double));
+    h2k::EigArgs ea[2];
+    for (int side = 0; side < 2; ++side) {
+      h2k::EigArgs& e = ea[side];
+      e = h2k::EigArgs{};
+      e.G = (side ? Gnc : Gnr).d();
+      e.gstride = (long long)D * D;
+      e.D = D;
+      e.U = (side ? Uc_ : Ur_).d();
+      e.ustride = (long long)D * D;
+      e.rank = (side ? rank_c_ : rank_r_).as<int>();
+      e.k1 = side ? k1c : k1r;
+      e.k2 = side ? k2c : k2r;
+      e.kstride = kstride;
+      e.half = half;
+      e.scratch = scratch.d() + (size_t)side * ncl * 7 * D * D;
+      e.sstride = 7LL * D * D;
+      e.tau = tau;
+      e.exact = exact ? 1 : 0;
+      e.status = status.as<int>();
+    }
     hipEvent_t e = nullptr;
     prof.begin(kKindEig, 0, &e);
-    H2_HIP(h2k::launch_eig(ea, ncl, st));
+    H2_HIP(h2k::launch_eig(ea[0], ea[1], ncl, st));
     prof.end(e, kKindEig, 0);
-    // opt-in diagnostic dump of one level's eigen problems (H2MMP_DUMP_DIR)
-    if (const char* dir = getenv("H2MMP_DUMP_DIR")) {
-      if (D >= 96) {
-        H2_HIP(hipStreamSynchronize(st));
-        std::vector<double> g((size_t)ncl * D * D), u((size_t)ncl * D * D);
-        std::vector<int> rk(ncl), kk1(ncl * kstride + 1), kk2(ncl * kstride + 1, 0);
-        H2_HIP(hipMemcpy(g.data(), Gn.d(), g.size() * 8, hipMemcpyDeviceToHost));
-        H2_HIP(hipMemcpy(u.data(), Ug.d(), u.size() * 8, hipMemcpyDeviceToHost));
-        H2_HIP(hipMemcpy(rk.data(), rank.as<int>(), ncl * 4, hipMemcpyDeviceToHost));
-        H2_HIP(hipMemcpy(kk1.data(), k1, ((ncl - 1) * kstride + 1) * 4, hipMemcpyDeviceToHost));
-        if (k2) H2_HIP(hipMemcpy(kk2.data(), k2, ((ncl - 1) * kstride + 1) * 4, hipMemcpyDeviceToHost));
-        static int serial = 0;
-        const std::string base = std::string(dir) + "/eig_l" + std::to_string(l) + "_" +
-                                 std::to_string(serial++) + "_D" + std::to_string(D) + "_n" +
-                                 std::to_string(ncl) + "_h" + std::to_string(half);
-        FILE* f = fopen((base + ".bin").c_str(), "wb");
-        if (f) {
-          fwrite(g.data(), 8, g.size(), f);
-          fwrite(u.data(), 8, u.size(), f);
-          fwrite(rk.data(), 4, rk.size(), f);
-          for (int c2 = 0; c2 < ncl; ++c2) fwrite(&kk1[c2 * kstride], 4, 1, f);
-          for (int c2 = 0; c2 < ncl; ++c2) fwrite(&kk2[c2 * kstride], 4, 1, f);
-          fclose(f);
-        }
-      }
-    }
   };
   auto read_ranks = [&](int l, Buf& rr_, Buf& rc_) {
     const int ncl = 1 << l;
@@ -281,8 +265,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       gemm(st, pp, kKindGram, dl(LP.G3c), np, np, rcB[L], Op{B->W.d(), nullptr, B->W_stride, 0, np},
            false, Op{B->W.d(), nullptr, B->W_stride, 0, np}, true, Gc[2].d(), nn2, np, 0, 0, 1, 0);
     }
-    eig_level(L, np, G, Ur_L, rank_r[L], leaf_sizes.as<int>(), nullptr, 1, np);
-    eig_level(L, np, Gc, Uc_L, rank_c[L], leaf_sizes.as<int>(), nullptr, 1, np);
+    eig_level(L, np, G, Gc, Ur_L, Uc_L, rank_r[L], rank_c[L], leaf_sizes.as<int>(), nullptr,
+              leaf_sizes.as<int>(), nullptr, 1, np);
   }
   c = read_ranks(L, rank_r[L], rank_c[L]);
   cpad[L] = c;
@@ -423,8 +407,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     gemm(st, pp, kKindGram, dl(Q.G3c), K, K, rcB[l], Op{Qm.d(), nullptr, qs, 0, K}, false,
          Op{Qm.d(), nullptr, qs, 0, K}, true, Gc[2].d(), K2, K, 0, 0, 1, 0);
     // new transfer matrices
-    eig_level(l, K, G, Ur[l], rank_r[l], rank_r[ch].as<int>(), rank_r[ch].as<int>() + 1, 2, cc);
-    eig_level(l, K, Gc, Uc[l], rank_c[l], rank_c[ch].as<int>(), rank_c[ch].as<int>() + 1, 2, cc);
+    eig_level(l, K, G, Gc, Ur[l], Uc[l], rank_r[l], rank_c[l], rank_r[ch].as<int>(),
+              rank_r[ch].as<int>() + 1, rank_c[ch].as<int>(), rank_c[ch].as<int>() + 1, 2, cc);
     for (int k = 0; k < 3; ++k) {
       G[k].reset();
       Gc[k].reset();
