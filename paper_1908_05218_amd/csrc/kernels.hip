@@ -56,22 +56,26 @@ struct Mfma<float> {
 };
 
 // One workgroup = 4 wave64 in a 2x2 grid computes a TM x TN output tile;
-// each wave holds (TM/32) x (TN/32) 16x16 MFMA accumulators.  Operands are
-// staged through LDS in k-chunks of 16 (plain and transposed operands both
-// load coalesced).
+// each wave holds (TM/32) x (TN/32) 16x16 MFMA accumulators.  The segment's
+// (task, k-chunk) steps are software-pipelined: the global loads of step s+1
+// are issued into registers before the MFMAs of step s run from one LDS
+// buffer, then stored into the other buffer (one barrier per step).  Plain
+// and transposed operands both load coalesced.
 template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KC = 16;
   constexpr int SM = TM / 32;  // 16-row subtiles per wave
   constexpr int SN = TN / 32;
+  constexpr int LA = (TM * KC) / 256;  // A elements per thread per step
+  constexpr int LB = (TN * KC) / 256;
   const int ntile = p.tiles_m * p.tiles_n;
   const int o = blockIdx.x / ntile;
   const int tt = blockIdx.x - o * ntile;
   const int tm = tt % p.tiles_m;
   const int tn = tt / p.tiles_m;
-  __shared__ T As[KC][TM + 1];
-  __shared__ T Bs[KC][TN + 1];
+  __shared__ T As[2][KC][TM + 1];
+  __shared__ T Bs[2][KC][TN + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -83,55 +87,77 @@ __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
 #pragma unroll
     for (int b = 0; b < SN; ++b) acc[a][b] = v4{0, 0, 0, 0};
   const int s0 = p.seg[o];
-  const int s1 = p.seg[o + 1];
+  const int nk = p.k / KC;
+  const int nsteps = (p.seg[o + 1] - s0) * nk;
   const int row0 = tm * TM;
   const int col0 = tn * TN;
   const int lda = p.A.ld;
   const int ldb = p.B.ld;
-  for (int t = s0; t < s1; ++t) {
+  // per-thread element coordinates within a step's A and B tiles
+  int ai[LA], aq[LA], bj[LB], bq[LB];
+#pragma unroll
+  for (int r = 0; r < LA; ++r) {
+    const int e = tid + r * 256;
+    if (!p.transA) { ai[r] = e % TM; aq[r] = e / TM; } else { aq[r] = e % KC; ai[r] = e / KC; }
+  }
+#pragma unroll
+  for (int r = 0; r < LB; ++r) {
+    const int e = tid + r * 256;
+    if (!p.transB) { bq[r] = e % KC; bj[r] = e / KC; } else { bj[r] = e % TN; bq[r] = e / TN; }
+  }
+  T ra[LA], rb[LB];
+  auto load_step = [&](int st) {
+    const int t = s0 + st / nk;
+    const int kk = (st % nk) * KC;
     int sa, sb;
     const long long oa = opnd_off(p.A, p.a_idx[t], sa);
     const long long ob = opnd_off(p.B, p.b_idx[t], sb);
     const T* Ab = (const T*)p.A.base[sa] + oa;
     const T* Bb = (const T*)p.B.base[sb] + ob;
-    for (int kk = 0; kk < p.k; kk += KC) {
 #pragma unroll
-      for (int r = 0; r < (TM * KC) / 256; ++r) {
-        const int e = tid + r * 256;
-        int i, q;
-        if (!p.transA) { i = e % TM; q = e / TM; } else { q = e % KC; i = e / KC; }
-        const int gi = row0 + i;
-        T v = 0;
-        if (gi < p.m)
-          v = p.transA ? Ab[(kk + q) + (long long)gi * lda] : Ab[gi + (long long)(kk + q) * lda];
-        As[q][i] = v;
-      }
-#pragma unroll
-      for (int r = 0; r < (TN * KC) / 256; ++r) {
-        const int e = tid + r * 256;
-        int j, q;
-        if (!p.transB) { q = e % KC; j = e / KC; } else { j = e % TN; q = e / TN; }
-        const int gj = col0 + j;
-        T v = 0;
-        if (gj < p.n)
-          v = p.transB ? Bb[gj + (long long)(kk + q) * ldb] : Bb[(kk + q) + (long long)gj * ldb];
-        Bs[q][j] = v;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q4 = 0; q4 < KC / 4; ++q4) {
-        T av[SM], bv[SN];
-#pragma unroll
-        for (int a = 0; a < SM; ++a) av[a] = As[q4 * 4 + (lane >> 4)][wr + a * 16 + (lane & 15)];
-#pragma unroll
-        for (int b = 0; b < SN; ++b) bv[b] = Bs[q4 * 4 + (lane >> 4)][wc + b * 16 + (lane & 15)];
-#pragma unroll
-        for (int a = 0; a < SM; ++a)
-#pragma unroll
-          for (int b = 0; b < SN; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
-      }
-      __syncthreads();
+    for (int r = 0; r < LA; ++r) {
+      const int gi = row0 + ai[r];
+      ra[r] = gi < p.m ? (p.transA ? Ab[(kk + aq[r]) + (long long)gi * lda]
+                                   : Ab[gi + (long long)(kk + aq[r]) * lda])
+                       : (T)0;
     }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int gj = col0 + bj[r];
+      rb[r] = gj < p.n ? (p.transB ? Bb[gj + (long long)(kk + bq[r]) * ldb]
+                                   : Bb[(kk + bq[r]) + (long long)gj * ldb])
+                       : (T)0;
+    }
+  };
+  auto store_step = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) As[buf][aq[r]][ai[r]] = ra[r];
+#pragma unroll
+    for (int r = 0; r < LB; ++r) Bs[buf][bq[r]][bj[r]] = rb[r];
+  };
+  if (nsteps > 0) {
+    load_step(0);
+    store_step(0);
+    __syncthreads();
+  }
+  for (int st = 0; st < nsteps; ++st) {
+    const int buf = st & 1;
+    const bool more = st + 1 < nsteps;
+    if (more) load_step(st + 1);
+#pragma unroll
+    for (int q4 = 0; q4 < KC / 4; ++q4) {
+      T av[SM], bv[SN];
+#pragma unroll
+      for (int a = 0; a < SM; ++a) av[a] = As[buf][q4 * 4 + (lane >> 4)][wr + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < SN; ++b) bv[b] = Bs[buf][q4 * 4 + (lane >> 4)][wc + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < SM; ++a)
+#pragma unroll
+        for (int b = 0; b < SN; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
+    }
+    if (more) store_step(buf ^ 1);
+    __syncthreads();
   }
   const int ov = p.out_idx[o];
   T* Cb = p.C + ((long long)(ov >> 3) * p.cstride + ((ov & 1) ? p.csub_r : 0LL) +
