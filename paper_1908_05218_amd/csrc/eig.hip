@@ -1,43 +1,76 @@
 // Batched truncated eigen-decomposition of the summed normalised Gram
-// matrices that fix each new cluster basis of C (Section III-C and IV-C of
-// Ma & Jiao: "perform an SVD on G and keep the singular vectors whose
-// normalised singular values exceed eps"; G is Hermitian positive
-// semi-definite, so its SVD is its eigen-decomposition).
+// matrices that fix each new cluster basis of C (Sections III-C and IV-C of
+// Ma & Jiao).  The Gram matrix is symmetric positive semi-definite, so the
+// left singular vectors the method keeps are its leading eigenvectors; the
+// kept count follows from the truncation threshold tau * lambda_1.
 //
-// One workgroup per cluster, FP64 throughout:
+// One workgroup per cluster (NT = 64..512 lanes chosen from the padded
+// dimension), FP64 throughout:
 //   1. gather the live rows/columns (the children's actual ranks) into a
-//      packed lower triangle, in LDS for n <= 192 (148 KiB), else in the
-//      cluster's L2-resident scratch (n <= 256);
-//   2. Householder reduction to tridiagonal form in place, reflectors kept in
-//      the packed columns;
-//   3. all eigenvalues by Sturm-sequence bisection, one thread per eigenvalue;
-//   4. kept count from the threshold tau * lambda_1;
-//   5. eigenvectors of the tridiagonal matrix by two steps of inverse
-//      iteration (Gaussian elimination with partial pivoting), one thread per
-//      kept vector, then two passes of modified Gram-Schmidt in descending
-//      eigenvalue order;
-//   6. back-transformation by the reflectors, one wave per vector, and scatter
-//      to the padded row layout.
+//      packed lower triangle: in LDS for n <= kEigLdsN, else in the cluster's
+//      scratch;
+//   2. Householder reduction to tridiagonal form.  Per step the symmetric
+//      product p = 2 A u is split over waves (each row's column range in
+//      contiguous chunks, loads pipelined); the rank-2 update runs lanes over
+//      rows of one column at a time.  Finished reflectors go to the cluster's
+//      scratch, which frees the LDS for the eigenvectors;
+//   3. lambda_1 by block-wide multisection of Sturm counts, the kept count k
+//      by one Sturm count at the threshold, then the k leading eigenvalues
+//      by grouped multisection (G lanes and two interleaved Sturm sequences
+//      per eigenvalue);
+//   4. eigenvectors of the tridiagonal matrix by two steps of inverse
+//      iteration per lane (Gaussian elimination with partial pivoting fused
+//      with the forward sweep of the right-hand side); eigenvalues closer than
+//      1e-12 ||T|| are handled as clusters (fresh start, orthogonalisation
+//      against the earlier members between solves);
+//   5. classical Gram-Schmidt with one re-orthogonalisation over all kept
+//      vectors, in descending eigenvalue order;
+//   6. back-transformation by the reflectors, one wave per four vectors held
+//      in registers, and scatter to the padded row layout.
+// Wave reductions use DPP row operations and lane reads, not LDS permutes.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include "kernels.h"
 
 namespace h2k {
+namespace {
 
-constexpr int kEigThreads = 512;
-constexpr int kEigWaves = kEigThreads / 64;
+constexpr int kLdsBytes = 163840;  // LDS per workgroup on gfx950
+constexpr int kVB = 4;             // vectors per wave in the back-transformation
 
-__device__ __forceinline__ int pidx(int i, int j, int n) {  // i >= j
-  return j * n - (j * (j - 1)) / 2 + (i - j);
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xF, 0xF, false);
 }
 
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave; every lane gets the same value.  Every lane
+// of the wave must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror: each row of 16 lanes now holds its sum
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Maximum (MAX) or minimum over aligned groups of G in {1, 2, 4, 8} lanes.
+template <bool MAX>
+__device__ __forceinline__ double group_red(double v, int G) {
+  if (G >= 2) v = MAX ? fmax(v, dpp<0xB1>(v)) : fmin(v, dpp<0xB1>(v));
+  if (G >= 4) v = MAX ? fmax(v, dpp<0x4E>(v)) : fmin(v, dpp<0x4E>(v));
+  if (G >= 8) v = MAX ? fmax(v, dpp<0x141>(v)) : fmin(v, dpp<0x141>(v));
   return v;
 }
 
+template <int NT>
 __device__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   __syncthreads();
@@ -45,166 +78,192 @@ __device__ double block_sum(double v, double* red) {
   __syncthreads();
   double s = 0;
 #pragma unroll
-  for (int w = 0; w < kEigWaves; ++w) s += red[w];
+  for (int w = 0; w < NT / 64; ++w) s += red[w];
   return s;
 }
 
-__device__ __forceinline__ int sturm_count(const double* dd, const double* e2, int n, double x,
-                                           double pivmin) {
-  double q = dd[0] - x;
+// start of column j of a packed lower triangle of order n
+__device__ __forceinline__ int cs(int j, int n) { return j * n - (j * (j - 1)) / 2; }
+
+// number of eigenvalues below xa and below xb (Sturm counts, two sequences
+// interleaved)
+__device__ __forceinline__ void sturm2(const double* d, const double* e2, int n, double xa,
+                                       double xb, double pivmin, int& ca, int& cb) {
+  double qa = d[0] - xa, qb = d[0] - xb;
+  int na = qa < 0.0, nb = qb < 0.0;
+  for (int i = 1; i < n; ++i) {
+    const double di = d[i], ei = e2[i - 1];
+    if (fabs(qa) < pivmin) qa = -pivmin;
+    if (fabs(qb) < pivmin) qb = -pivmin;
+    qa = (di - xa) - ei / qa;
+    qb = (di - xb) - ei / qb;
+    na += qa < 0.0;
+    nb += qb < 0.0;
+  }
+  ca = na;
+  cb = nb;
+}
+
+__device__ __forceinline__ int sturm1(const double* d, const double* e2, int n, double x,
+                                      double pivmin) {
+  double q = d[0] - x;
   int cnt = q < 0.0;
   for (int i = 1; i < n; ++i) {
     if (fabs(q) < pivmin) q = -pivmin;
-    q = dd[i] - x - e2[i - 1] / q;
+    q = (d[i] - x) - e2[i - 1] / q;
     cnt += q < 0.0;
   }
   return cnt;
 }
 
-
 __device__ __forceinline__ double start_vec(int r, int m) {
   return cos(0.7548776662 * r + 0.5698402909 * m) + 0.1;
 }
 
-// Gaussian elimination with partial pivoting of (T - lambda I), T tridiagonal
-// (diagonal dd, off-diagonal ee); factors of vector m interleaved by m.  The
-// running row is carried in registers, so the loop only stores.
-__device__ void tri_factor(const double* dd, const double* ee, int n, double lm, double tiny,
-                           double* sd, double* sl, double* su, double* su2, double* spv, int D,
-                           int m) {
+// Per-lane solve (T - lm I) x = b for the tridiagonal T = (dd, ee): Gaussian
+// elimination with partial pivoting, the factor and the right-hand side swept
+// together; the factor rows (reciprocal pivot, two superdiagonals) and the
+// swept right-hand side are kept interleaved by m in F[0..3] (stride fs) for
+// the backward sweep.  b is the start vector of seed `seed` (fresh) or zm
+// itself; x overwrites zm and is normalised.  Near-singular pivots are
+// clamped to +-tiny; a growing solution is rescaled before it can overflow.
+__device__ void invit_solve(const double* dd, const double* ee, int n, double lm, double tiny,
+                            double* F0, double* F1, double* F2, double* F3, int fs, int m,
+                            double* zm, bool fresh, int seed) {
   double di = dd[0] - lm;
   double ui = n > 1 ? ee[0] : 0.0;
+  double bi = fresh ? start_vec(0, seed) : zm[0];
   for (int i = 0; i < n - 1; ++i) {
     const double li = ee[i];
     const double dn = dd[i + 1] - lm;
     const double un = i < n - 2 ? ee[i + 1] : 0.0;
+    const double bn = fresh ? start_vec(i + 1, seed) : zm[i + 1];
+    double piv, u1, u2, y;
     if (fabs(di) >= fabs(li)) {
       if (fabs(di) < tiny) di = di < 0.0 ? -tiny : tiny;
-      const double fact = li / di;
-      sd[i * D + m] = di;
-      sl[i * D + m] = fact;
-      su[i * D + m] = ui;
-      su2[i * D + m] = 0.0;
-      spv[i * D + m] = 0.0;
-      di = dn - fact * ui;
+      piv = di;
+      u1 = ui;
+      u2 = 0.0;
+      y = bi;
+      const double f = li / di;
+      di = dn - f * ui;
       ui = un;
+      bi = bn - f * bi;
     } else {
-      const double fact = di / li;
-      sd[i * D + m] = li;
-      sl[i * D + m] = fact;
-      su[i * D + m] = dn;
-      su2[i * D + m] = un;
-      spv[i * D + m] = 1.0;
-      di = ui - fact * dn;
-      ui = -fact * un;
+      piv = li;
+      u1 = dn;
+      u2 = un;
+      y = bn;
+      const double f = di / li;
+      di = ui - f * dn;
+      ui = -f * un;
+      bi = bi - f * bn;
     }
+    const long long o = (long long)i * fs + m;
+    F0[o] = 1.0 / piv;
+    F1[o] = u1;
+    F2[o] = u2;
+    F3[o] = y;
   }
   if (fabs(di) < tiny) di = di < 0.0 ? -tiny : tiny;
-  sd[(n - 1) * D + m] = di;
-}
-
-// Z[:, m] <- (T - lambda_m I)^{-1} Z[:, m] with the stored factors; the
-// running entries are carried in registers.  Near-singular shifts make the
-// solution grow: the whole system is rescaled before it can overflow.
-__device__ void tri_solve(int n, const double* sd, const double* sl, const double* su,
-                          const double* su2, const double* spv, int D, int m, double* Z) {
-  double zi = Z[m];
-  for (int i = 0; i < n - 1; ++i) {
-    const double f = sl[i * D + m];
-    const double zn = Z[(i + 1) * D + m];
-    if (spv[i * D + m] == 0.0) {
-      Z[i * D + m] = zi;
-      zi = zn - f * zi;
-    } else {
-      Z[i * D + m] = zn;
-      zi = zi - f * zn;
+  double x1 = bi / di, x2 = 0.0;
+  zm[n - 1] = x1;
+  double amax = fabs(x1);
+  // backward sweep; the factor rows are fetched eight at a time ahead of use
+  int i = n - 2;
+  while (i >= 0) {
+    constexpr int C = 8;
+    double r0[C], r1[C], r2[C], r3[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      const int ii = i - t;
+      const long long o = (long long)(ii < 0 ? 0 : ii) * fs + m;
+      r0[t] = F0[o];
+      r1[t] = F1[o];
+      r2[t] = F2[o];
+      r3[t] = F3[o];
     }
-  }
-  double x2 = 0.0;  // x_{i+2}
-  double x1 = zi / sd[(n - 1) * D + m];
-  Z[(n - 1) * D + m] = x1;
-  for (int i = n - 2; i >= 0; --i) {
-    const double xi = (Z[i * D + m] - su[i * D + m] * x1 - (i < n - 2 ? su2[i * D + m] * x2 : 0.0)) /
-                      sd[i * D + m];
-    x2 = x1;
-    x1 = xi;
-    Z[i * D + m] = xi;
-    if (fabs(xi) > 1e150) {
-      for (int r = 0; r < n; ++r) Z[r * D + m] *= 1e-150;
-      x1 *= 1e-150;
-      x2 *= 1e-150;
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      const int ii = i - t;
+      if (ii >= 0) {
+        const double xi = (r3[t] - r1[t] * x1 - r2[t] * x2) * r0[t];
+        x2 = x1;
+        x1 = xi;
+        zm[ii] = xi;
+        amax = fmax(amax, fabs(xi));
+        if (fabs(xi) > 1e150) {
+          for (int r = ii; r < n; ++r) zm[r] *= 1e-150;
+          for (int r = 0; r < ii; ++r) F3[(long long)r * fs + m] *= 1e-150;
+          for (int u = t + 1; u < C; ++u) r3[u] *= 1e-150;
+          x1 *= 1e-150;
+          x2 *= 1e-150;
+          amax *= 1e-150;
+        }
+      }
     }
+    i -= C;
   }
-}
-
-// Scale-safe normalisation of column m by one thread.
-__device__ void normalize_serial(double* Z, int D, int n, int m) {
-  double amax = 0.0;
-  for (int r = 0; r < n; ++r) amax = fmax(amax, fabs(Z[r * D + m]));
   if (!(amax > 0.0) || !(amax < 1e308)) return;
   double s = 0.0;
   for (int r = 0; r < n; ++r) {
-    const double v = Z[r * D + m] / amax;
+    const double v = zm[r] / amax;
     s += v * v;
   }
   const double inv = 1.0 / (amax * sqrt(s));
-  for (int r = 0; r < n; ++r) Z[r * D + m] *= inv;
+  for (int r = 0; r < n; ++r) zm[r] *= inv;
 }
 
-__device__ double block_max(double v, double* red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0;
-#pragma unroll
-  for (int w = 0; w < kEigWaves; ++w) s = fmax(s, red[w]);
-  return s;
-}
-
-// Scale-safe normalisation of column m by the whole workgroup.
-__device__ void normalize_col(double* Z, int D, int n, int m, double* red) {
-  double amax = 0.0;
-  for (int r = threadIdx.x; r < n; r += kEigThreads) amax = fmax(amax, fabs(Z[r * D + m]));
-  amax = block_max(amax, red);
-  double part = 0.0;
-  if (amax > 0.0 && amax < 1e308)
-    for (int r = threadIdx.x; r < n; r += kEigThreads) {
-      const double v = Z[r * D + m] / amax;
-      part += v * v;
-    }
-  const double nrm = block_sum(part, red);
-  const double inv = nrm > 0.0 ? 1.0 / (amax * sqrt(nrm)) : 0.0;
-  for (int r = threadIdx.x; r < n; r += kEigThreads) Z[r * D + m] *= inv;
-  __syncthreads();
-}
-
-// Z[:, m] -= sum_{q0 <= q < m} (Z[:,q] . Z[:,m]) Z[:,q] twice (classical Gram-Schmidt
-// with one re-orthogonalisation), then normalise (whole workgroup).
-__device__ void mgs_step(double* Z, int D, int n, int m, int q0, double* dots, double* red,
-                         int passes = 2) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  for (int pass = 0; pass < passes && m > q0; ++pass) {
-    for (int q = q0 + wave; q < m; q += kEigWaves) {
+// Z[:, m] -= sum_{q0 <= q < m} (Z[:,q] . Z[:,m]) Z[:,q], twice (classical
+// Gram-Schmidt with one re-orthogonalisation), then normalise.  Z is
+// column-major with leading dimension ldz.  Whole workgroup.
+template <int NT>
+__device__ void cgs2(double* Z, int ldz, int n, int m, int q0, double* dots, double* red) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* zm = Z + (long long)m * ldz;
+  for (int pass = 0; pass < 2 && m > q0; ++pass) {
+    for (int q = q0 + wave; q < m; q += NW) {
+      const double* zq = Z + (long long)q * ldz;
       double s = 0.0;
-      for (int r = lane; r < n; r += 64) s += Z[r * D + q] * Z[r * D + m];
+      for (int r = lane; r < n; r += 64) s += zq[r] * zm[r];
       s = wave_sum(s);
       if (lane == 0) dots[q] = s;
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < n; r += kEigThreads) {
-      double s = Z[r * D + m];
-      for (int q = q0; q < m; ++q) s -= dots[q] * Z[r * D + q];
-      Z[r * D + m] = s;
+    for (int r = threadIdx.x; r < n; r += NT) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int q = q0;
+      for (; q + 3 < m; q += 4) {
+        s0 += dots[q] * Z[(long long)q * ldz + r];
+        s1 += dots[q + 1] * Z[(long long)(q + 1) * ldz + r];
+        s2 += dots[q + 2] * Z[(long long)(q + 2) * ldz + r];
+        s3 += dots[q + 3] * Z[(long long)(q + 3) * ldz + r];
+      }
+      for (; q < m; ++q) s0 += dots[q] * Z[(long long)q * ldz + r];
+      zm[r] -= (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
   }
-  normalize_col(Z, D, n, m, red);
+  double part = 0.0;
+  for (int r = threadIdx.x; r < n; r += NT) part += zm[r] * zm[r];
+  const double nrm2 = block_sum<NT>(part, red);
+  const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+  for (int r = threadIdx.x; r < n; r += NT) zm[r] *= inv;
+  __syncthreads();
 }
 
-__global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p0, EigArgs p1) {
+}  // namespace
+
+// LDS layout (doubles): [0, zr) packed triangle, later the eigenvectors |
+// dd[dv] | ee[dv] | vv[dv] (reflector, later the eigenvalues) | pv[dv]
+// (squared off-diagonal, later Gram-Schmidt coefficients) | ybuf[NT] |
+// red[8].  Cluster scratch (doubles, sstride >= 7 D^2): [0, D^2) packed
+// reflectors (or the whole packed matrix when it is not in LDS) | 4 D^2
+// factor rows | (D|1) D eigenvectors when they are not in LDS.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_eig(EigArgs p0, EigArgs p1, int zr, int dv) {
+  constexpr int NW = NT / 64;
   extern __shared__ double sm[];
   const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
   const int c = blockIdx.x;
@@ -212,177 +271,290 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p0, EigArgs p1) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int D = p.D;
+  const int half = p.half;
   const int k1 = p.k1[(long long)c * p.kstride];
   const int k2 = p.k2 ? p.k2[(long long)c * p.kstride] : 0;
   const int n = k1 + k2;
   double* Uc = p.U + (long long)c * p.ustride;
-  for (long long e = tid; e < (long long)D * D; e += kEigThreads) Uc[e] = 0.0;
-  if (n > kEigNmax || n <= 0) {
+  for (long long e = tid; e < (long long)D * D; e += NT) Uc[e] = 0.0;
+  if (n > kEigNmax || n <= 0 || k1 < 0 || k2 < 0 || k1 > half || k2 > D - half || D > dv) {
     if (tid == 0) {
       p.rank[c] = 0;
-      if (n > kEigNmax) p.status[1] = 1;
+      if (n != 0) p.status[1] = 1;
     }
     return;
   }
   const int np = n * (n + 1) / 2;
-  // packed triangle in LDS up to kEigLdsN, else in the cluster's scratch (L2)
-  const bool lds_p = n <= kEigLdsN;
   double* S = p.scratch + (long long)c * p.sstride;
-  double* P = lds_p ? sm : S + 6LL * D * D;
-  double* dd = lds_p ? sm + np : sm;
-  double* ee = dd + n;
-  double* lam = ee + n;
-  double* pv = lam + n;
-  double* wv = pv + n;
-  double* red = wv + n;
+  const long long DD = (long long)D * D;
+  double* Pg = S;
+  const bool lds_p = n <= kEigLdsN && np <= zr;
+  double* P = lds_p ? sm : Pg;
+  double* dd = sm + zr;
+  double* ee = dd + dv;
+  double* vv = ee + dv;
+  double* pv = vv + dv;
+  double* ybuf = pv + dv;
+  double* red = ybuf + NT;
   const double* Gc = p.G + (long long)c * p.gstride;
-  const int half = p.half;
 
   // 1. gather the live block, packed lower triangle
   int bad = 0;
-  for (int j = wave; j < n; j += kEigWaves) {
+  for (int j = wave; j < n; j += NW) {
     const int oj = j < k1 ? j : half + (j - k1);
+    const int cj = cs(j, n) - j;
     for (int i = j + lane; i < n; i += 64) {
       const int oi = i < k1 ? i : half + (i - k1);
       const double v = Gc[oi + (long long)oj * D];
       if (!(v == v) || v - v != 0.0) bad = 1;
-      P[pidx(i, j, n)] = v;
+      P[cj + i] = v;
     }
   }
   if (bad) p.status[0] = 1;
   __syncthreads();
 
-  // 2. Householder tridiagonalisation (lower), reflector v_i in column i
-  for (int i = 0; i < n - 2; ++i) {
-    double part = 0;
-    for (int r = i + 1 + tid; r < n; r += kEigThreads) {
-      const double x = P[pidx(r, i, n)];
-      part += x * x;
+  // 2. Householder tridiagonalisation (lower); reflector u_i (unit norm,
+  // H_i = I - 2 u_i u_i^T) kept in column i of Pg
+  for (int i = 0; i + 2 < n; ++i) {
+    const int m = n - i - 1;
+    const int ci = cs(i, n);
+    double xr[4], ur[4];
+    double part = 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = i + 1 + lane + 64 * s;
+      xr[s] = r < n ? P[ci + r - i] : 0.0;
+      part += xr[s] * xr[s];
     }
-    const double xx = block_sum(part, red);
-    const double x0 = P[pidx(i + 1, i, n)];
+    const double xx = wave_sum(part);
+    const double x0 = P[ci + 1];
     const double nx = sqrt(xx);
-    double alpha = 0.0;
-    double vn = 1.0;
-    if (nx > 0.0) {
-      alpha = -copysign(nx, x0);
-      const double v0 = x0 - alpha;
-      vn = sqrt(xx - x0 * x0 + v0 * v0);
-    }
-    __syncthreads();
-    if (nx > 0.0) {
-      for (int r = i + 1 + tid; r < n; r += kEigThreads) {
-        const double x = (r == i + 1) ? (x0 - alpha) : P[pidx(r, i, n)];
-        P[pidx(r, i, n)] = x / vn;
-      }
-    }
-    if (tid == 0) {
-      dd[i] = P[pidx(i, i, n)];
-      ee[i] = alpha;
-    }
-    __syncthreads();
-    if (nx > 0.0) {
-      for (int r = i + 1 + tid; r < n; r += kEigThreads) {
-        double s = 0.0;
-        int cc = i + 1;
-        for (; cc <= r; ++cc) s += P[pidx(r, cc, n)] * P[pidx(cc, i, n)];
-        const int base = pidx(r, r, n);
-        for (; cc < n; ++cc) s += P[base + (cc - r)] * P[pidx(cc, i, n)];
-        pv[r] = 2.0 * s;
-      }
-      __syncthreads();
-      double part2 = 0.0;
-      for (int r = i + 1 + tid; r < n; r += kEigThreads) part2 += P[pidx(r, i, n)] * pv[r];
-      const double K = block_sum(part2, red);
-      for (int r = i + 1 + tid; r < n; r += kEigThreads) wv[r] = pv[r] - K * P[pidx(r, i, n)];
-      __syncthreads();
-      for (int cc = i + 1 + wave; cc < n; cc += kEigWaves) {
-        const double vc = P[pidx(cc, i, n)];
-        const double wc = wv[cc];
-        const int base = pidx(cc, cc, n) - cc;
-        for (int r = cc + lane; r < n; r += 64) {
-          P[base + r] -= P[pidx(r, i, n)] * wc + wv[r] * vc;
+    if (!(nx > 0.0)) {  // column already reduced: H_i = I
+      if (wave == 0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int r = i + 1 + lane + 64 * s;
+          if (r < n) Pg[ci + r - i] = 0.0;
+        }
+        if (lane == 0) {
+          dd[i] = P[ci];
+          ee[i] = 0.0;
         }
       }
       __syncthreads();
+      continue;
     }
+    const double alpha = -copysign(nx, x0);
+    const double v0 = x0 - alpha;
+    const double vn = sqrt(xx - x0 * x0 + v0 * v0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = i + 1 + lane + 64 * s;
+      ur[s] = r < n ? (r == i + 1 ? v0 : xr[s]) / vn : 0.0;
+    }
+    if (wave == 0) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = i + 1 + lane + 64 * s;
+        if (r < n) vv[r] = ur[s];
+      }
+      if (lane == 0) {
+        dd[i] = P[ci];
+        ee[i] = alpha;
+      }
+    }
+    __syncthreads();
+    // p = 2 A22 u: row r by T waves, each over a contiguous range of columns
+    const int nslot = (m + 63) >> 6;
+    const int T = NW / nslot;
+    {
+      const int slot = wave % nslot, t = wave / nslot;
+      if (t < T) {
+        const int r = i + 1 + slot * 64 + lane;
+        const int c_lo = i + 1 + (m * t) / T, c_hi = i + 1 + (m * (t + 1)) / T;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (r < n) {
+          int cc = c_lo;
+          int addr = cc <= r ? cs(cc, n) + r - cc : cs(r, n) + cc - r;
+          for (; cc + 3 < c_hi; cc += 4) {
+            const int a0 = addr;
+            const int a1 = a0 + (cc < r ? n - cc - 1 : 1);
+            const int a2 = a1 + (cc + 1 < r ? n - cc - 2 : 1);
+            const int a3 = a2 + (cc + 2 < r ? n - cc - 3 : 1);
+            addr = a3 + (cc + 3 < r ? n - cc - 4 : 1);
+            s0 += P[a0] * vv[cc];
+            s1 += P[a1] * vv[cc + 1];
+            s2 += P[a2] * vv[cc + 2];
+            s3 += P[a3] * vv[cc + 3];
+          }
+          for (; cc < c_hi; ++cc) {
+            s0 += P[addr] * vv[cc];
+            addr += cc < r ? n - cc - 1 : 1;
+          }
+        }
+        ybuf[(t * nslot + slot) * 64 + lane] = (s0 + s1) + (s2 + s3);
+      }
+    }
+    if (lds_p && wave == NW - 1) {
+      // the finished reflector to the cluster's scratch
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = i + 1 + lane + 64 * s;
+        if (r < n) Pg[ci + r - i] = ur[s];
+      }
+    }
+    __syncthreads();
+    if (!lds_p && wave == 0) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = i + 1 + lane + 64 * s;
+        if (r < n) Pg[ci + r - i] = ur[s];
+      }
+    }
+    // K = u . p and w = p - K u, by every wave
+    const int ts = nslot * 64;
+    double pr[4], wr[4];
+    part = 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = i + 1 + lane + 64 * s;
+      double q = 0.0;
+      if (r < n)
+        for (int t = 0; t < T; ++t) q += ybuf[t * ts + (r - i - 1)];
+      pr[s] = 2.0 * q;
+      part += ur[s] * pr[s];
+    }
+    const double K = wave_sum(part);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) wr[s] = pr[s] - K * ur[s];
+    // A22 -= u w^T + w u^T on the lower triangle: waves over columns, lanes
+    // over rows
+    for (int cc = i + 1 + wave; cc < n; cc += NW) {
+      double q = 0.0;
+      for (int t = 0; t < T; ++t) q += ybuf[t * ts + (cc - i - 1)];
+      const double uc = vv[cc];
+      const double wc = 2.0 * q - K * uc;
+      const int base = cs(cc, n) - cc;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = i + 1 + lane + 64 * s;
+        if (r >= cc && r < n) P[base + r] -= ur[s] * wc + wr[s] * uc;
+      }
+    }
+    __syncthreads();
   }
   if (tid == 0) {
     if (n >= 2) {
-      dd[n - 2] = P[pidx(n - 2, n - 2, n)];
-      dd[n - 1] = P[pidx(n - 1, n - 1, n)];
-      ee[n - 2] = P[pidx(n - 1, n - 2, n)];
+      dd[n - 2] = P[cs(n - 2, n)];
+      dd[n - 1] = P[cs(n - 1, n)];
+      ee[n - 2] = P[cs(n - 2, n) + 1];
     } else {
       dd[0] = P[0];
     }
   }
   __syncthreads();
-  // e^2 for the Sturm counts (pv is free now)
-  for (int i = tid; i < n - 1; i += kEigThreads) pv[i] = ee[i] * ee[i];
+  double* e2 = pv;
+  for (int j = tid; j < n - 1; j += NT) e2[j] = ee[j] * ee[j];
   __syncthreads();
 
-  // 3. eigenvalues by bisection, lam[m] = m-th largest
+  // 3. eigenvalues.  Gershgorin interval of T
   double gl = 1e300, gu = -1e300;
-  for (int i = 0; i < n; ++i) {
-    const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < n - 1 ? fabs(ee[i]) : 0.0);
-    gl = fmin(gl, dd[i] - r);
-    gu = fmax(gu, dd[i] + r);
+  for (int j = 0; j < n; ++j) {
+    const double rad = (j > 0 ? fabs(ee[j - 1]) : 0.0) + (j < n - 1 ? fabs(ee[j]) : 0.0);
+    gl = fmin(gl, dd[j] - rad);
+    gu = fmax(gu, dd[j] + rad);
   }
   const double bnd = fmax(fabs(gl), fabs(gu));
   const double tol = 4e-16 * bnd + 1e-300;
   gl -= tol;
   gu += tol;
   const double pivmin = 1e-290;
-  for (int m = tid; m < n; m += kEigThreads) {
-    const int j = n - 1 - m;
-    double lo = gl, hi = gu;
-    for (int it = 0; it < 160 && hi - lo > tol; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (sturm_count(dd, pv, n, mid, pivmin) > j)
-        hi = mid;
-      else
-        lo = mid;
-    }
-    lam[m] = 0.5 * (lo + hi);
-  }
-  __syncthreads();
-
-  // 4. kept count
+  double* lam = vv;
   int k;
+  double lo0 = gl, hi0 = gu;
   if (p.exact) {
     k = n;
-  } else if (!(lam[0] > 0.0)) {
-    k = 1;
   } else {
-    const double thr = p.tau * lam[0];
-    k = 0;
-    for (int m = 0; m < n; ++m) k += lam[m] > thr;
-    if (k < 1) k = 1;
+    // lambda_1 by multisection over the whole workgroup
+    double lo = gl, hi = gu;
+    for (int it = 0; it < 64 && hi - lo > tol; ++it) {
+      const double h = hi - lo;
+      const double x = lo + h * (double)(tid + 1) / (double)(NT + 1);
+      const int below = sturm1(dd, e2, n, x, pivmin) < n;
+      const int wc = __popcll(__ballot(below));
+      __syncthreads();
+      if (lane == 0) red[wave] = (double)wc;
+      __syncthreads();
+      int cnt = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) cnt += (int)red[w];
+      const double nlo = cnt > 0 ? lo + h * (double)cnt / (double)(NT + 1) : lo;
+      const double nhi = cnt < NT ? lo + h * (double)(cnt + 1) / (double)(NT + 1) : hi;
+      lo = nlo;
+      hi = nhi;
+    }
+    const double l1 = 0.5 * (lo + hi);
+    hi0 = hi;
+    if (!(l1 > 0.0)) {
+      k = 1;
+    } else {
+      const double thr = p.tau * l1;
+      k = n - sturm1(dd, e2, n, thr, pivmin);
+      k = k < 1 ? 1 : (k > n ? n : k);
+      lo0 = fmin(thr, lo) - tol;
+    }
   }
-
-  // 5a. inverse iteration, thread m owns vector m; scratch interleaved by m
-  double* sd = S;
-  double* sl = S + (long long)D * D;
-  double* su = S + 2LL * D * D;
-  double* su2 = S + 3LL * D * D;
-  double* Z = S + 4LL * D * D;    // Z[r*D + m]
-  double* spv = S + 5LL * D * D;  // pivot flags of the factorisation of vector m
-  const double tiny = 1e-16 * fmax(bnd, 1e-300);
-  if (tid < k) {
-    const int m = tid;
-    tri_factor(dd, ee, n, lam[m], tiny, sd, sl, su, su2, spv, D, m);
-    for (int r = 0; r < n; ++r) Z[r * D + m] = start_vec(r, m);
-    for (int it = 0; it < 2; ++it) {
-      tri_solve(n, sd, sl, su, su2, spv, D, m, Z);
-      normalize_serial(Z, D, n, m);
+  {
+    int G = 8;
+    while (G > 1 && G * k > NT) G >>= 1;
+    const int Q = 2 * G;
+    const double span = hi0 - lo0;
+    int R = span > tol ? (int)ceil(log2(span / tol) / log2((double)(Q + 1))) : 0;
+    R = R > 200 ? 200 : R;
+    const int g = tid / G, jl = tid % G;
+    if (g < k) {
+      const int jt = n - 1 - g;
+      double lo = lo0, hi = hi0;
+      for (int it = 0; it < R; ++it) {
+        const double h = (hi - lo) / (double)(Q + 1);
+        const double xa = lo + h * (double)(2 * jl + 1);
+        const double xb = lo + h * (double)(2 * jl + 2);
+        int ca, cb;
+        sturm2(dd, e2, n, xa, xb, pivmin, ca, cb);
+        double nlo = lo, nhi = hi;
+        if (ca <= jt) nlo = xa;
+        if (cb <= jt) nlo = xb;
+        if (cb > jt) nhi = xb;
+        if (ca > jt) nhi = xa;
+        lo = group_red<true>(nlo, G);
+        hi = group_red<false>(nhi, G);
+      }
+      if (jl == 0) lam[g] = 0.5 * (lo + hi);
     }
   }
   __syncthreads();
 
-  // 5b. eigenvalues closer than delta form a cluster: independent inverse
+  // 4. inverse iteration, lane m owns vector m
+  const int ldz = n | 1;
+  const bool z_lds = (long long)ldz * k <= zr;
+  double* Z = z_lds ? sm : S + 5 * DD;
+  double* F0 = S + DD;
+  double* F1 = S + 2 * DD;
+  double* F2 = S + 3 * DD;
+  double* F3 = S + 4 * DD;
+  const double tiny = 1e-16 * fmax(bnd, 1e-300);
+  if (tid < k) {
+    double* zm = Z + (long long)tid * ldz;
+    invit_solve(dd, ee, n, lam[tid], tiny, F0, F1, F2, F3, D, tid, zm, true, tid);
+    invit_solve(dd, ee, n, lam[tid], tiny, F0, F1, F2, F3, D, tid, zm, false, 0);
+  }
+  __syncthreads();
+
+  // eigenvalues closer than delta form a cluster: independent inverse
   // iterations cannot separate them, so each further member restarts from a
   // fresh vector and alternates orthogonalisation against the earlier
-  // members with solves (the cluster handling of classical inverse iteration)
+  // members with solves
+  double* dots = pv;
   const double delta = 1e-12 * bnd;
   int c0 = 0;
   for (int m = 1; m < k; ++m) {
@@ -390,75 +562,127 @@ __global__ __launch_bounds__(kEigThreads) void k_eig(EigArgs p0, EigArgs p1) {
       c0 = m;
       continue;
     }
-    for (int r = tid; r < n; r += kEigThreads) Z[r * D + m] = start_vec(r, m + 7919);
+    double* zm = Z + (long long)m * ldz;
+    for (int r = tid; r < n; r += NT) zm[r] = start_vec(r, m + 7919);
     __syncthreads();
     for (int it = 0; it < 3; ++it) {
-      mgs_step(Z, D, n, m, c0, pv, red);
-      if (tid == 0) tri_solve(n, sd, sl, su, su2, spv, D, m, Z);
+      cgs2<NT>(Z, ldz, n, m, c0, dots, red);
+      if (tid == 0) invit_solve(dd, ee, n, lam[m], tiny, F0, F1, F2, F3, D, m, zm, false, 0);
       __syncthreads();
-      normalize_col(Z, D, n, m, red);
     }
-    mgs_step(Z, D, n, m, c0, pv, red);
+    cgs2<NT>(Z, ldz, n, m, c0, dots, red);
   }
 
-  // 5c. Gram-Schmidt with re-orthogonalisation over all kept vectors: a vector
-  // left with almost no component outside the earlier ones needs the second
-  // pass to come out orthogonal
-  for (int m = 0; m < k; ++m) mgs_step(Z, D, n, m, 0, pv, red, 2);
+  // 5. Gram-Schmidt with re-orthogonalisation over all kept vectors
+  for (int m = 0; m < k; ++m) cgs2<NT>(Z, ldz, n, m, 0, dots, red);
 
-  // 6. back-transformation, one wave per vector, scatter to padded rows
-  for (int m = wave; m < k; m += kEigWaves) {
-    double z[4];
+  // 6. back-transformation: z <- H_0 ... H_{n-3} z, four vectors per wave
+  for (int b0 = wave * kVB; b0 < k; b0 += NW * kVB) {
+    double z[kVB][4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int r = lane + 64 * s;
-      z[s] = r < n ? Z[r * D + m] : 0.0;
+    for (int v = 0; v < kVB; ++v)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = lane + 64 * s;
+        z[v][s] = (b0 + v < k && r < n) ? Z[(long long)(b0 + v) * ldz + r] : 0.0;
+      }
+    double un[4];
+    if (n >= 3) {
+      const int ci = cs(n - 3, n);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = lane + 64 * s;
+        un[s] = (r > n - 3 && r < n) ? Pg[ci + r - (n - 3)] : 0.0;
+      }
     }
     for (int i = n - 3; i >= 0; --i) {
-      double part = 0.0;
+      double u[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int r = lane + 64 * s;
-        if (r > i && r < n) part += P[pidx(r, i, n)] * z[s];
-      }
-      const double sum2 = 2.0 * wave_sum(part);
+      for (int s = 0; s < 4; ++s) u[s] = un[s];
+      if (i > 0) {  // fetch the next reflector while this one is applied
+        const int cn = cs(i - 1, n);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int r = lane + 64 * s;
-        if (r > i && r < n) z[s] -= sum2 * P[pidx(r, i, n)];
+        for (int s = 0; s < 4; ++s) {
+          const int r = lane + 64 * s;
+          un[s] = (r > i - 1 && r < n) ? Pg[cn + r - (i - 1)] : 0.0;
+        }
       }
+      double d[kVB];
+#pragma unroll
+      for (int v = 0; v < kVB; ++v) {
+        double t = 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) t += u[s] * z[v][s];
+        d[v] = t;
+      }
+#pragma unroll
+      for (int v = 0; v < kVB; ++v) d[v] = 2.0 * wave_sum(d[v]);
+#pragma unroll
+      for (int v = 0; v < kVB; ++v)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) z[v][s] -= d[v] * u[s];
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int r = lane + 64 * s;
-      if (r < n) {
-        const int orow = r < k1 ? r : half + (r - k1);
-        Uc[orow + (long long)m * D] = z[s];
+    for (int v = 0; v < kVB; ++v) {
+      const int m = b0 + v;
+      if (m < k) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int r = lane + 64 * s;
+          if (r < n) {
+            const int orow = r < k1 ? r : half + (r - k1);
+            Uc[orow + (long long)m * D] = z[v][s];
+          }
+        }
       }
     }
   }
   if (tid == 0) p.rank[c] = k;
 }
 
-static size_t eig_lds_bytes(int D) {
-  const size_t nl = D < kEigLdsN ? D : kEigLdsN;
-  const size_t nv = D < kEigNmax ? D : kEigNmax;
-  return sizeof(double) * (nl * (nl + 1) / 2 + 5 * nv + kEigWaves);
+namespace {
+
+int eig_threads(int D) { return D <= 32 ? 64 : D <= 64 ? 128 : D <= 128 ? 256 : 512; }
+
+// Z/packed-triangle region (doubles) for a launch of padded dimension D
+int eig_zr(int D, int nt) {
+  const int dv = D;
+  const int cap = kLdsBytes / 8 - 4 * dv - nt - 8;
+  const int dl = D < kEigLdsN ? D : kEigLdsN;
+  int zr = dl * (dl + 1) / 2;
+  const int zfull = (D | 1) * D;
+  if (zfull <= 8192 && zfull > zr) zr = zfull;
+  if (D > kEigLdsN) zr = cap;
+  return zr < cap ? zr : cap;
 }
 
-hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStream_t s) {
-  if (nclusters <= 0) return hipSuccess;
-  const size_t lds = eig_lds_bytes(a.D > b.D ? a.D : b.D);
+template <int NT>
+hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, hipStream_t s) {
+  const int zr = eig_zr(D, NT);
+  const size_t lds = sizeof(double) * ((size_t)zr + 4 * (size_t)D + NT + 8);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_eig,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)eig_lds_bytes(kEigNmax));
+    hipError_t e = hipFuncSetAttribute((const void*)k_eig<NT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_eig, dim3(nclusters, 2), dim3(kEigThreads), lds, s, a, b);
+  hipLaunchKernelGGL(k_eig<NT>, dim3(nclusters, 2), dim3(NT), lds, s, a, b, zr, D);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStream_t s) {
+  if (nclusters <= 0) return hipSuccess;
+  const int D = a.D > b.D ? a.D : b.D;
+  if (D > kEigNmax || D < 1) return hipErrorInvalidValue;
+  switch (eig_threads(D)) {
+    case 64: return launch_nt<64>(a, b, nclusters, D, s);
+    case 128: return launch_nt<128>(a, b, nclusters, D, s);
+    case 256: return launch_nt<256>(a, b, nclusters, D, s);
+    default: return launch_nt<512>(a, b, nclusters, D, s);
+  }
 }
 
 }  // namespace h2k

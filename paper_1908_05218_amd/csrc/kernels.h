@@ -71,7 +71,7 @@ struct EigArgs {
   const int* k2;   // k2[c*kstride]: live rows of the second child (null: none)
   int kstride;
   int half;
-  double* scratch;  // per cluster 6*D*D doubles
+  double* scratch;  // per cluster 7*D*D doubles
   long long sstride;
   double tau;
   int exact;
@@ -79,7 +79,7 @@ struct EigArgs {
 };
 
 constexpr int kEigNmax = 256;  // largest Gram dimension
-constexpr int kEigLdsN = 192;  // largest dimension whose packed triangle stays in LDS
+constexpr int kEigLdsN = 195;  // largest dimension whose packed triangle stays in LDS
 
 template <typename T>
 hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s);
