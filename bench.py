@@ -3,7 +3,9 @@
 Workload: plates64k — N = 65,536 points on two parallel unit plates 0.1 apart
 (128 x 256 cell-centre grid per plate, U[-1e-3, 1e-3] jitter, seed 1), leaf
 size 32, eta = 1, 3x3x3 Chebyshev bases (rank 27), kernel 1/(4 pi r) with the
-panel self-term; C = A A at eps = 1e-4 (ACCURACY truncation), FP64.
+panel self-term; C = A A at eps = 1e-4 (ACCURACY truncation).  The headline is
+the FP32-bulk product (FP32 MFMA block products, FP64 Gram sums and
+eigen-decompositions); the plain FP64 product is timed beside it.
 
 A step is one full product (every level: Grams, eigen-decompositions,
 projections, collects, block products, split) on inputs already resident in
@@ -19,6 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 MFMA
 
 
 def cpu_baseline():
@@ -45,57 +48,45 @@ def cpu_baseline():
                       f"full checker product in {t:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--eps", type=float, default=1e-4)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
+PEAK = {"fp64": FP64_PEAK_TFLOPS, "fp32_bulk": FP32_PEAK_TFLOPS}
 
+
+def run_precision(h2, ctx, dA, n, prec, steps, warmup, eps):
+    """Warm-up, then `steps` timed products (per-launch HIP events on the
+    library's stream give the per-kernel-class split); returns the timing,
+    the relative error of the last product and the breakdown."""
     import numpy as np
-    import paper_1908_05218_amd as h2
-    from h2inputs import configs
-
-    t0 = time.perf_counter()
-    A = configs.plates64k().build()
-    t_build = time.perf_counter() - t0
-    ctx = h2.Context(0)
-    dA = h2.load(ctx, A.to_flat())
-    print(f"[bench] inputs built in {t_build:.1f}s, loaded", file=sys.stderr, flush=True)
-    for i in range(args.warmup):
-        C = h2.mmp(ctx, dA, dA, args.eps)
-        print(f"[bench] warmup {i}: {h2.stats(C)['mmp_ms']:.1f} ms", file=sys.stderr, flush=True)
+    for i in range(warmup):
+        C = h2.mmp(ctx, dA, dA, eps, precision=prec)
+        print(f"[bench] {prec} warmup {i}: {h2.stats(C)['mmp_ms']:.1f} ms", file=sys.stderr, flush=True)
         C.free()
     ctx.set_profiling(True)
-    dev_ms, walls, st = [], [], None
-    prof = {"contraction_ms": 0.0, "contraction_launches": 0, "flops": 0.0, "eig_ms": 0.0,
-            "eig_launches": 0, "gram_ms": 0.0, "gram_launches": 0, "gram_flops": 0.0,
-            "other_ms": 0.0, "other_launches": 0, "contraction_flops": 0.0}
-    for i in range(args.steps):
+    walls, dev_ms = [], []
+    prof = {"contraction_ms": 0.0, "contraction_launches": 0, "eig_ms": 0.0, "eig_launches": 0,
+            "gram_ms": 0.0, "gram_launches": 0, "gram_flops": 0.0, "other_ms": 0.0,
+            "other_launches": 0, "contraction_flops": 0.0}
+    C = None
+    for i in range(steps):
+        if C is not None:
+            C.free()
         t1 = time.perf_counter()
-        C = h2.mmp(ctx, dA, dA, args.eps)
+        C = h2.mmp(ctx, dA, dA, eps, precision=prec)
         walls.append(time.perf_counter() - t1)
         st = h2.stats(C)
         dev_ms.append(st["mmp_ms"])
         for k in prof:
             prof[k] += st[k]
-        if i < args.steps - 1:
-            C.free()
-        print(f"[bench] step {i}: wall {walls[-1] * 1e3:.1f} ms, device {dev_ms[-1]:.1f} ms",
+        print(f"[bench] {prec} step {i}: wall {walls[-1] * 1e3:.1f} ms, device {dev_ms[-1]:.1f} ms",
               file=sys.stderr, flush=True)
-    ms = 1e3 * float(np.mean(walls))
+    ctx.set_profiling(False)
     # relative error criterion (equation `error`) on the last product
-    x = np.random.default_rng(7).standard_normal(A.n)
+    x = np.random.default_rng(7).standard_normal(n)
     ref = h2.matvec(ctx, dA, h2.matvec(ctx, dA, x))
     erel = float(np.linalg.norm(h2.matvec(ctx, C, x) - ref) / np.linalg.norm(ref))
-    flops = st["flops"]
-    K = args.steps
+    st = h2.stats(C)
+    C.free()
+    K = steps
+    ms = 1e3 * float(np.mean(walls))
     kinds = {
         "triple_contraction": (prof["contraction_ms"], prof["contraction_launches"]),
         "eigensolver": (prof["eig_ms"], prof["eig_launches"]),
@@ -105,47 +96,89 @@ def main():
     dom = max(kinds, key=lambda k: kinds[k][0])
     dms, dl = kinds[dom]
     if dom == "triple_contraction":
-        alg = prof["flops"]          # canonical flops of the block products (actual ranks)
-        roof = {"bound": "mfma", "unit": "TFLOP/s"}
+        # canonical flops of every evaluated block product (actual ranks)
+        alg = st["flops"] * K
+        roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK[prec]}
     elif dom == "gram_products":
         alg = prof["gram_flops"]
-        roof = {"bound": "mfma", "unit": "TFLOP/s"}
-    elif dom == "eigensolver":
-        n_eig = dl
-        alg = None
-        roof = {"bound": "alu", "unit": "TFLOP/s"}
+        roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS}
     else:
         alg = None
-        roof = {"bound": "mfma", "unit": "TFLOP/s"}
+        roof = {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS}
     achieved = (alg / (dms * 1e-3) / 1e12) if (alg and dms > 0) else None
-    roof.update({"kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                 "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None,
+    roof.update({"kernel": dom, "achieved": achieved,
+                 "frac": (achieved / roof["peak"]) if achieved else None,
                  "traffic": None, "avg_launch_ms": dms / max(dl, 1),
                  "launches_per_step": dl / K,
                  "time_share": dms / (sum(v[0] for v in kinds.values()) or 1)})
     breakdown = {k: {"ms_per_step": v[0] / K, "launches_per_step": v[1] / K} for k, v in kinds.items()}
+    return {"ms": ms, "device_ms": float(np.mean(dev_ms)), "eps_rel": erel, "stats": st,
+            "breakdown": breakdown, "roofline": roof}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--precision", choices=["fp32_bulk", "fp64"], default="fp32_bulk",
+                    help="precision of the headline product (the other one is timed beside it)")
+    ap.add_argument("--no-compare", action="store_true", help="skip the second precision")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1908_05218_amd as h2
+    from h2inputs import configs
+
+    t0 = time.perf_counter()
+    A = configs.plates64k().build()
+    t_build = time.perf_counter() - t0
+    ctx = h2.Context(0)
+    dA = h2.load(ctx, A.to_flat())
+    print(f"[bench] inputs built in {t_build:.1f}s, loaded", file=sys.stderr, flush=True)
+    head = run_precision(h2, ctx, dA, A.n, args.precision, args.steps, args.warmup, args.eps)
+    other = None
+    if not args.no_compare:
+        op = "fp64" if args.precision == "fp32_bulk" else "fp32_bulk"
+        other = run_precision(h2, ctx, dA, A.n, op, args.steps, args.warmup, args.eps)
+    ctx.close()
+    st = head["stats"]
+    ms = head["ms"]
     out = {
         "metric": "H2-MMP unknowns/s (C = A A, eps = 1e-4)",
         "value": A.n / (ms * 1e-3),
         "unit": "unknowns/s",
-        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f32" if args.precision == "fp32_bulk" else "f64",
+        "data": "synthetic",
         "config": {"workload": "plates64k", "N": int(A.n), "leaf_size": 32, "eta": 1.0,
                    "basis": "chebyshev 3x3x3 (rank 27)", "eps": args.eps,
-                   "truncation": "accuracy", "precision": "fp64", "product": "A*A"},
-        "gflops": flops / (ms * 1e-3) / 1e9,
-        "canonical_gflop_per_step": flops / 1e9,
-        "device_ms_per_step": float(np.mean(dev_ms)),
-        "eps_rel": erel,
+                   "truncation": "accuracy", "precision": args.precision,
+                   "arithmetic": ("FP32 MFMA block products; FP64 Gram sums, eigen-decompositions "
+                                  "and bases" if args.precision == "fp32_bulk" else "FP64 throughout"),
+                   "product": "A*A"},
+        "gflops": st["flops"] / (ms * 1e-3) / 1e9,
+        "canonical_gflop_per_step": st["flops"] / 1e9,
+        "device_ms_per_step": head["device_ms"],
+        "eps_rel": head["eps_rel"],
         "rank_max": st["rank_max_r"], "lmin": st["lmin"], "n_triples": st["n_triples"],
         "sparsity_constant": st["sparsity_constant"],
-        "breakdown": breakdown,
-        "roofline": roof,
+        "breakdown": head["breakdown"],
+        "roofline": head["roofline"],
     }
-    C.free()
-    ctx.close()
+    if other is not None:
+        key = "fp64_plain" if args.precision == "fp32_bulk" else "fp32_bulk"
+        out[key] = {"ms_per_step": other["ms"], "value": A.n / (other["ms"] * 1e-3),
+                    "device_ms_per_step": other["device_ms"], "eps_rel": other["eps_rel"],
+                    "speedup_of_headline": other["ms"] / ms,
+                    "breakdown": other["breakdown"], "roofline": other["roofline"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -143,8 +143,10 @@ h2_status h2_export(h2_mat M, const h2_export_buffers* out);
 
 /* Statistics of the last h2_mmp that produced M (zeros for loaded
  * matrices).  rank_max/rank_mean per level for the row (r) and column (c)
- * bases; canonical flops (2 r1 r2 r3 per block product, Grams, 9 d^3 per
- * eigen-decomposition); device time of the numeric phase in ms; the
+ * bases; canonical flops of the block products (2 r1 r2 r3 per evaluated
+ * block product at the actual ranks, Sections III-IV; Gram and eigensolver
+ * work is not included), counted on the first h2_stats call for M by a host
+ * pass over every evaluated block product; device time of the numeric phase in ms; the
  * triple-contraction kernels' summed device time and launch count. */
 #define H2_MAX_LEVELS 40
 typedef struct {

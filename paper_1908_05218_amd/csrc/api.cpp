@@ -53,6 +53,7 @@ void Profiler::collect(double* ms, long long* launches, double* flops) {
 }
 
 thread_local h2_ctx g_active_ctx = nullptr;
+thread_local bool g_bulk_f32 = false;
 
 void scan_limits(const TaskList& t, DevList& d) {
   for (int v : t.a) d.max_a[(v >> 2) & 1] = std::max(d.max_a[(v >> 2) & 1], v >> 3);
@@ -79,6 +80,8 @@ static void check_extent(const void* base, long long stride, int maxtile, long l
                                      std::to_string(it->second) + " bytes)");
 }
 
+static size_t elt_of(const void* p) { return g_active_ctx ? g_active_ctx->elt(p) : 8; }
+
 static h2k::Opnd to_opnd(const Op& o) {
   h2k::Opnd r;
   r.base[0] = o.base0;
@@ -88,25 +91,18 @@ static h2k::Opnd to_opnd(const Op& o) {
   r.ld = o.ld;
   r.sub_r = o.sub_r;
   r.sub_c = o.sub_c;
+  r.f32 = elt_of(o.base0) == 4;
+  if (o.base1 && elt_of(o.base1) != elt_of(o.base0))
+    throw Error(H2_ERR_INTERNAL, "operand bases of different element types");
   return r;
 }
 
-void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int n, int k,
-          const Op& A, bool tA, const Op& B, bool tB, double* C, long long cstride, int ldc,
-          long long csub_r, long long csub_c, double alpha, double beta) {
-  if (tl.nout == 0) return;
-  if (k % 16 != 0 || m <= 0 || n <= 0) throw Error(H2_ERR_INTERNAL, "gemm shape");
-  {
-    const long long ar = tA ? k : m, ac = tA ? m : k, br = tB ? n : k, bc = tB ? k : n;
-    check_extent(A.base0, A.stride0, tl.max_a[0], A.sub_r, A.sub_c, ar, ac, A.ld, 8, "gemm A");
-    check_extent(A.base1 ? A.base1 : A.base0, A.base1 ? A.stride1 : A.stride0, tl.max_a[1], A.sub_r,
-                 A.sub_c, ar, ac, A.ld, 8, "gemm A(sel)");
-    check_extent(B.base0, B.stride0, tl.max_b[0], B.sub_r, B.sub_c, br, bc, B.ld, 8, "gemm B");
-    check_extent(B.base1 ? B.base1 : B.base0, B.base1 ? B.stride1 : B.stride0, tl.max_b[1], B.sub_r,
-                 B.sub_c, br, bc, B.ld, 8, "gemm B(sel)");
-    check_extent(C, cstride, tl.max_out, csub_r, csub_c, m, n, ldc, 8, "gemm C");
-  }
-  h2k::BgemmArgs<double> a{};
+template <typename T>
+static void launch_gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int n,
+                        int k, const Op& A, bool tA, const Op& B, bool tB, void* C,
+                        long long cstride, int ldc, long long csub_r, long long csub_c,
+                        double alpha, double beta) {
+  h2k::BgemmArgs<T> a{};
   a.m = m;
   a.n = n;
   a.k = k;
@@ -116,6 +112,7 @@ void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int
   a.A = to_opnd(A);
   a.B = to_opnd(B);
   a.C = C;
+  a.c_f32 = elt_of(C) == 4;
   a.cstride = cstride;
   a.ldc = ldc;
   a.csub_r = csub_r;
@@ -124,18 +121,46 @@ void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int
   a.seg = tl.seg;
   a.a_idx = tl.a;
   a.b_idx = tl.b;
-  a.alpha = alpha;
-  a.beta = beta;
+  a.alpha = (T)alpha;
+  a.beta = (T)beta;
   hipEvent_t ev = nullptr;
   const double fl = 2.0 * m * n * (double)k * tl.ntask;
   if (prof) prof->begin(kind, fl, &ev);
-  H2_HIP(h2k::launch_bgemm<double>(a, s));
+  H2_HIP(h2k::launch_bgemm<T>(a, s));
   if (prof) prof->end(ev, kind, fl);
 }
 
-void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, double* C,
+void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int n, int k,
+          const Op& A, bool tA, const Op& B, bool tB, void* C, long long cstride, int ldc,
+          long long csub_r, long long csub_c, double alpha, double beta) {
+  if (tl.nout == 0) return;
+  if (k % 16 != 0 || m <= 0 || n <= 0) throw Error(H2_ERR_INTERNAL, "gemm shape");
+  {
+    const long long ar = tA ? k : m, ac = tA ? m : k, br = tB ? n : k, bc = tB ? k : n;
+    const void* a1 = A.base1 ? A.base1 : A.base0;
+    const void* b1 = B.base1 ? B.base1 : B.base0;
+    check_extent(A.base0, A.stride0, tl.max_a[0], A.sub_r, A.sub_c, ar, ac, A.ld, elt_of(A.base0),
+                 "gemm A");
+    check_extent(a1, A.base1 ? A.stride1 : A.stride0, tl.max_a[1], A.sub_r, A.sub_c, ar, ac, A.ld,
+                 elt_of(a1), "gemm A(sel)");
+    check_extent(B.base0, B.stride0, tl.max_b[0], B.sub_r, B.sub_c, br, bc, B.ld, elt_of(B.base0),
+                 "gemm B");
+    check_extent(b1, B.base1 ? B.stride1 : B.stride0, tl.max_b[1], B.sub_r, B.sub_c, br, bc, B.ld,
+                 elt_of(b1), "gemm B(sel)");
+    check_extent(C, cstride, tl.max_out, csub_r, csub_c, m, n, ldc, elt_of(C), "gemm C");
+  }
+  if (g_bulk_f32 && kind != kKindGram)
+    launch_gemm<float>(s, prof, kind, tl, m, n, k, A, tA, B, tB, C, cstride, ldc, csub_r, csub_c,
+                       alpha, beta);
+  else
+    launch_gemm<double>(s, prof, kind, tl, m, n, k, A, tA, B, tB, C, cstride, ldc, csub_r, csub_c,
+                        alpha, beta);
+}
+
+void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, void* C,
             long long cstride, int ldc, long long csub_r, long long csub_c, double beta) {
   if (tl.nout == 0) return;
+  if (elt_of(A.base0) != 8 || elt_of(C) != 8) throw Error(H2_ERR_INTERNAL, "segsum: FP64 only");
   check_extent(A.base0, A.stride0, tl.max_a[0], A.sub_r, A.sub_c, m, n, A.ld, 8, "segsum A");
   check_extent(C, cstride, tl.max_out, csub_r, csub_c, m, n, ldc, 8, "segsum C");
   h2k::SegsumArgs<double> a{};
@@ -143,7 +168,7 @@ void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, double*
   a.n = n;
   a.nout = tl.nout;
   a.A = to_opnd(A);
-  a.C = C;
+  a.C = (double*)C;
   a.cstride = cstride;
   a.ldc = ldc;
   a.csub_r = csub_r;
@@ -155,8 +180,38 @@ void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, double*
   H2_HIP(h2k::launch_segsum<double>(a, s));
 }
 
-void zero(hipStream_t s, double* p, long long n) {
-  if (n > 0) H2_HIP(hipMemsetAsync(p, 0, (size_t)n * sizeof(double), s));
+void zero(hipStream_t s, void* p, long long n) {
+  if (n > 0) H2_HIP(hipMemsetAsync(p, 0, (size_t)n * elt_of(p), s));
+}
+
+const h2_mat_s& f32_shadow(h2_ctx ctx, h2_mat M, hipStream_t s) {
+  if (M->f32) return *M->f32;
+  auto S = std::make_unique<h2_mat_s>();
+  auto cv = [&](const Buf& src) {
+    Buf dst;
+    const long long n = (long long)(src.bytes() / sizeof(double));
+    if (n > 0) {
+      dst = Buf(ctx, (size_t)n * sizeof(float), true);
+      H2_HIP(h2k::launch_d2f(src.as<double>(), dst.as<float>(), n, s));
+    }
+    return dst;
+  };
+  S->ctx = ctx;
+  S->shape = M->shape;
+  S->rr = M->rr;
+  S->rc = M->rc;
+  S->V = cv(M->V);
+  S->W = cv(M->W);
+  S->V_stride = M->V_stride;
+  S->W_stride = M->W_stride;
+  for (const Buf& b : M->Tr) S->Tr.push_back(cv(b));
+  for (const Buf& b : M->Tc) S->Tc.push_back(cv(b));
+  S->Tr_stride = M->Tr_stride;
+  S->Tc_stride = M->Tc_stride;
+  for (const Buf& b : M->S) S->S.push_back(cv(b));
+  S->F = cv(M->F);
+  M->f32 = std::move(S);
+  return *M->f32;
 }
 
 std::unique_ptr<DevPlan> upload_plan(h2_ctx ctx, const Plan& p) {
@@ -353,13 +408,14 @@ void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64
 }  // namespace h2
 
 // ------------------------------------------------------------------ context
-void* h2_ctx_s::alloc(size_t bytes) {
+void* h2_ctx_s::alloc(size_t bytes, bool is_f32) {
   bytes = (bytes + 4095) & ~(size_t)4095;
   auto it = pool.find(bytes);
   if (it != pool.end()) {
     void* p = it->second;
     pool.erase(it);
     live[p] = bytes;
+    if (is_f32) f32.insert(p);
     return p;
   }
   if (budget && used + bytes > budget) {
@@ -387,6 +443,7 @@ void* h2_ctx_s::alloc(size_t bytes) {
   }
   used += bytes;
   live[p] = bytes;
+  if (is_f32) f32.insert(p);
   return p;
 }
 
@@ -395,6 +452,7 @@ void h2_ctx_s::release(void* p) {
   if (it == live.end()) return;
   pool.emplace(it->second, p);
   live.erase(it);
+  f32.erase(p);
 }
 
 h2_ctx_s::~h2_ctx_s() {
@@ -770,6 +828,12 @@ h2_status h2_export(h2_mat M, const h2_export_buffers* o) {
 
 h2_status h2_stats(h2_mat M, h2_stats_t* out) {
   if (!M || !out) return h2::set_error(H2_ERR_ARG, "null argument");
+  if (M->flops_pending) {
+    M->stats.flops = h2::canonical_flops(M->st(), M->flop_akcol, M->flop_bkrow, *M);
+    M->flops_pending = false;
+    std::vector<int64_t>().swap(M->flop_akcol);
+    std::vector<int64_t>().swap(M->flop_bkrow);
+  }
   *out = M->stats;
   return H2_OK;
 }

@@ -6,6 +6,7 @@
 #include <memory>
 #include <string>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "h2mmp.h"
@@ -41,7 +42,10 @@ struct h2_ctx_s {
   bool profiling = false;
   std::multimap<size_t, void*> pool;
   std::unordered_map<void*, size_t> live;
-  void* alloc(size_t bytes);
+  std::unordered_set<void*> f32;  // live allocations that hold float elements
+  void* alloc(size_t bytes, bool is_f32 = false);
+  // element size of the live allocation starting at p (4 or 8)
+  size_t elt(const void* p) const { return f32.count(const_cast<void*>(p)) ? 4 : 8; }
   void release(void* p);
   ~h2_ctx_s();
 };
@@ -52,7 +56,9 @@ namespace h2 {
 class Buf {
  public:
   Buf() = default;
-  Buf(h2_ctx c, size_t bytes) : ctx_(c), bytes_(bytes) { p_ = bytes ? c->alloc(bytes) : nullptr; }
+  Buf(h2_ctx c, size_t bytes, bool is_f32 = false) : ctx_(c), bytes_(bytes) {
+    p_ = bytes ? c->alloc(bytes, is_f32) : nullptr;
+  }
   ~Buf() { reset(); }
   Buf(const Buf&) = delete;
   Buf& operator=(const Buf&) = delete;
@@ -76,6 +82,7 @@ class Buf {
   template <typename T>
   T* as() const { return (T*)p_; }
   double* d() const { return (double*)p_; }
+  void* p() const { return p_; }
   size_t bytes() const { return bytes_; }
 
  private:
@@ -126,15 +133,25 @@ struct h2_mat_s {
   std::vector<h2::Buf> S;          // per level, flat by node, rr[l] x rc[l]
   h2::Buf F;                       // leaf level, flat by node, npad x npad
   h2_stats_t stats{};
+  // ranks of the operands a product's canonical flop count needs (counted
+  // on the first h2_stats call)
+  std::vector<int64_t> flop_akcol, flop_bkrow;
+  bool flops_pending = false;
+  // float copy of V, W, Tr, Tc, S and F for FP32-bulk products (made on the
+  // first such product, kept with the matrix)
+  std::unique_ptr<h2_mat_s> f32;
   const h2::Structure& st() const { return shape->s; }
 };
 
 namespace h2 {
 
+double canonical_flops(const Structure& s, const std::vector<int64_t>& a_kcol,
+                       const std::vector<int64_t>& b_krow, const h2_mat_s& C);
+
 // Operand description for the batched GEMM helpers.
 struct Op {
-  const double* base0 = nullptr;
-  const double* base1 = nullptr;
+  const void* base0 = nullptr;  // element type from the allocation (ctx->elt)
+  const void* base1 = nullptr;
   long long stride0 = 0, stride1 = 0;
   int ld = 0;
   long long sub_r = 0, sub_c = 0;
@@ -156,17 +173,28 @@ struct Profiler {
   void collect(double* ms, long long* launches, double* flops);
 };
 
+// Batched segmented product.  The arithmetic is FP32 for the bulk kinds
+// (kKindOther, kKindTriple) while g_bulk_f32 is set, FP64 otherwise (always for
+// kKindGram); operands and C may be float or double allocations.
 void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int n, int k,
-          const Op& A, bool tA, const Op& B, bool tB, double* C, long long cstride, int ldc,
+          const Op& A, bool tA, const Op& B, bool tB, void* C, long long cstride, int ldc,
           long long csub_r, long long csub_c, double alpha, double beta);
-void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, double* C,
+void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, void* C,
             long long cstride, int ldc, long long csub_r, long long csub_c, double beta);
-void zero(hipStream_t s, double* p, long long n);
+void zero(hipStream_t s, void* p, long long n);
+// float copy of M's data for FP32-bulk products (cached in M->f32)
+const h2_mat_s& f32_shadow(h2_ctx ctx, h2_mat M, hipStream_t s);
 
 std::unique_ptr<DevPlan> upload_plan(h2_ctx ctx, const Plan& p);
 void scan_limits(const TaskList& t, DevList& d);
 // context whose allocations bound-check the launches of the current call
 extern thread_local h2_ctx g_active_ctx;
+// FP32-bulk arithmetic for the bulk GEMM kinds during the current product
+extern thread_local bool g_bulk_f32;
+struct BulkScope {
+  explicit BulkScope(bool on) { g_bulk_f32 = on; }
+  ~BulkScope() { g_bulk_f32 = false; }
+};
 
 h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C);
 void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64_t nrhs);

@@ -14,14 +14,18 @@ struct Opnd {
   int ld;
   long long sub_r;
   long long sub_c;
+  int f32;  // elements are float (else double); both bases share the type
 };
 
+// T is the arithmetic type (FP64 or FP32 MFMA) and the type of C (c_f32 must
+// match); each operand may be stored in either precision.
 template <typename T>
 struct BgemmArgs {
   int m, n, k, nout, tiles_m, tiles_n;
   int transA, transB;
   Opnd A, B;
-  T* C;
+  void* C;
+  int c_f32;
   long long cstride;
   int ldc;
   long long csub_r, csub_c;

@@ -9,11 +9,15 @@
 //
 //   C[out(o)] = alpha * sum_{t in seg(o)} op(A[a(t)]) op(B[b(t)]) + beta * C[out(o)]
 //
-// One workgroup owns one 32x32 tile of one output and loops over the tasks
-// of that output's segment, so every output is reduced in registers in a
-// fixed order (deterministic, no atomics).  Four wave64s each hold a 16x16
-// MFMA accumulator; operand tiles are staged through LDS so that transposed
-// and plain operands load coalesced.
+// One workgroup owns one TM x TN tile (32..96 per side) of one output and
+// loops over the tasks of that output's segment, so every output is reduced
+// in registers in a fixed order (deterministic, no atomics).  Four wave64s
+// hold 16x16 MFMA accumulators; operand tiles are staged through LDS so that
+// transposed and plain operands load coalesced.  The arithmetic runs in FP64
+// or FP32 MFMA (the output has that type); each operand is stored in float or
+// double (template parameters) and converted when staged into LDS, so the
+// bulk products of the FP32 mode and the FP64 Gram sums over FP32 factors
+// share one kernel.
 //
 // Operand addressing: an index v encodes (tile << 3) | (sel << 2) | (ch << 1) | rh.
 // The block lives at base[sel] + tile*stride[sel] + rh*sub_r + ch*sub_c, so a
@@ -61,7 +65,7 @@ struct Mfma<float> {
 // are issued into registers before the MFMAs of step s run from one LDS
 // buffer, then stored into the other buffer (one barrier per step).  Plain
 // and transposed operands both load coalesced.
-template <typename T, int TM, int TN>
+template <typename T, int TM, int TN, typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KC = 16;
@@ -105,35 +109,39 @@ __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
     const int e = tid + r * 256;
     if (!p.transB) { bq[r] = e % KC; bj[r] = e / KC; } else { bj[r] = e % TN; bq[r] = e / TN; }
   }
-  T ra[LA], rb[LB];
+  // prefetch registers hold the operands in their storage types TA/TB; the
+  // conversion to T happens at the LDS store, after the step's MFMAs, so the
+  // loads stay in flight across them
+  TA ra[LA];
+  TB rb[LB];
   auto load_step = [&](int st) {
     const int t = s0 + st / nk;
     const int kk = (st % nk) * KC;
     int sa, sb;
     const long long oa = opnd_off(p.A, p.a_idx[t], sa);
     const long long ob = opnd_off(p.B, p.b_idx[t], sb);
-    const T* Ab = (const T*)p.A.base[sa] + oa;
-    const T* Bb = (const T*)p.B.base[sb] + ob;
+    const TA* Ab = (const TA*)p.A.base[sa] + oa;
+    const TB* Bb = (const TB*)p.B.base[sb] + ob;
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
       const int gi = row0 + ai[r];
       ra[r] = gi < p.m ? (p.transA ? Ab[(kk + aq[r]) + (long long)gi * lda]
                                    : Ab[gi + (long long)(kk + aq[r]) * lda])
-                       : (T)0;
+                       : (TA)0;
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
       const int gj = col0 + bj[r];
       rb[r] = gj < p.n ? (p.transB ? Bb[gj + (long long)(kk + bq[r]) * ldb]
                                    : Bb[(kk + bq[r]) + (long long)gj * ldb])
-                       : (T)0;
+                       : (TB)0;
     }
   };
   auto store_step = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < LA; ++r) As[buf][aq[r]][ai[r]] = ra[r];
+    for (int r = 0; r < LA; ++r) As[buf][aq[r]][ai[r]] = (T)ra[r];
 #pragma unroll
-    for (int r = 0; r < LB; ++r) Bs[buf][bq[r]][bj[r]] = rb[r];
+    for (int r = 0; r < LB; ++r) Bs[buf][bq[r]][bj[r]] = (T)rb[r];
   };
   if (nsteps > 0) {
     load_step(0);
@@ -160,8 +168,8 @@ __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
     __syncthreads();
   }
   const int ov = p.out_idx[o];
-  T* Cb = p.C + ((long long)(ov >> 3) * p.cstride + ((ov & 1) ? p.csub_r : 0LL) +
-                 ((ov & 2) ? p.csub_c : 0LL));
+  T* Cb = (T*)p.C + ((long long)(ov >> 3) * p.cstride + ((ov & 1) ? p.csub_r : 0LL) +
+                     ((ov & 2) ? p.csub_c : 0LL));
 #pragma unroll
   for (int a = 0; a < SM; ++a)
 #pragma unroll
@@ -290,7 +298,15 @@ static hipError_t launch_tile(BgemmArgs<T> a, hipStream_t s) {
   a.tiles_m = cdiv(a.m, TM);
   a.tiles_n = cdiv(a.n, TN);
   const long long grid = (long long)a.nout * a.tiles_m * a.tiles_n;
-  hipLaunchKernelGGL((k_bgemm<T, TM, TN>), dim3((unsigned)grid), dim3(256), 0, s, a);
+  const dim3 g((unsigned)grid), b(256);
+  if (a.A.f32 && a.B.f32)
+    hipLaunchKernelGGL((k_bgemm<T, TM, TN, float, float>), g, b, 0, s, a);
+  else if (a.A.f32)
+    hipLaunchKernelGGL((k_bgemm<T, TM, TN, float, double>), g, b, 0, s, a);
+  else if (a.B.f32)
+    hipLaunchKernelGGL((k_bgemm<T, TM, TN, double, float>), g, b, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_bgemm<T, TM, TN, double, double>), g, b, 0, s, a);
   return hipGetLastError();
 }
 
@@ -299,6 +315,7 @@ static hipError_t launch_tile(BgemmArgs<T> a, hipStream_t s) {
 template <typename T>
 hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s) {
   if (a.nout <= 0) return hipSuccess;
+  if (a.c_f32 != (sizeof(T) == sizeof(float))) return hipErrorInvalidValue;  // C has type T
   const int mx = a.m > a.n ? a.m : a.n;
   if (mx > 64 && a.m <= 96 && a.n <= 96) return launch_tile<T, 96, 96>(a, s);
   if (a.m <= 32 && a.n <= 32) return launch_tile<T, 32, 32>(a, s);

@@ -38,8 +38,14 @@ struct Dims {
   int m, n, k;
 };
 
-double canonical_flops(const Structure& s, const h2_mat A, const h2_mat B, const h2_mat C) {
-  // 2 r1 r2 r3 per evaluated block product with the actual dimensions
+
+}  // namespace
+
+// 2 r1 r2 r3 per evaluated block product with the actual dimensions; run on
+// the first h2_stats call for a product, not inside it
+double canonical_flops(const Structure& s, const std::vector<int64_t>& a_kcol,
+                       const std::vector<int64_t>& b_krow, const h2_mat_s& Cm) {
+  const h2_mat_s* C = &Cm;
   double f = 0;
   const int L = s.L;
   for (int l = s.lmin; l <= L; ++l) {
@@ -59,7 +65,7 @@ double canonical_flops(const Structure& s, const h2_mat A, const h2_mat B, const
           else
             f += 2.0 * C->krow[cidx(l, i)] * s.leaf_size[j] * C->kcol[cidx(l, k)];
         } else {
-          const double inner = ta == kNL ? B->krow[cidx(l, j)] : A->kcol[cidx(l, j)];
+          const double inner = ta == kNL ? b_krow[cidx(l, j)] : a_kcol[cidx(l, j)];
           f += 2.0 * C->krow[cidx(l, i)] * inner * C->kcol[cidx(l, k)];
         }
       }
@@ -68,11 +74,15 @@ double canonical_flops(const Structure& s, const h2_mat A, const h2_mat B, const
   return f;
 }
 
-}  // namespace
-
 h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C_out) {
-  (void)prec;
   g_active_ctx = ctx;
+  // FP32-bulk: block products on FP32 MFMA over float copies of the operands;
+  // Gram sums accumulate in FP64 (the truncation thresholds eigenvalues at
+  // eps^2 lambda_1, far below FP32 rounding of a squared quantity), and the
+  // eigen-decompositions and bases stay FP64
+  const bool bulk = prec == H2_PREC_FP32_BULK;
+  const size_t eb = bulk ? sizeof(float) : sizeof(double);
+  BulkScope bulk_scope(bulk);
   const auto t_sym0 = std::chrono::steady_clock::now();
   Shape& sh = *A->shape;
   const Structure& s = sh.s;
@@ -91,6 +101,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   const DevPlan& DP = *sh.dplan;
   auto dl = [&](const TaskList& t) -> const DevList& { return DP.get(t); };
   hipStream_t st = ctx->stream;
+  const h2_mat_s* Ad = bulk ? &f32_shadow(ctx, A, st) : A;
+  const h2_mat_s* Bd = bulk ? (B == A ? Ad : &f32_shadow(ctx, B, st)) : B;
   const int L = s.L, lmin = s.lmin, np = s.npad, nleaf = 1 << L;
   const bool exact = (mode == H2_TRUNC_EXACT) || eps == 0.0;
   const double tau = exact ? 0.0 : (mode == H2_TRUNC_PAPER ? eps : eps * eps);
@@ -127,21 +139,21 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
 
   // ---------------------------------------------------------- step 0: Pi
   std::vector<Buf> Pi(L + 1);
-  Pi[L] = Buf(ctx, (size_t)nleaf * rcA[L] * rrB[L] * sizeof(double));
+  Pi[L] = Buf(ctx, (size_t)nleaf * rcA[L] * rrB[L] * eb, bulk);
   gemm(st, pp, kKindOther, dl(P.pi.leaf), rcA[L], rrB[L], np,
-       Op{A->W.d(), nullptr, A->W_stride, 0, np}, true, Op{B->V.d(), nullptr, B->V_stride, 0, np},
-       false, Pi[L].d(), (long long)rcA[L] * rrB[L], rcA[L], 0, 0, 1.0, 0.0);
+       Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, true, Op{Bd->V.p(), nullptr, B->V_stride, 0, np},
+       false, Pi[L].p(), (long long)rcA[L] * rrB[L], rcA[L], 0, 0, 1.0, 0.0);
   for (int l = L - 1; l >= lmin; --l) {
     const int ch = l + 1;
-    Buf X(ctx, (size_t)(2 << l) * rcA[ch] * rrB[l] * sizeof(double));
+    Buf X(ctx, (size_t)(2 << l) * rcA[ch] * rrB[l] * eb, bulk);
     gemm(st, pp, kKindOther, dl(P.pi.X[l]), rcA[ch], rrB[l], rrB[ch],
-         Op{Pi[ch].d(), nullptr, (long long)rcA[ch] * rrB[ch], 0, rcA[ch]}, false,
-         Op{B->Tr[l].d(), nullptr, B->Tr_stride[l], 0, 2 * rrB[ch], rrB[ch], 0}, false, X.d(),
+         Op{Pi[ch].p(), nullptr, (long long)rcA[ch] * rrB[ch], 0, rcA[ch]}, false,
+         Op{Bd->Tr[l].p(), nullptr, B->Tr_stride[l], 0, 2 * rrB[ch], rrB[ch], 0}, false, X.p(),
          (long long)rcA[ch] * rrB[l], rcA[ch], 0, 0, 1.0, 0.0);
-    Pi[l] = Buf(ctx, (size_t)(1 << l) * rcA[l] * rrB[l] * sizeof(double));
+    Pi[l] = Buf(ctx, (size_t)(1 << l) * rcA[l] * rrB[l] * eb, bulk);
     gemm(st, pp, kKindOther, dl(P.pi.S[l]), rcA[l], rrB[l], rcA[ch],
-         Op{A->Tc[l].d(), nullptr, A->Tc_stride[l], 0, 2 * rcA[ch], rcA[ch], 0}, true,
-         Op{X.d(), nullptr, (long long)rcA[ch] * rrB[l], 0, rcA[ch]}, false, Pi[l].d(),
+         Op{Ad->Tc[l].p(), nullptr, A->Tc_stride[l], 0, 2 * rcA[ch], rcA[ch], 0}, true,
+         Op{X.p(), nullptr, (long long)rcA[ch] * rrB[l], 0, rcA[ch]}, false, Pi[l].p(),
          (long long)rcA[l] * rrB[l], rcA[l], 0, 0, 1.0, 0.0);
   }
 
@@ -234,36 +246,36 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     {
       Buf b1(ctx, nnL * nn2 * sizeof(double)), b2(ctx, nnL * nn2 * sizeof(double)),
           b3(ctx, nnL * nn2 * sizeof(double));
-      const Op FA{A->F.d(), nullptr, nn2, 0, np}, FB{B->F.d(), nullptr, nn2, 0, np};
-      const Op o1{b1.d(), nullptr, nn2, 0, np}, o2{b2.d(), nullptr, nn2, 0, np},
-          o3{b3.d(), nullptr, nn2, 0, np};
+      const Op FA{Ad->F.p(), nullptr, nn2, 0, np}, FB{Bd->F.p(), nullptr, nn2, 0, np};
+      const Op o1{b1.p(), nullptr, nn2, 0, np}, o2{b2.p(), nullptr, nn2, 0, np},
+          o3{b3.p(), nullptr, nn2, 0, np};
       // row Gram, case 1: sum_j F^A_ij (sum_k F^B_jk F^B_jk^T) F^A_ij^T over
       // dense products with an admissible or blue target (equation Gr1L)
-      gemm(st, pp, kKindGram, dl(LP.gB), np, np, np, FB, false, FB, true, b1.d(), nn2, np, 0, 0, 1, 0);
-      segsum(st, dl(LP.H), np, np, o1, b2.d(), nn2, np, 0, 0, 0.0);
-      gemm(st, pp, kKindGram, dl(LP.X1), np, np, np, FA, false, o2, false, b3.d(), nn2, np, 0, 0, 1, 0);
-      gemm(st, pp, kKindGram, dl(LP.G1), np, np, np, o3, false, FA, true, G[0].d(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.gB), np, np, np, FB, false, FB, true, b1.p(), nn2, np, 0, 0, 1, 0);
+      segsum(st, dl(LP.H), np, np, o1, b2.p(), nn2, np, 0, 0, 0.0);
+      gemm(st, pp, kKindGram, dl(LP.X1), np, np, np, FA, false, o2, false, b3.p(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G1), np, np, np, o3, false, FA, true, G[0].p(), nn2, np, 0, 0, 1, 0);
       // column Gram, case 1 (equation case1-ch)
-      gemm(st, pp, kKindGram, dl(LP.hA), np, np, np, FA, true, FA, false, b1.d(), nn2, np, 0, 0, 1, 0);
-      segsum(st, dl(LP.Hc), np, np, o1, b2.d(), nn2, np, 0, 0, 0.0);
-      gemm(st, pp, kKindGram, dl(LP.X1c), np, np, np, FB, true, o2, false, b3.d(), nn2, np, 0, 0, 1, 0);
-      gemm(st, pp, kKindGram, dl(LP.G1c), np, np, np, o3, false, FB, false, Gc[0].d(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.hA), np, np, np, FA, true, FA, false, b1.p(), nn2, np, 0, 0, 1, 0);
+      segsum(st, dl(LP.Hc), np, np, o1, b2.p(), nn2, np, 0, 0, 0.0);
+      gemm(st, pp, kKindGram, dl(LP.X1c), np, np, np, FB, true, o2, false, b3.p(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G1c), np, np, np, o3, false, FB, false, Gc[0].p(), nn2, np, 0, 0, 1, 0);
       // case 2: F^A_ij V^B_j (Gr2L) and (W^A_j^T F^B_jk)^T (case2-ch)
       Buf Z(ctx, (size_t)nnL * np * std::max(rrB[L], rcA[L]) * sizeof(double));
       const long long zs = (long long)np * rrB[L], zcs = (long long)np * rcA[L];
       gemm(st, pp, kKindGram, dl(LP.Z), np, rrB[L], np, FA, false,
-           Op{B->V.d(), nullptr, B->V_stride, 0, np}, false, Z.d(), zs, np, 0, 0, 1, 0);
-      gemm(st, pp, kKindGram, dl(LP.G2), np, np, rrB[L], Op{Z.d(), nullptr, zs, 0, np}, false,
-           Op{Z.d(), nullptr, zs, 0, np}, true, G[1].d(), nn2, np, 0, 0, 1, 0);
+           Op{Bd->V.p(), nullptr, B->V_stride, 0, np}, false, Z.p(), zs, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G2), np, np, rrB[L], Op{Z.p(), nullptr, zs, 0, np}, false,
+           Op{Z.p(), nullptr, zs, 0, np}, true, G[1].p(), nn2, np, 0, 0, 1, 0);
       gemm(st, pp, kKindGram, dl(LP.Zc), np, rcA[L], np, FB, true,
-           Op{A->W.d(), nullptr, A->W_stride, 0, np}, false, Z.d(), zcs, np, 0, 0, 1, 0);
-      gemm(st, pp, kKindGram, dl(LP.G2c), np, np, rcA[L], Op{Z.d(), nullptr, zcs, 0, np}, false,
-           Op{Z.d(), nullptr, zcs, 0, np}, true, Gc[1].d(), nn2, np, 0, 0, 1, 0);
+           Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, false, Z.p(), zcs, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G2c), np, np, rcA[L], Op{Z.p(), nullptr, zcs, 0, np}, false,
+           Op{Z.p(), nullptr, zcs, 0, np}, true, Gc[1].p(), nn2, np, 0, 0, 1, 0);
       // case 3/4: the old bases V^A_i V^A_i^T (Gr3L) and W^B_k W^B_k^T (case3-ch)
-      gemm(st, pp, kKindGram, dl(LP.G3), np, np, rrA[L], Op{A->V.d(), nullptr, A->V_stride, 0, np},
-           false, Op{A->V.d(), nullptr, A->V_stride, 0, np}, true, G[2].d(), nn2, np, 0, 0, 1, 0);
-      gemm(st, pp, kKindGram, dl(LP.G3c), np, np, rcB[L], Op{B->W.d(), nullptr, B->W_stride, 0, np},
-           false, Op{B->W.d(), nullptr, B->W_stride, 0, np}, true, Gc[2].d(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G3), np, np, rrA[L], Op{Ad->V.p(), nullptr, A->V_stride, 0, np},
+           false, Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, true, G[2].p(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G3c), np, np, rcB[L], Op{Bd->W.p(), nullptr, B->W_stride, 0, np},
+           false, Op{Bd->W.p(), nullptr, B->W_stride, 0, np}, true, Gc[2].p(), nn2, np, 0, 0, 1, 0);
     }
     eig_level(L, np, G, Gc, Ur_L, Uc_L, rank_r[L], rank_c[L], leaf_sizes.as<int>(), nullptr,
               leaf_sizes.as<int>(), nullptr, 1, np);
@@ -271,86 +283,86 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   c = read_ranks(L, rank_r[L], rank_c[L]);
   cpad[L] = c;
   {
-    const Op VC{Ur_L.d(), nullptr, nn2, 0, np}, WC{Uc_L.d(), nullptr, nn2, 0, np};
-    const Op FA{A->F.d(), nullptr, nn2, 0, np}, FB{B->F.d(), nullptr, nn2, 0, np};
+    const Op VC{Ur_L.p(), nullptr, nn2, 0, np}, WC{Uc_L.p(), nullptr, nn2, 0, np};
+    const Op FA{Ad->F.p(), nullptr, nn2, 0, np}, FB{Bd->F.p(), nullptr, nn2, 0, np};
     // projections (leafproj)
-    PA_L = Buf(ctx, (size_t)nleaf * c * rrA[L] * sizeof(double));
-    PB_L = Buf(ctx, (size_t)nleaf * rcB[L] * c * sizeof(double));
+    PA_L = Buf(ctx, (size_t)nleaf * c * rrA[L] * eb, bulk);
+    PB_L = Buf(ctx, (size_t)nleaf * rcB[L] * c * eb, bulk);
     gemm(st, pp, kKindOther, dl(LP.PA), c, rrA[L], np, VC, true,
-         Op{A->V.d(), nullptr, A->V_stride, 0, np}, false, PA_L.d(), (long long)c * rrA[L], c, 0, 0, 1, 0);
-    gemm(st, pp, kKindOther, dl(LP.PB), rcB[L], c, np, Op{B->W.d(), nullptr, B->W_stride, 0, np},
-         true, WC, false, PB_L.d(), (long long)rcB[L] * c, rcB[L], 0, 0, 1, 0);
+         Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, false, PA_L.p(), (long long)c * rrA[L], c, 0, 0, 1, 0);
+    gemm(st, pp, kKindOther, dl(LP.PB), rcB[L], c, np, Op{Bd->W.p(), nullptr, B->W_stride, 0, np},
+         true, WC, false, PB_L.p(), (long long)rcB[L] * c, rcB[L], 0, 0, 1, 0);
     // leaf-coordinate left / right operands of every leaf block
     const long long las = (long long)c * np;
-    Buf LA(ctx, (size_t)nnL * las * sizeof(double)), RB(ctx, (size_t)nnL * las * sizeof(double));
+    Buf LA(ctx, (size_t)nnL * las * eb, bulk), RB(ctx, (size_t)nnL * las * eb, bulk);
     {
-      Buf PS(ctx, (size_t)nnL * c * rcA[L] * sizeof(double));
-      Buf SP(ctx, (size_t)nnL * rrB[L] * c * sizeof(double));
-      gemm(st, pp, kKindOther, dl(LP.LA_F), c, np, np, VC, true, FA, false, LA.d(), las, c, 0, 0, 1, 0);
+      Buf PS(ctx, (size_t)nnL * c * rcA[L] * eb, bulk);
+      Buf SP(ctx, (size_t)nnL * rrB[L] * c * eb, bulk);
+      gemm(st, pp, kKindOther, dl(LP.LA_F), c, np, np, VC, true, FA, false, LA.p(), las, c, 0, 0, 1, 0);
       gemm(st, pp, kKindOther, dl(LP.PS), c, rcA[L], rrA[L],
-           Op{PA_L.d(), nullptr, (long long)c * rrA[L], 0, c}, false,
-           Op{A->S[L].d(), nullptr, (long long)rrA[L] * rcA[L], 0, rrA[L]}, false, PS.d(),
+           Op{PA_L.p(), nullptr, (long long)c * rrA[L], 0, c}, false,
+           Op{Ad->S[L].p(), nullptr, (long long)rrA[L] * rcA[L], 0, rrA[L]}, false, PS.p(),
            (long long)c * rcA[L], c, 0, 0, 1, 0);
       gemm(st, pp, kKindOther, dl(LP.LA_R), c, np, rcA[L],
-           Op{PS.d(), nullptr, (long long)c * rcA[L], 0, c}, false,
-           Op{A->W.d(), nullptr, A->W_stride, 0, np}, true, LA.d(), las, c, 0, 0, 1, 0);
-      gemm(st, pp, kKindOther, dl(LP.RB_F), np, c, np, FB, false, WC, false, RB.d(), las, np, 0, 0, 1, 0);
+           Op{PS.p(), nullptr, (long long)c * rcA[L], 0, c}, false,
+           Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, true, LA.p(), las, c, 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.RB_F), np, c, np, FB, false, WC, false, RB.p(), las, np, 0, 0, 1, 0);
       gemm(st, pp, kKindOther, dl(LP.SP), rrB[L], c, rcB[L],
-           Op{B->S[L].d(), nullptr, (long long)rrB[L] * rcB[L], 0, rrB[L]}, false,
-           Op{PB_L.d(), nullptr, (long long)rcB[L] * c, 0, rcB[L]}, false, SP.d(),
+           Op{Bd->S[L].p(), nullptr, (long long)rrB[L] * rcB[L], 0, rrB[L]}, false,
+           Op{PB_L.p(), nullptr, (long long)rcB[L] * c, 0, rcB[L]}, false, SP.p(),
            (long long)rrB[L] * c, rrB[L], 0, 0, 1, 0);
-      gemm(st, pp, kKindOther, dl(LP.RB_R), np, c, rrB[L], Op{B->V.d(), nullptr, B->V_stride, 0, np},
-           false, Op{SP.d(), nullptr, (long long)rrB[L] * c, 0, rrB[L]}, false, RB.d(), las, np, 0,
+      gemm(st, pp, kKindOther, dl(LP.RB_R), np, c, rrB[L], Op{Bd->V.p(), nullptr, B->V_stride, 0, np},
+           false, Op{SP.p(), nullptr, (long long)rrB[L] * c, 0, rrB[L]}, false, RB.p(), las, np, 0,
            0, 1, 0);
     }
     // collected leaf blocks for the level above (Fcollect; 2x2 grouped)
     if (L >= 1) {
       const int ntile = s.lev[L - 1].n_nl;
-      Ahat_L = Buf(ctx, (size_t)ntile * 4 * c * rrB[L] * sizeof(double));
-      Bhat_L = Buf(ctx, (size_t)ntile * 4 * rcA[L] * c * sizeof(double));
-      gemm(st, pp, kKindOther, dl(LP.Ahat), c, rrB[L], np, Op{LA.d(), nullptr, las, 0, c}, false,
-           Op{B->V.d(), nullptr, B->V_stride, 0, np}, false, Ahat_L.d(), 4LL * c * rrB[L], 2 * c,
+      Ahat_L = Buf(ctx, (size_t)ntile * 4 * c * rrB[L] * eb, bulk);
+      Bhat_L = Buf(ctx, (size_t)ntile * 4 * rcA[L] * c * eb, bulk);
+      gemm(st, pp, kKindOther, dl(LP.Ahat), c, rrB[L], np, Op{LA.p(), nullptr, las, 0, c}, false,
+           Op{Bd->V.p(), nullptr, B->V_stride, 0, np}, false, Ahat_L.p(), 4LL * c * rrB[L], 2 * c,
            c, (long long)rrB[L] * 2 * c, 1, 0);
-      gemm(st, pp, kKindOther, dl(LP.Bhat), rcA[L], c, np, Op{A->W.d(), nullptr, A->W_stride, 0, np},
-           true, Op{RB.d(), nullptr, las, 0, np}, false, Bhat_L.d(), 4LL * rcA[L] * c, 2 * rcA[L],
+      gemm(st, pp, kKindOther, dl(LP.Bhat), rcA[L], c, np, Op{Ad->W.p(), nullptr, A->W_stride, 0, np},
+           true, Op{RB.p(), nullptr, las, 0, np}, false, Bhat_L.p(), 4LL * rcA[L] * c, 2 * rcA[L],
            rcA[L], (long long)c * 2 * rcA[L], 1, 0);
     }
     // products into admissible and blue targets (leafcoup_simple)
-    C->S[L] = Buf(ctx, (size_t)nnL * c * c * sizeof(double));
-    zero(st, C->S[L].d(), (long long)nnL * c * c);
+    C->S[L] = Buf(ctx, (size_t)nnL * c * c * eb, bulk);
+    zero(st, C->S[L].p(), (long long)nnL * c * c);
     const int nbt = std::max(1, LP.n_blue_tiles);
-    Acc_L = Buf(ctx, (size_t)nbt * 4 * c * c * sizeof(double));
-    zero(st, Acc_L.d(), (long long)nbt * 4 * c * c);
-    gemm(st, pp, kKindTriple, dl(LP.adm_R), c, c, np, Op{LA.d(), nullptr, las, 0, c}, false,
-         Op{RB.d(), nullptr, las, 0, np}, false, C->S[L].d(), (long long)c * c, c, 0, 0, 1, 1);
-    gemm(st, pp, kKindTriple, dl(LP.adm_B), c, c, np, Op{LA.d(), nullptr, las, 0, c}, false,
-         Op{RB.d(), nullptr, las, 0, np}, false, Acc_L.d(), 4LL * c * c, 2 * c, c,
+    Acc_L = Buf(ctx, (size_t)nbt * 4 * c * c * eb, bulk);
+    zero(st, Acc_L.p(), (long long)nbt * 4 * c * c);
+    gemm(st, pp, kKindTriple, dl(LP.adm_R), c, c, np, Op{LA.p(), nullptr, las, 0, c}, false,
+         Op{RB.p(), nullptr, las, 0, np}, false, C->S[L].p(), (long long)c * c, c, 0, 0, 1, 1);
+    gemm(st, pp, kKindTriple, dl(LP.adm_B), c, c, np, Op{LA.p(), nullptr, las, 0, c}, false,
+         Op{RB.p(), nullptr, las, 0, np}, false, Acc_L.p(), 4LL * c * c, 2 * c, c,
          (long long)c * 2 * c, 1, 1);
   }
   {
     // dense targets: exact leaf products with admissible factors densified
-    FC = Buf(ctx, (size_t)nnL * nn2 * sizeof(double));
-    zero(st, FC.d(), nnL * nn2);
-    Buf DA(ctx, (size_t)nnL * nn2 * sizeof(double)), DB(ctx, (size_t)nnL * nn2 * sizeof(double));
+    FC = Buf(ctx, (size_t)nnL * nn2 * eb, bulk);
+    zero(st, FC.p(), nnL * nn2);
+    Buf DA(ctx, (size_t)nnL * nn2 * eb, bulk), DB(ctx, (size_t)nnL * nn2 * eb, bulk);
     {
-      Buf T(ctx, (size_t)nnL * np * std::max(rcA[L], rcB[L]) * sizeof(double));
+      Buf T(ctx, (size_t)nnL * np * std::max(rcA[L], rcB[L]) * eb, bulk);
       gemm(st, pp, kKindOther, dl(LP.densA1), np, rcA[L], rrA[L],
-           Op{A->V.d(), nullptr, A->V_stride, 0, np}, false,
-           Op{A->S[L].d(), nullptr, (long long)rrA[L] * rcA[L], 0, rrA[L]}, false, T.d(),
+           Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, false,
+           Op{Ad->S[L].p(), nullptr, (long long)rrA[L] * rcA[L], 0, rrA[L]}, false, T.p(),
            (long long)np * rcA[L], np, 0, 0, 1, 0);
       gemm(st, pp, kKindOther, dl(LP.densA2), np, np, rcA[L],
-           Op{T.d(), nullptr, (long long)np * rcA[L], 0, np}, false,
-           Op{A->W.d(), nullptr, A->W_stride, 0, np}, true, DA.d(), nn2, np, 0, 0, 1, 0);
+           Op{T.p(), nullptr, (long long)np * rcA[L], 0, np}, false,
+           Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, true, DA.p(), nn2, np, 0, 0, 1, 0);
       gemm(st, pp, kKindOther, dl(LP.densB1), np, rcB[L], rrB[L],
-           Op{B->V.d(), nullptr, B->V_stride, 0, np}, false,
-           Op{B->S[L].d(), nullptr, (long long)rrB[L] * rcB[L], 0, rrB[L]}, false, T.d(),
+           Op{Bd->V.p(), nullptr, B->V_stride, 0, np}, false,
+           Op{Bd->S[L].p(), nullptr, (long long)rrB[L] * rcB[L], 0, rrB[L]}, false, T.p(),
            (long long)np * rcB[L], np, 0, 0, 1, 0);
       gemm(st, pp, kKindOther, dl(LP.densB2), np, np, rcB[L],
-           Op{T.d(), nullptr, (long long)np * rcB[L], 0, np}, false,
-           Op{B->W.d(), nullptr, B->W_stride, 0, np}, true, DB.d(), nn2, np, 0, 0, 1, 0);
+           Op{T.p(), nullptr, (long long)np * rcB[L], 0, np}, false,
+           Op{Bd->W.p(), nullptr, B->W_stride, 0, np}, true, DB.p(), nn2, np, 0, 0, 1, 0);
     }
-    gemm(st, pp, kKindTriple, dl(LP.dense), np, np, np, Op{A->F.d(), DA.d(), nn2, nn2, np}, false,
-         Op{B->F.d(), DB.d(), nn2, nn2, np}, false, FC.d(), nn2, np, 0, 0, 1, 1);
+    gemm(st, pp, kKindTriple, dl(LP.dense), np, np, np, Op{Ad->F.p(), DA.p(), nn2, nn2, np}, false,
+         Op{Bd->F.p(), DB.p(), nn2, nn2, np}, false, FC.p(), nn2, np, 0, 0, 1, 1);
   }
 
   // ========================================================= non-leaf levels
@@ -367,45 +379,45 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     const LevelPlan& Q = P.lev[l];
     const int ncl = 1 << l;
     const int nn = s.lev[l].size();
-    const Op AccT{Acc_ch.d(), nullptr, 4LL * cc * cc, 0, K};
+    const Op AccT{Acc_ch.p(), nullptr, 4LL * cc * cc, 0, K};
     Buf G[3], Gc[3];
     for (int k = 0; k < 3; ++k) {
       G[k] = Buf(ctx, (size_t)ncl * K2 * sizeof(double));
       Gc[k] = Buf(ctx, (size_t)ncl * K2 * sizeof(double));
     }
     // case 1: merged children couplings M_IK (nonleafA; case1-ch-nl)
-    gemm(st, pp, kKindGram, dl(Q.G1), K, K, K, AccT, false, AccT, true, G[0].d(), K2, K, 0, 0, 1, 0);
-    gemm(st, pp, kKindGram, dl(Q.G1c), K, K, K, AccT, true, AccT, false, Gc[0].d(), K2, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G1), K, K, K, AccT, false, AccT, true, G[0].p(), K2, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G1c), K, K, K, AccT, true, AccT, false, Gc[0].p(), K2, K, 0, 0, 1, 0);
     // case 2: (NL^A)_coll T^B_J (case2-ch-nl) and its column mirror
     const long long ys = (long long)K * rrB[l], ycs = (long long)rcA[l] * K;
     Buf Y(ctx, (size_t)std::max(1, nn) * ys * sizeof(double));
     Buf Yc(ctx, (size_t)std::max(1, nn) * ycs * sizeof(double));
     gemm(st, pp, kKindGram, dl(Q.Y), K, rrB[l], 2 * rrB[ch],
-         Op{Ahat_ch.d(), nullptr, 4LL * cc * rrB[ch], 0, K}, false,
-         Op{B->Tr[l].d(), nullptr, B->Tr_stride[l], 0, 2 * rrB[ch]}, false, Y.d(), ys, K, 0, 0, 1, 0);
-    gemm(st, pp, kKindGram, dl(Q.G2), K, K, rrB[l], Op{Y.d(), nullptr, ys, 0, K}, false,
-         Op{Y.d(), nullptr, ys, 0, K}, true, G[1].d(), K2, K, 0, 0, 1, 0);
+         Op{Ahat_ch.p(), nullptr, 4LL * cc * rrB[ch], 0, K}, false,
+         Op{Bd->Tr[l].p(), nullptr, B->Tr_stride[l], 0, 2 * rrB[ch]}, false, Y.p(), ys, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G2), K, K, rrB[l], Op{Y.p(), nullptr, ys, 0, K}, false,
+         Op{Y.p(), nullptr, ys, 0, K}, true, G[1].p(), K2, K, 0, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.Yc), rcA[l], K, 2 * rcA[ch],
-         Op{A->Tc[l].d(), nullptr, A->Tc_stride[l], 0, 2 * rcA[ch]}, true,
-         Op{Bhat_ch.d(), nullptr, 4LL * rcA[ch] * cc, 0, 2 * rcA[ch]}, false, Yc.d(), ycs, rcA[l],
+         Op{Ad->Tc[l].p(), nullptr, A->Tc_stride[l], 0, 2 * rcA[ch]}, true,
+         Op{Bhat_ch.p(), nullptr, 4LL * rcA[ch] * cc, 0, 2 * rcA[ch]}, false, Yc.p(), ycs, rcA[l],
          0, 0, 1, 0);
-    gemm(st, pp, kKindGram, dl(Q.G2c), K, K, rcA[l], Op{Yc.d(), nullptr, ycs, 0, rcA[l]}, true,
-         Op{Yc.d(), nullptr, ycs, 0, rcA[l]}, false, Gc[1].d(), K2, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G2c), K, K, rcA[l], Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, true,
+         Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, false, Gc[1].p(), K2, K, 0, 0, 1, 0);
     // cases 3/4: old bases projected on the children's new bases (case3-ch-nl)
     const long long ds = (long long)K * rrA[l], qs = (long long)K * rcB[l];
     Buf Dm(ctx, (size_t)ncl * ds * sizeof(double)), Qm(ctx, (size_t)ncl * qs * sizeof(double));
     gemm(st, pp, kKindGram, dl(Q.D), cc, rrA[l], rrA[ch],
-         Op{PA_ch.d(), nullptr, (long long)cc * rrA[ch], 0, cc}, false,
-         Op{A->Tr[l].d(), nullptr, A->Tr_stride[l], 0, 2 * rrA[ch], rrA[ch], 0}, false, Dm.d(), ds,
+         Op{PA_ch.p(), nullptr, (long long)cc * rrA[ch], 0, cc}, false,
+         Op{Ad->Tr[l].p(), nullptr, A->Tr_stride[l], 0, 2 * rrA[ch], rrA[ch], 0}, false, Dm.p(), ds,
          K, cc, 0, 1, 0);
-    gemm(st, pp, kKindGram, dl(Q.G3), K, K, rrA[l], Op{Dm.d(), nullptr, ds, 0, K}, false,
-         Op{Dm.d(), nullptr, ds, 0, K}, true, G[2].d(), K2, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G3), K, K, rrA[l], Op{Dm.p(), nullptr, ds, 0, K}, false,
+         Op{Dm.p(), nullptr, ds, 0, K}, true, G[2].p(), K2, K, 0, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.Q), cc, rcB[l], rcB[ch],
-         Op{PB_ch.d(), nullptr, (long long)rcB[ch] * cc, 0, rcB[ch]}, true,
-         Op{B->Tc[l].d(), nullptr, B->Tc_stride[l], 0, 2 * rcB[ch], rcB[ch], 0}, false, Qm.d(), qs,
+         Op{PB_ch.p(), nullptr, (long long)rcB[ch] * cc, 0, rcB[ch]}, true,
+         Op{Bd->Tc[l].p(), nullptr, B->Tc_stride[l], 0, 2 * rcB[ch], rcB[ch], 0}, false, Qm.p(), qs,
          K, cc, 0, 1, 0);
-    gemm(st, pp, kKindGram, dl(Q.G3c), K, K, rcB[l], Op{Qm.d(), nullptr, qs, 0, K}, false,
-         Op{Qm.d(), nullptr, qs, 0, K}, true, Gc[2].d(), K2, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G3c), K, K, rcB[l], Op{Qm.p(), nullptr, qs, 0, K}, false,
+         Op{Qm.p(), nullptr, qs, 0, K}, true, Gc[2].p(), K2, K, 0, 0, 1, 0);
     // new transfer matrices
     eig_level(l, K, G, Gc, Ur[l], Uc[l], rank_r[l], rank_c[l], rank_r[ch].as<int>(),
               rank_r[ch].as<int>() + 1, rank_c[ch].as<int>(), rank_c[ch].as<int>() + 1, 2, cc);
@@ -415,76 +427,76 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     }
     const int cl = read_ranks(l, rank_r[l], rank_c[l]);
     cpad[l] = cl;
-    const Op TCr{Ur[l].d(), nullptr, K2, 0, K}, TCc{Uc[l].d(), nullptr, K2, 0, K};
+    const Op TCr{Ur[l].p(), nullptr, K2, 0, K}, TCc{Uc[l].p(), nullptr, K2, 0, K};
     // projections (nonleafproj)
-    Buf PA_l(ctx, (size_t)ncl * cl * rrA[l] * sizeof(double));
-    Buf PB_l(ctx, (size_t)ncl * rcB[l] * cl * sizeof(double));
-    gemm(st, pp, kKindOther, dl(Q.PA), cl, rrA[l], K, TCr, true, Op{Dm.d(), nullptr, ds, 0, K},
-         false, PA_l.d(), (long long)cl * rrA[l], cl, 0, 0, 1, 0);
-    gemm(st, pp, kKindOther, dl(Q.PB), rcB[l], cl, K, Op{Qm.d(), nullptr, qs, 0, K}, true, TCc,
-         false, PB_l.d(), (long long)rcB[l] * cl, rcB[l], 0, 0, 1, 0);
+    Buf PA_l(ctx, (size_t)ncl * cl * rrA[l] * eb, bulk);
+    Buf PB_l(ctx, (size_t)ncl * rcB[l] * cl * eb, bulk);
+    gemm(st, pp, kKindOther, dl(Q.PA), cl, rrA[l], K, TCr, true, Op{Dm.p(), nullptr, ds, 0, K},
+         false, PA_l.p(), (long long)cl * rrA[l], cl, 0, 0, 1, 0);
+    gemm(st, pp, kKindOther, dl(Q.PB), rcB[l], cl, K, Op{Qm.p(), nullptr, qs, 0, K}, true, TCc,
+         false, PB_l.p(), (long long)rcB[l] * cl, rcB[l], 0, 0, 1, 0);
     // collected blocks of this level (NLcollect; admissible ones projected)
     const int ntile = l >= 1 ? s.lev[l - 1].n_nl : 1;
-    Buf Ahat_l(ctx, (size_t)std::max(1, ntile) * 4 * cl * rrB[l] * sizeof(double));
-    Buf Bhat_l(ctx, (size_t)std::max(1, ntile) * 4 * rcA[l] * cl * sizeof(double));
+    Buf Ahat_l(ctx, (size_t)std::max(1, ntile) * 4 * cl * rrB[l] * eb, bulk);
+    Buf Bhat_l(ctx, (size_t)std::max(1, ntile) * 4 * rcA[l] * cl * eb, bulk);
     const long long pas_s = (long long)cl * rcA[l], sbp_s = (long long)rrB[l] * cl;
-    Buf PAS(ctx, (size_t)std::max(1, nn) * pas_s * sizeof(double));
-    Buf SBP(ctx, (size_t)std::max(1, nn) * sbp_s * sizeof(double));
+    Buf PAS(ctx, (size_t)std::max(1, nn) * pas_s * eb, bulk);
+    Buf SBP(ctx, (size_t)std::max(1, nn) * sbp_s * eb, bulk);
     const long long at_s = 4LL * cl * rrB[l], bt_s = 4LL * rcA[l] * cl;
-    gemm(st, pp, kKindOther, dl(Q.AhatNL), cl, rrB[l], K, TCr, true, Op{Y.d(), nullptr, ys, 0, K},
-         false, Ahat_l.d(), at_s, 2 * cl, cl, (long long)rrB[l] * 2 * cl, 1, 0);
+    gemm(st, pp, kKindOther, dl(Q.AhatNL), cl, rrB[l], K, TCr, true, Op{Y.p(), nullptr, ys, 0, K},
+         false, Ahat_l.p(), at_s, 2 * cl, cl, (long long)rrB[l] * 2 * cl, 1, 0);
     gemm(st, pp, kKindOther, dl(Q.PAS), cl, rcA[l], rrA[l],
-         Op{PA_l.d(), nullptr, (long long)cl * rrA[l], 0, cl}, false,
-         Op{A->S[l].d(), nullptr, (long long)rrA[l] * rcA[l], 0, rrA[l]}, false, PAS.d(), pas_s,
+         Op{PA_l.p(), nullptr, (long long)cl * rrA[l], 0, cl}, false,
+         Op{Ad->S[l].p(), nullptr, (long long)rrA[l] * rcA[l], 0, rrA[l]}, false, PAS.p(), pas_s,
          cl, 0, 0, 1, 0);
-    gemm(st, pp, kKindOther, dl(Q.AhatR), cl, rrB[l], rcA[l], Op{PAS.d(), nullptr, pas_s, 0, cl},
-         false, Op{Pi[l].d(), nullptr, (long long)rcA[l] * rrB[l], 0, rcA[l]}, false, Ahat_l.d(),
+    gemm(st, pp, kKindOther, dl(Q.AhatR), cl, rrB[l], rcA[l], Op{PAS.p(), nullptr, pas_s, 0, cl},
+         false, Op{Pi[l].p(), nullptr, (long long)rcA[l] * rrB[l], 0, rcA[l]}, false, Ahat_l.p(),
          at_s, 2 * cl, cl, (long long)rrB[l] * 2 * cl, 1, 0);
-    gemm(st, pp, kKindOther, dl(Q.BhatNL), rcA[l], cl, K, Op{Yc.d(), nullptr, ycs, 0, rcA[l]},
-         false, TCc, false, Bhat_l.d(), bt_s, 2 * rcA[l], rcA[l], (long long)cl * 2 * rcA[l], 1, 0);
+    gemm(st, pp, kKindOther, dl(Q.BhatNL), rcA[l], cl, K, Op{Yc.p(), nullptr, ycs, 0, rcA[l]},
+         false, TCc, false, Bhat_l.p(), bt_s, 2 * rcA[l], rcA[l], (long long)cl * 2 * rcA[l], 1, 0);
     gemm(st, pp, kKindOther, dl(Q.SBP), rrB[l], cl, rcB[l],
-         Op{B->S[l].d(), nullptr, (long long)rrB[l] * rcB[l], 0, rrB[l]}, false,
-         Op{PB_l.d(), nullptr, (long long)rcB[l] * cl, 0, rcB[l]}, false, SBP.d(), sbp_s, rrB[l],
+         Op{Bd->S[l].p(), nullptr, (long long)rrB[l] * rcB[l], 0, rrB[l]}, false,
+         Op{PB_l.p(), nullptr, (long long)rcB[l] * cl, 0, rcB[l]}, false, SBP.p(), sbp_s, rrB[l],
          0, 0, 1, 0);
     gemm(st, pp, kKindOther, dl(Q.BhatR), rcA[l], cl, rrB[l],
-         Op{Pi[l].d(), nullptr, (long long)rcA[l] * rrB[l], 0, rcA[l]}, false,
-         Op{SBP.d(), nullptr, sbp_s, 0, rrB[l]}, false, Bhat_l.d(), bt_s, 2 * rcA[l], rcA[l],
+         Op{Pi[l].p(), nullptr, (long long)rcA[l] * rrB[l], 0, rcA[l]}, false,
+         Op{SBP.p(), nullptr, sbp_s, 0, rrB[l]}, false, Bhat_l.p(), bt_s, 2 * rcA[l], rcA[l],
          (long long)cl * 2 * rcA[l], 1, 0);
     // targets of this level
-    C->S[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * sizeof(double));
-    zero(st, C->S[l].d(), (long long)std::max(1, nn) * cl * cl);
-    SNL[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * sizeof(double));
-    zero(st, SNL[l].d(), (long long)std::max(1, nn) * cl * cl);
+    C->S[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * eb, bulk);
+    zero(st, C->S[l].p(), (long long)std::max(1, nn) * cl * cl);
+    SNL[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * eb, bulk);
+    zero(st, SNL[l].p(), (long long)std::max(1, nn) * cl * cl);
     const int nbt = std::max(1, Q.n_blue_tiles);
-    Buf Acc_l(ctx, (size_t)nbt * 4 * cl * cl * sizeof(double));
-    zero(st, Acc_l.d(), (long long)nbt * 4 * cl * cl);
+    Buf Acc_l(ctx, (size_t)nbt * 4 * cl * cl * eb, bulk);
+    zero(st, Acc_l.p(), (long long)nbt * 4 * cl * cl);
     const long long cs = (long long)cl * cl, acs = 4LL * cl * cl;
     // case 1: T^C_I^T M_IK T^C_K (nonleafcoup_simple, first case)
     {
-      Buf X1(ctx, (size_t)std::max(1, Q.n_case1) * cl * K * sizeof(double));
-      gemm(st, pp, kKindOther, dl(Q.c1X), cl, K, K, TCr, true, AccT, false, X1.d(),
+      Buf X1(ctx, (size_t)std::max(1, Q.n_case1) * cl * K * eb, bulk);
+      gemm(st, pp, kKindOther, dl(Q.c1X), cl, K, K, TCr, true, AccT, false, X1.p(),
            (long long)cl * K, cl, 0, 0, 1, 0);
-      const Op X1o{X1.d(), nullptr, (long long)cl * K, 0, cl};
-      gemm(st, pp, kKindTriple, dl(Q.c1_R), cl, cl, K, X1o, false, TCc, false, C->S[l].d(), cs, cl,
+      const Op X1o{X1.p(), nullptr, (long long)cl * K, 0, cl};
+      gemm(st, pp, kKindTriple, dl(Q.c1_R), cl, cl, K, X1o, false, TCc, false, C->S[l].p(), cs, cl,
            0, 0, 1, 1);
-      gemm(st, pp, kKindTriple, dl(Q.c1_B), cl, cl, K, X1o, false, TCc, false, Acc_l.d(), acs,
+      gemm(st, pp, kKindTriple, dl(Q.c1_B), cl, cl, K, X1o, false, TCc, false, Acc_l.p(), acs,
            2 * cl, cl, (long long)cl * 2 * cl, 1, 1);
     }
     // cases 2-4 (nonleafcoup_simple)
-    const Op AhatT{Ahat_l.d(), nullptr, at_s, 0, 2 * cl, cl, (long long)rrB[l] * 2 * cl};
-    const Op BhatT{Bhat_l.d(), nullptr, bt_s, 0, 2 * rcA[l], rcA[l], (long long)cl * 2 * rcA[l]};
-    const Op SBPo{SBP.d(), nullptr, sbp_s, 0, rrB[l]}, PASo{PAS.d(), nullptr, pas_s, 0, cl};
-    gemm(st, pp, kKindTriple, dl(Q.t_nl_R), cl, cl, rrB[l], AhatT, false, SBPo, false, C->S[l].d(),
+    const Op AhatT{Ahat_l.p(), nullptr, at_s, 0, 2 * cl, cl, (long long)rrB[l] * 2 * cl};
+    const Op BhatT{Bhat_l.p(), nullptr, bt_s, 0, 2 * rcA[l], rcA[l], (long long)cl * 2 * rcA[l]};
+    const Op SBPo{SBP.p(), nullptr, sbp_s, 0, rrB[l]}, PASo{PAS.p(), nullptr, pas_s, 0, cl};
+    gemm(st, pp, kKindTriple, dl(Q.t_nl_R), cl, cl, rrB[l], AhatT, false, SBPo, false, C->S[l].p(),
          cs, cl, 0, 0, 1, 1);
-    gemm(st, pp, kKindTriple, dl(Q.t_nl_B), cl, cl, rrB[l], AhatT, false, SBPo, false, Acc_l.d(),
+    gemm(st, pp, kKindTriple, dl(Q.t_nl_B), cl, cl, rrB[l], AhatT, false, SBPo, false, Acc_l.p(),
          acs, 2 * cl, cl, (long long)cl * 2 * cl, 1, 1);
     gemm(st, pp, kKindTriple, dl(Q.t_nl_NL), cl, cl, rrB[l], AhatT, false, SBPo, false,
-         SNL[l].d(), cs, cl, 0, 0, 1, 1);
-    gemm(st, pp, kKindTriple, dl(Q.t_r_R), cl, cl, rcA[l], PASo, false, BhatT, false, C->S[l].d(),
+         SNL[l].p(), cs, cl, 0, 0, 1, 1);
+    gemm(st, pp, kKindTriple, dl(Q.t_r_R), cl, cl, rcA[l], PASo, false, BhatT, false, C->S[l].p(),
          cs, cl, 0, 0, 1, 1);
-    gemm(st, pp, kKindTriple, dl(Q.t_r_B), cl, cl, rcA[l], PASo, false, BhatT, false, Acc_l.d(),
+    gemm(st, pp, kKindTriple, dl(Q.t_r_B), cl, cl, rcA[l], PASo, false, BhatT, false, Acc_l.p(),
          acs, 2 * cl, cl, (long long)cl * 2 * cl, 1, 1);
-    gemm(st, pp, kKindTriple, dl(Q.t_r_NL), cl, cl, rcA[l], PASo, false, BhatT, false, SNL[l].d(),
+    gemm(st, pp, kKindTriple, dl(Q.t_r_NL), cl, cl, rcA[l], PASo, false, BhatT, false, SNL[l].p(),
          cs, cl, 0, 0, 1, 1);
     PA_ch = std::move(PA_l);
     PB_ch = std::move(PB_l);
@@ -502,27 +514,40 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     const int nn = s.lev[l].size();
     if (SP.X.nout() == 0) continue;
     const long long xs = (long long)K * cl;
-    Buf XS(ctx, (size_t)nn * xs * sizeof(double));
-    gemm(st, pp, kKindOther, dl(SP.X), K, cl, cl, Op{Ur[l].d(), nullptr, (long long)K * K, 0, K},
-         false, Op{SNL[l].d(), nullptr, (long long)cl * cl, 0, cl}, false, XS.d(), xs, K, 0, 0, 1, 0);
-    const Op XSo{XS.d(), nullptr, xs, 0, K, cc, 0};
-    const Op TCc{Uc[l].d(), nullptr, (long long)K * K, 0, K, cc, 0};
-    gemm(st, pp, kKindOther, dl(SP.toR), cc, cc, cl, XSo, false, TCc, true, C->S[ch].d(),
+    Buf XS(ctx, (size_t)nn * xs * eb, bulk);
+    gemm(st, pp, kKindOther, dl(SP.X), K, cl, cl, Op{Ur[l].p(), nullptr, (long long)K * K, 0, K},
+         false, Op{SNL[l].p(), nullptr, (long long)cl * cl, 0, cl}, false, XS.p(), xs, K, 0, 0, 1, 0);
+    const Op XSo{XS.p(), nullptr, xs, 0, K, cc, 0};
+    const Op TCc{Uc[l].p(), nullptr, (long long)K * K, 0, K, cc, 0};
+    gemm(st, pp, kKindOther, dl(SP.toR), cc, cc, cl, XSo, false, TCc, true, C->S[ch].p(),
          (long long)cc * cc, cc, 0, 0, 1, 1);
     if (ch < L)
-      gemm(st, pp, kKindOther, dl(SP.toNL), cc, cc, cl, XSo, false, TCc, true, SNL[ch].d(),
+      gemm(st, pp, kKindOther, dl(SP.toNL), cc, cc, cl, XSo, false, TCc, true, SNL[ch].p(),
            (long long)cc * cc, cc, 0, 0, 1, 1);
     if (ch == L && SP.toF.nout() > 0) {
-      Buf YF(ctx, (size_t)nnL * cc * cc * sizeof(double));
-      Buf ZF(ctx, (size_t)nnL * np * cc * sizeof(double));
-      gemm(st, pp, kKindOther, dl(SP.toF), cc, cc, cl, XSo, false, TCc, true, YF.d(),
+      Buf YF(ctx, (size_t)nnL * cc * cc * eb, bulk);
+      Buf ZF(ctx, (size_t)nnL * np * cc * eb, bulk);
+      gemm(st, pp, kKindOther, dl(SP.toF), cc, cc, cl, XSo, false, TCc, true, YF.p(),
            (long long)cc * cc, cc, 0, 0, 1, 0);
-      gemm(st, pp, kKindOther, dl(SP.F1), np, cc, cc, Op{Ur[L].d(), nullptr, nn2, 0, np}, false,
-           Op{YF.d(), nullptr, (long long)cc * cc, 0, cc}, false, ZF.d(), (long long)np * cc, np,
+      gemm(st, pp, kKindOther, dl(SP.F1), np, cc, cc, Op{Ur[L].p(), nullptr, nn2, 0, np}, false,
+           Op{YF.p(), nullptr, (long long)cc * cc, 0, cc}, false, ZF.p(), (long long)np * cc, np,
            0, 0, 1, 0);
-      gemm(st, pp, kKindOther, dl(SP.F2), np, np, cc, Op{ZF.d(), nullptr, (long long)np * cc, 0, np},
-           false, Op{Uc[L].d(), nullptr, nn2, 0, np}, true, FC.d(), nn2, np, 0, 0, 1, 1);
+      gemm(st, pp, kKindOther, dl(SP.F2), np, np, cc, Op{ZF.p(), nullptr, (long long)np * cc, 0, np},
+           false, Op{Uc[L].p(), nullptr, nn2, 0, np}, true, FC.p(), nn2, np, 0, 0, 1, 1);
     }
+  }
+  if (bulk) {
+    // C is stored in FP64 like every matrix: widen the bulk-computed couplings
+    // and dense blocks
+    auto widen = [&](Buf& b) {
+      const long long n = (long long)(b.bytes() / sizeof(float));
+      if (n <= 0) return;
+      Buf d(ctx, (size_t)n * sizeof(double));
+      H2_HIP(h2k::launch_f2d(b.as<float>(), d.as<double>(), n, st));
+      b = std::move(d);
+    };
+    for (int l = lmin; l <= L; ++l) widen(C->S[l]);
+    widen(FC);
   }
   H2_HIP(hipEventRecord(ev1, st));
   H2_HIP(hipStreamSynchronize(st));
@@ -574,7 +599,9 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   S.symbolic_ms = sym_ms;
   S.n_triples = P.n_triples;
   S.sparsity_constant = s.sparsity_constant();
-  S.flops = canonical_flops(s, A, B, C.get());
+  C->flop_akcol = A->kcol;
+  C->flop_bkrow = B->krow;
+  C->flops_pending = true;
   S.bytes_device = (int64_t)ctx->used;
   if (prof.on) {
     double pms[kKindCount], pfl[kKindCount];

@@ -183,3 +183,65 @@ def test_full_size_plates64k_relative_error(ctx):
         ref = h2.matvec(ctx, dA, h2.matvec(ctx, dA, x))
         e = np.linalg.norm(h2.matvec(ctx, dC, x) - ref) / np.linalg.norm(ref)
         assert e <= 2e-4, e
+
+
+# FP32-bulk mode: block products in FP32 on the matrix cores, Gram sums,
+# eigen-decompositions and bases in FP64.  FP32 rounding of the products adds
+# a relative error of order 1e-6 on top of the truncation error, so the bound
+# is eps + 2e-6; ranks are fixed by FP64 Grams of FP32 factors and agree with
+# the checker like the FP64 path.
+FP32_SLACK = 2e-6
+
+
+@pytest.mark.parametrize("name,eps", [("plates2048", 1e-4), ("random_nonsym", 1e-4),
+                                      ("cube1k", 1e-5), ("ragged777", 1e-3)])
+def test_fp32_bulk_matches_checker(ctx, name, eps):
+    print(f"case fp32_bulk {name} eps {eps}", flush=True)
+    if name == "plates2048":
+        A = B = cases.plates(2048)
+    else:
+        A, B = CASES[name]()
+    dA, dB = _load_pair(ctx, A, B)
+    dC = h2.mmp(ctx, dA, dB, eps, precision="fp32_bulk")
+    d64 = h2.mmp(ctx, dA, dB, eps)
+    Co, info = omp.h2_mmp(A, B, eps)
+    ref = h2ops.to_dense(A) @ h2ops.to_dense(B)
+    Dg = h2.to_dense(ctx, dC, A.n)
+    D64 = h2.to_dense(ctx, d64, A.n)
+    assert rel(Dg, ref) <= eps + FP32_SLACK
+    assert np.linalg.norm(Dg - D64) <= (eps + FP32_SLACK) * np.linalg.norm(D64)
+    exp = h2.export(dC)
+    frac, dmax = _rank_agreement(exp, info)
+    assert frac >= 0.99 and dmax <= 2, (frac, dmax)
+    C = H2Matrix.from_flat(exp)
+    assert C.blocks.same_as(A.blocks)
+    for v in C.V + C.W:
+        assert np.abs(v.T @ v - np.eye(v.shape[1])).max() < 1e-12
+
+
+@pytest.mark.parametrize("name", ["cube1k", "plates1024_leaf16", "random_nonsym"])
+def test_fp32_bulk_exact_mode(ctx, name):
+    print(f"case fp32_bulk exact {name}", flush=True)
+    A, B = CASES[name]()
+    dA, dB = _load_pair(ctx, A, B)
+    dC = h2.mmp(ctx, dA, dB, 0.0, precision="fp32_bulk")
+    ref = h2ops.to_dense(A) @ h2ops.to_dense(B)
+    assert rel(h2.to_dense(ctx, dC, A.n), ref) < 1e-5
+
+
+def test_fp32_bulk_full_size_plates64k(ctx):
+    """plates64k in FP32-bulk mode: the same 2 eps criterion as FP64 and the
+    same ranks on every level."""
+    print("case fp32_bulk plates64k eps 1e-4", flush=True)
+    A = configs.plates64k().build()
+    dA = h2.load(ctx, A.to_flat())
+    dC = h2.mmp(ctx, dA, dA, 1e-4, precision="fp32_bulk")
+    d64 = h2.mmp(ctx, dA, dA, 1e-4)
+    s32, s64 = h2.stats(dC), h2.stats(d64)
+    assert s32["rank_max_r"] == s64["rank_max_r"]
+    rng = np.random.default_rng(12)
+    for _ in range(2):
+        x = rng.standard_normal(A.n)
+        ref = h2.matvec(ctx, dA, h2.matvec(ctx, dA, x))
+        e = np.linalg.norm(h2.matvec(ctx, dC, x) - ref) / np.linalg.norm(ref)
+        assert e <= 2e-4, e
