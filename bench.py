@@ -49,6 +49,27 @@ def cpu_baseline():
 
 
 PEAK = {"fp64": FP64_PEAK_TFLOPS, "fp32_bulk": FP32_PEAK_TFLOPS}
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plates64k_fp32bulk_block_products_hbm.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32-bulk block-product kernels from the
+    committed FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
+    has changed since those counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    src = os.path.join(ROOT, "paper_1908_05218_amd", "csrc", "kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    val, rec = None, None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            val = float(line.split(":")[1])
+        if line.startswith("kernels.hip sha256 (first 16 hex):"):
+            rec = line.split(":")[1].strip()
+    return val if (val is not None and rec == h) else None
 
 
 def run_precision(h2, ctx, dA, n, prec, steps, warmup, eps):
@@ -106,9 +127,11 @@ def run_precision(h2, ctx, dA, n, prec, steps, warmup, eps):
         alg = None
         roof = {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS}
     achieved = (alg / (dms * 1e-3) / 1e12) if (alg and dms > 0) else None
+    traffic = measured_traffic() if (dom == "triple_contraction" and prec == "fp32_bulk") else None
     roof.update({"kernel": dom, "achieved": achieved,
                  "frac": (achieved / roof["peak"]) if achieved else None,
-                 "traffic": None, "avg_launch_ms": dms / max(dl, 1),
+                 "traffic": traffic, "traffic_unit": "bytes per launch",
+                 "avg_launch_ms": dms / max(dl, 1),
                  "launches_per_step": dl / K,
                  "time_share": dms / (sum(v[0] for v in kinds.values()) or 1)})
     breakdown = {k: {"ms_per_step": v[0] / K, "launches_per_step": v[1] / K} for k, v in kinds.items()}
@@ -126,7 +149,21 @@ def main():
                     help="precision of the headline product (the other one is timed beside it)")
     ap.add_argument("--no-compare", action="store_true", help="skip the second precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three plain 1 GiB device copies (scale of the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 1 << 27  # doubles: 1 GiB
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_each": n * 8, "copy_bytes_written_each": n * 8,
+                          "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)

@@ -99,6 +99,41 @@ typedef struct {
  * H2_ERR_UNSUPPORTED (complex), H2_ERR_OOM. */
 h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out);
 
+/* Kernel of h2_build: H2_KERNEL_LAPLACE is 1/(4 pi r), with self_value where
+ * r = 0 (coincident points; e.g. the mean of 1/(4 pi r) over a panel). */
+typedef enum { H2_KERNEL_LAPLACE = 0 } h2_kernel_kind;
+typedef struct {
+  int32_t kind;
+  double self_value;
+} h2_kernel;
+
+/* Construction options of h2_build.  leaf_size: leaves hold at most this many
+ * points (all leaves at one depth); eta: strong admissibility
+ * max(diam t, diam s) <= eta dist(t, s) on tight bounding boxes (Section II);
+ * cheb_order p: nested tensor Chebyshev interpolation of order p per axis,
+ * rank p^3 at every cluster. */
+typedef struct {
+  int64_t leaf_size;
+  double eta;
+  int32_t cheb_order;
+} h2_build_opts;
+
+/* Build the H^2 matrix (Section II: binary cluster tree by median bisection
+ * along the longest axis of each cluster's tight box, block tree by the
+ * admissibility rule, nested bases with transfer matrices, couplings of the
+ * admissible blocks, dense leaf blocks) of `kernel` over the n points xyz
+ * (host, n x 3 row-major, original order; copied).  Tree, block tree, leaf
+ * bases and transfers are built on the host; couplings and dense blocks are
+ * evaluated on the device.  The result matches h2_load of the same matrix
+ * assembled on the host.  share_tree_with (nullable): a matrix of the same
+ * points and options whose structure object is then shared.  Synchronous.
+ * Errors: H2_ERR_ARG (null pointer, n < 1, leaf_size < 1, eta <= 0,
+ * cheb_order outside 1..6, non-finite input, share_tree_with of another size
+ * or structure), H2_ERR_UNSUPPORTED (another kernel), H2_ERR_OOM,
+ * H2_ERR_DEVICE. */
+h2_status h2_build(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* kernel,
+                   const h2_build_opts* opts, h2_mat share_tree_with, h2_mat* out);
+
 /* C = A B (Sections III and IV).  A and B must have been loaded with the
  * same tree (leaf_off, perm) and block partition; C shares them (the
  * product keeps A's partition).  eps >= 0; eps == 0 selects EXACT.

@@ -61,6 +61,16 @@ class _Stats(C.Structure):
                 ("other_flops", C.c_double)]
 
 
+class _Kernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("self_value", C.c_double)]
+
+
+class _BuildOpts(C.Structure):
+    _fields_ = [("leaf_size", C.c_int64), ("eta", C.c_double), ("cheb_order", C.c_int32)]
+
+
+KERNELS = {"laplace": 0}
+
 _lib = None
 
 
@@ -83,9 +93,11 @@ def lib():
         L.h2_set_profiling.argtypes = [vp, C.c_int]
         L.h2_free.argtypes = [vp]
         L.h2_plan_info.argtypes = [C.POINTER(_HostMatrix), C.c_int64, vp, vp, vp, vp]
+        L.h2_build.argtypes = [vp, vp, C.c_int64, C.POINTER(_Kernel), C.POINTER(_BuildOpts), vp,
+                               C.POINTER(vp)]
         L.h2_last_error.restype = C.c_char_p
         L.h2_version.restype = C.c_int
-        for f in ("h2_ctx_create", "h2_load", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
+        for f in ("h2_ctx_create", "h2_load", "h2_build", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
                   "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -205,6 +217,21 @@ def load(ctx, flat):
         setattr(hm, k, keep[k].ctypes.data if keep[k].size else None)
     h = C.c_void_p()
     _check(lib().h2_load(ctx.h, C.byref(hm), C.byref(h)))
+    return Matrix(ctx, h)
+
+
+def build(ctx, points, leaf_size, eta, order, self_value, kernel="laplace", share_tree_with=None):
+    """h2_build: the H^2 matrix of the kernel over `points` (n x 3), built by
+    the library (tree and bases on the host, couplings and dense blocks on
+    the device)."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    if pts.ndim != 2 or pts.shape[1] != 3:
+        raise ValueError("points must be n x 3")
+    k = _Kernel(KERNELS[kernel], float(self_value))
+    o = _BuildOpts(int(leaf_size), float(eta), int(order))
+    h = C.c_void_p()
+    _check(lib().h2_build(ctx.h, _ptr(pts), pts.shape[0], C.byref(k), C.byref(o),
+                          share_tree_with.h if share_tree_with is not None else None, C.byref(h)))
     return Matrix(ctx, h)
 
 

@@ -123,6 +123,7 @@ static void launch_gemm(hipStream_t s, Profiler* prof, int kind, const DevList& 
   a.b_idx = tl.b;
   a.alpha = (T)alpha;
   a.beta = (T)beta;
+  a.triple = kind == kKindTriple;
   hipEvent_t ev = nullptr;
   const double fl = 2.0 * m * n * (double)k * tl.ntask;
   if (prof) prof->begin(kind, fl, &ev);
@@ -227,7 +228,8 @@ std::unique_ptr<DevPlan> upload_plan(h2_ctx ctx, const Plan& p) {
     for (const TaskList* t :
          {&Q.G1, &Q.G1c, &Q.Y, &Q.G2, &Q.Yc, &Q.G2c, &Q.D, &Q.G3, &Q.Q, &Q.G3c, &Q.PA, &Q.PB,
           &Q.AhatNL, &Q.PAS, &Q.AhatR, &Q.BhatNL, &Q.SBP, &Q.BhatR, &Q.c1X, &Q.c1_R, &Q.c1_B,
-          &Q.t_nl_R, &Q.t_nl_B, &Q.t_nl_NL, &Q.t_r_R, &Q.t_r_B, &Q.t_r_NL})
+          &Q.w_nl_R, &Q.w_nl_B, &Q.w_nl_NL, &Q.f_nl_R, &Q.f_nl_B, &Q.f_nl_NL, &Q.w_r_R,
+          &Q.w_r_B, &Q.w_r_NL, &Q.f_r_R, &Q.f_r_B, &Q.f_r_NL, &Q.f_R, &Q.f_B, &Q.f_NL})
       addl(*t);
   for (const SplitPlan& S : p.split)
     for (const TaskList* t : {&S.X, &S.toR, &S.toNL, &S.toF, &S.F1, &S.F2}) addl(*t);
@@ -494,8 +496,14 @@ h2_status h2_set_profiling(h2_ctx ctx, int on) {
   return H2_OK;
 }
 
-h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out) {
-  using namespace h2;
+}  // extern "C"
+
+namespace h2 {
+
+// Upload of a host matrix.  device_blocks: the couplings and dense blocks are
+// left zero on the device for the caller to fill (S, F and their offsets are
+// not read).
+h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_mat* out) {
   if (!ctx || !m || !out) return set_error(H2_ERR_ARG, "null argument");
   if (m->is_complex) return set_error(H2_ERR_UNSUPPORTED, "complex matrices are not supported");
   try {
@@ -507,7 +515,7 @@ h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out) {
     const Structure& s = shape->s;
     const int L = s.L, np = s.npad, nleaf = 1 << L;
     if (!m->krow || !m->kcol || !m->V || !m->W || !m->V_off || !m->W_off || !m->Er_off ||
-        !m->Ec_off || !m->S_off || !m->F_off)
+        !m->Ec_off || (!device_blocks && (!m->S_off || !m->F_off)))
       return set_error(H2_ERR_ARG, "null matrix array");
     const long long ncl = (2LL << L) - 1;
     auto M = std::make_unique<h2_mat_s>();
@@ -578,6 +586,11 @@ h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out) {
     for (int l = 0; l <= L; ++l) {
       const LevelNodes& ln = s.lev[l];
       const long long bs = (long long)M->rr[l] * M->rc[l];
+      if (device_blocks) {
+        M->S[l] = Buf(ctx, (size_t)bs * std::max(1, ln.size()) * sizeof(double));
+        zero(ctx->stream, M->S[l].p(), bs * std::max(1, ln.size()));
+        continue;
+      }
       std::vector<double> h((size_t)bs * std::max(1, ln.size()), 0.0);
       for (int q = 0; q < ln.size(); ++q) {
         const long long g = s.node_base[l] + q;
@@ -594,7 +607,11 @@ h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out) {
       M->S[l] = Buf(ctx, h.size() * sizeof(double));
       H2_HIP(hipMemcpy(M->S[l].d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
     }
-    {
+    if (device_blocks) {
+      const long long nb = (long long)np * np * s.lev[L].size();
+      M->F = Buf(ctx, (size_t)nb * sizeof(double));
+      zero(ctx->stream, M->F.p(), nb);
+    } else {
       const LevelNodes& ln = s.lev[L];
       const long long bs = (long long)np * np;
       std::vector<double> h((size_t)bs * ln.size(), 0.0);
@@ -633,6 +650,14 @@ h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out) {
   } catch (const std::exception& e) {
     return set_error(H2_ERR_INTERNAL, e.what());
   }
+}
+
+}  // namespace h2
+
+extern "C" {
+
+h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out) {
+  return h2::load_impl(ctx, m, false, out);
 }
 
 h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int precision,

@@ -34,6 +34,7 @@ struct BgemmArgs {
   const int* a_idx;    // [ntask]
   const int* b_idx;    // [ntask]
   T alpha, beta;
+  int triple;  // launch under the block-product symbol (k_bgemm_triple)
 };
 
 template <typename T>
@@ -92,6 +93,30 @@ hipError_t launch_segsum(const SegsumArgs<T>& a, hipStream_t s);
 hipError_t launch_gram_norm(const GramNormArgs& a, int nclusters, hipStream_t s);
 // two problem sets (row and column bases of one level) in one launch
 hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStream_t s);
+// Kernel entries of h2_build (1/(4 pi r), self_value at r = 0).  Coupling
+// matrices of one level: node q (rows[q], cols[q], types[q]; type 0 =
+// admissible) gets the kernel at the row and column clusters' p^3 tensor
+// Chebyshev nodes (axes: per cluster 3 x p node coordinates) at
+// S + q*rr*rc (ld rr).  Dense leaf blocks (type 1): the kernel at the points
+// (pts: tree order, 3 per point) of the two leaves at F + q*npad^2 (ld npad).
+struct BuildCouplingArgs {
+  const double* axes;
+  const int *rows, *cols, *types;
+  int nnodes, p, rr, rc;
+  double self_value;
+  double* S;
+};
+struct BuildDenseArgs {
+  const double* pts;
+  const long long* leaf_off;
+  const int *rows, *cols, *types;
+  int nnodes, npad;
+  double self_value;
+  double* F;
+};
+hipError_t launch_build_coupling(const BuildCouplingArgs& a, hipStream_t s);
+hipError_t launch_build_dense(const BuildDenseArgs& a, hipStream_t s);
+
 hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);
 hipError_t launch_fill_f(float* p, float v, long long n, hipStream_t s);
 hipError_t launch_d2f(const double* in, float* out, long long n, hipStream_t s);

@@ -66,7 +66,7 @@ struct Mfma<float> {
 // buffer, then stored into the other buffer (one barrier per step).  Plain
 // and transposed operands both load coalesced.
 template <typename T, int TM, int TN, typename TA, typename TB>
-__global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
+__device__ __forceinline__ void bgemm_body(const BgemmArgs<T>& p) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KC = 16;
   constexpr int SM = TM / 32;  // 16-row subtiles per wave
@@ -188,6 +188,19 @@ __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
     }
 }
 
+// Two entry points over the same body: the block-product ("triple") batches of
+// the coupling step get their own symbol so that traces separate them from
+// the projections, collects, Gram sums and splits.
+template <typename T, int TM, int TN, typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
+  bgemm_body<T, TM, TN, TA, TB>(p);
+}
+
+template <typename T, int TM, int TN, typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_bgemm_triple(BgemmArgs<T> p) {
+  bgemm_body<T, TM, TN, TA, TB>(p);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_segsum(SegsumArgs<T> p) {
   const int per = (p.m * p.n + 255) / 256;
@@ -299,26 +312,36 @@ static hipError_t launch_tile(BgemmArgs<T> a, hipStream_t s) {
   a.tiles_n = cdiv(a.n, TN);
   const long long grid = (long long)a.nout * a.tiles_m * a.tiles_n;
   const dim3 g((unsigned)grid), b(256);
-  if (a.A.f32 && a.B.f32)
-    hipLaunchKernelGGL((k_bgemm<T, TM, TN, float, float>), g, b, 0, s, a);
-  else if (a.A.f32)
-    hipLaunchKernelGGL((k_bgemm<T, TM, TN, float, double>), g, b, 0, s, a);
-  else if (a.B.f32)
-    hipLaunchKernelGGL((k_bgemm<T, TM, TN, double, float>), g, b, 0, s, a);
+#define H2K_LAUNCH(K)                                                  \
+  do {                                                                 \
+    if (a.A.f32 && a.B.f32)                                            \
+      hipLaunchKernelGGL((K<T, TM, TN, float, float>), g, b, 0, s, a);   \
+    else if (a.A.f32)                                                  \
+      hipLaunchKernelGGL((K<T, TM, TN, float, double>), g, b, 0, s, a);  \
+    else if (a.B.f32)                                                  \
+      hipLaunchKernelGGL((K<T, TM, TN, double, float>), g, b, 0, s, a);  \
+    else                                                               \
+      hipLaunchKernelGGL((K<T, TM, TN, double, double>), g, b, 0, s, a); \
+  } while (0)
+  if (a.triple)
+    H2K_LAUNCH(k_bgemm_triple);
   else
-    hipLaunchKernelGGL((k_bgemm<T, TM, TN, double, double>), g, b, 0, s, a);
+    H2K_LAUNCH(k_bgemm);
+#undef H2K_LAUNCH
   return hipGetLastError();
 }
 
-// Workgroup tile: 96x96 when the whole output fits one, otherwise 32 or 64
-// per side.
+// Workgroup tile: the whole output when it fits 96 x 96 (96 x 32, 32 x 96 and
+// 96 x 96 shapes), otherwise 32 or 64 per side.
 template <typename T>
 hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s) {
   if (a.nout <= 0) return hipSuccess;
   if (a.c_f32 != (sizeof(T) == sizeof(float))) return hipErrorInvalidValue;  // C has type T
   const int mx = a.m > a.n ? a.m : a.n;
-  if (mx > 64 && a.m <= 96 && a.n <= 96) return launch_tile<T, 96, 96>(a, s);
   if (a.m <= 32 && a.n <= 32) return launch_tile<T, 32, 32>(a, s);
+  if (a.m > 64 && a.m <= 96 && a.n <= 32) return launch_tile<T, 96, 32>(a, s);
+  if (a.n > 64 && a.n <= 96 && a.m <= 32) return launch_tile<T, 32, 96>(a, s);
+  if (mx > 64 && a.m <= 96 && a.n <= 96) return launch_tile<T, 96, 96>(a, s);
   if (a.m <= 32) return launch_tile<T, 32, 64>(a, s);
   if (a.n <= 32) return launch_tile<T, 64, 32>(a, s);
   return launch_tile<T, 64, 64>(a, s);

@@ -482,22 +482,71 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       gemm(st, pp, kKindTriple, dl(Q.c1_B), cl, cl, K, X1o, false, TCc, false, Acc_l.p(), acs,
            2 * cl, cl, (long long)cl * 2 * cl, 1, 1);
     }
-    // cases 2-4 (nonleafcoup_simple)
+    // cases 2-4 (nonleafcoup_simple), re-associated: for an admissible B
+    // factor sum_J Ahat_IJ (S^B_JK P^B_K) = (sum_J Ahat_IJ S^B_JK) P^B_K, and
+    // for an admissible A factor sum_J (P^A_I S^A_IJ) Bhat_JK =
+    // P^A_I (sum_J S^A_IJ Bhat_JK): the per-triple product shrinks to
+    // k_C x k x k and the projection is applied once per target
     const Op AhatT{Ahat_l.p(), nullptr, at_s, 0, 2 * cl, cl, (long long)rrB[l] * 2 * cl};
     const Op BhatT{Bhat_l.p(), nullptr, bt_s, 0, 2 * rcA[l], rcA[l], (long long)cl * 2 * rcA[l]};
-    const Op SBPo{SBP.p(), nullptr, sbp_s, 0, rrB[l]}, PASo{PAS.p(), nullptr, pas_s, 0, cl};
-    gemm(st, pp, kKindTriple, dl(Q.t_nl_R), cl, cl, rrB[l], AhatT, false, SBPo, false, C->S[l].p(),
-         cs, cl, 0, 0, 1, 1);
-    gemm(st, pp, kKindTriple, dl(Q.t_nl_B), cl, cl, rrB[l], AhatT, false, SBPo, false, Acc_l.p(),
-         acs, 2 * cl, cl, (long long)cl * 2 * cl, 1, 1);
-    gemm(st, pp, kKindTriple, dl(Q.t_nl_NL), cl, cl, rrB[l], AhatT, false, SBPo, false,
-         SNL[l].p(), cs, cl, 0, 0, 1, 1);
-    gemm(st, pp, kKindTriple, dl(Q.t_r_R), cl, cl, rcA[l], PASo, false, BhatT, false, C->S[l].p(),
-         cs, cl, 0, 0, 1, 1);
-    gemm(st, pp, kKindTriple, dl(Q.t_r_B), cl, cl, rcA[l], PASo, false, BhatT, false, Acc_l.p(),
-         acs, 2 * cl, cl, (long long)cl * 2 * cl, 1, 1);
-    gemm(st, pp, kKindTriple, dl(Q.t_r_NL), cl, cl, rcA[l], PASo, false, BhatT, false, SNL[l].p(),
-         cs, cl, 0, 0, 1, 1);
+    const Op SBo{Bd->S[l].p(), nullptr, (long long)rrB[l] * rcB[l], 0, rrB[l]};
+    const Op SAo{Ad->S[l].p(), nullptr, (long long)rrA[l] * rcA[l], 0, rrA[l]};
+    const Op PBo{PB_l.p(), nullptr, (long long)rcB[l] * cl, 0, rcB[l]};
+    const Op PAo{PA_l.p(), nullptr, (long long)cl * rrA[l], 0, cl};
+    struct Tgt {
+      void* p;
+      long long stride;
+      int ld;
+      long long sr, sc;
+    };
+    const Tgt tR{C->S[l].p(), cs, cl, 0, 0}, tB{Acc_l.p(), acs, 2 * cl, cl, (long long)cl * 2 * cl},
+        tNL{SNL[l].p(), cs, cl, 0, 0};
+    const long long wns = (long long)cl * rcB[l], wrs = (long long)rrA[l] * cl;
+    auto stage1 = [&](const TaskList& wnl, const TaskList& wr, Buf& Wn, Buf& Wr) {
+      const DevList &dn = dl(wnl), &dr = dl(wr);
+      if (dn.nout) {
+        Wn = Buf(ctx, (size_t)dn.nout * wns * eb, bulk);
+        gemm(st, pp, kKindTriple, dn, cl, rcB[l], rrB[l], AhatT, false, SBo, false, Wn.p(), wns,
+             cl, 0, 0, 1, 0);
+      }
+      if (dr.nout) {
+        Wr = Buf(ctx, (size_t)dr.nout * wrs * eb, bulk);
+        gemm(st, pp, kKindTriple, dr, rrA[l], cl, rcA[l], SAo, false, BhatT, false, Wr.p(), wrs,
+             rrA[l], 0, 0, 1, 0);
+      }
+    };
+    auto stage2 = [&](const TaskList& fnl, const TaskList& fr, const TaskList& fboth,
+                      const Buf& Wn, const Buf& Wr, const Tgt& t) {
+      if (rcB[l] == rrA[l] && Wn.bytes() && Wr.bytes()) {
+        // one pass over the targets: [W_nl | P^A_I] x [P^B_K ; W_r]
+        gemm(st, pp, kKindTriple, dl(fboth), cl, cl, rcB[l],
+             Op{Wn.p(), PA_l.p(), wns, (long long)cl * rrA[l], cl}, false,
+             Op{PB_l.p(), Wr.p(), (long long)rcB[l] * cl, wrs, rcB[l]}, false, t.p, t.stride, t.ld,
+             t.sr, t.sc, 1, 1);
+        return;
+      }
+      if (Wn.bytes())
+        gemm(st, pp, kKindTriple, dl(fnl), cl, cl, rcB[l], Op{Wn.p(), nullptr, wns, 0, cl}, false,
+             PBo, false, t.p, t.stride, t.ld, t.sr, t.sc, 1, 1);
+      if (Wr.bytes())
+        gemm(st, pp, kKindTriple, dl(fr), cl, cl, rrA[l], PAo, false,
+             Op{Wr.p(), nullptr, wrs, 0, rrA[l]}, false, t.p, t.stride, t.ld, t.sr, t.sc, 1, 1);
+    };
+    {
+      Buf Wn, Wr;
+      stage1(Q.w_nl_R, Q.w_r_R, Wn, Wr);
+      stage2(Q.f_nl_R, Q.f_r_R, Q.f_R, Wn, Wr, tR);
+    }
+    {
+      Buf Wn, Wr;
+      stage1(Q.w_nl_B, Q.w_r_B, Wn, Wr);
+      stage2(Q.f_nl_B, Q.f_r_B, Q.f_B, Wn, Wr, tB);
+    }
+    {
+      Buf Wn, Wr;
+      stage1(Q.w_nl_NL, Q.w_r_NL, Wn, Wr);
+      stage2(Q.f_nl_NL, Q.f_r_NL, Q.f_NL, Wn, Wr, tNL);
+    }
     PA_ch = std::move(PA_l);
     PB_ch = std::move(PB_l);
     Ahat_ch = std::move(Ahat_l);

@@ -133,14 +133,55 @@ int target_of(const Structure& s, int l, int i, int k, int* node) {
 
 struct Seg {
   std::map<std::pair<int, int>, std::vector<std::pair<int, int>>> byout;
-  void add(int sortkey, int outv, int av, int bv) { byout[{sortkey, outv}].push_back({av, bv}); }
+  std::map<std::pair<int, int>, int> pcl;  // per output: cluster of its projection factor
+  void add(int sortkey, int outv, int av, int bv, int pc = -1) {
+    byout[{sortkey, outv}].push_back({av, bv});
+    pcl[{sortkey, outv}] = pc;
+  }
   void emit(TaskList& t) const {
     for (const auto& kv : byout) {
       for (const auto& ab : kv.second) t.add_task(ab.first, ab.second);
       t.close(kv.first.second);
     }
   }
+  // two-stage form: stage 1 sums the tasks of output o into slot o; stage 2
+  // applies the output's projection factor (cluster pcl) to slot o and adds
+  // into the target; pfirst: the factor is the left operand of stage 2
+  void emit2(TaskList& w, TaskList& f, bool pfirst) const {
+    int o = 0;
+    for (const auto& kv : byout) {
+      for (const auto& ab : kv.second) w.add_task(ab.first, ab.second);
+      w.close(enc(o));
+      const int pc = pcl.at(kv.first);
+      if (pfirst)
+        f.add_task(enc(pc), enc(o));
+      else
+        f.add_task(enc(o), enc(pc));
+      f.close(kv.first.second);
+      ++o;
+    }
+  }
 };
+
+// One second-stage list over the targets of both forms, in target order:
+// W_nl[o] P^B_K with selector 0 on both operands, P^A_I W_r[o] with selector 1.
+void merge_second_stage(const Seg& nl, const Seg& r, TaskList& f) {
+  std::map<std::pair<int, int>, std::pair<int, int>> onl, orr;  // key -> (slot, cluster)
+  int o = 0;
+  for (const auto& kv : nl.byout) onl[kv.first] = {o++, nl.pcl.at(kv.first)};
+  o = 0;
+  for (const auto& kv : r.byout) orr[kv.first] = {o++, r.pcl.at(kv.first)};
+  std::map<std::pair<int, int>, int> keys;
+  for (const auto& kv : onl) keys[kv.first] = 1;
+  for (const auto& kv : orr) keys[kv.first] = 1;
+  for (const auto& kv : keys) {
+    auto a = onl.find(kv.first);
+    if (a != onl.end()) f.add_task(enc(a->second.first), enc(a->second.second));
+    auto b = orr.find(kv.first);
+    if (b != orr.end()) f.add_task(enc(b->second.second, 0, 0, 1), enc(b->second.first, 0, 0, 1));
+    f.close(kv.first.second);
+  }
+}
 
 }  // namespace
 
@@ -453,16 +494,19 @@ std::string build_plan(const Structure& s, Plan& p) {
         return "internal: dense target above the leaf level";
       }
       if (t.ta == kNL)
-        s_nl[cls].add(sk, outv, ln.tile_loc[t.qa], enc(t.qb));
+        s_nl[cls].add(sk, outv, ln.tile_loc[t.qa], enc(t.qb), t.k);
       else
-        s_r[cls].add(sk, outv, enc(t.qa), ln.tile_loc[t.qb]);
+        s_r[cls].add(sk, outv, enc(t.qa), ln.tile_loc[t.qb], t.i);
     }
-    s_nl[0].emit(Q.t_nl_R);
-    s_nl[1].emit(Q.t_nl_B);
-    s_nl[2].emit(Q.t_nl_NL);
-    s_r[0].emit(Q.t_r_R);
-    s_r[1].emit(Q.t_r_B);
-    s_r[2].emit(Q.t_r_NL);
+    s_nl[0].emit2(Q.w_nl_R, Q.f_nl_R, false);
+    s_nl[1].emit2(Q.w_nl_B, Q.f_nl_B, false);
+    s_nl[2].emit2(Q.w_nl_NL, Q.f_nl_NL, false);
+    s_r[0].emit2(Q.w_r_R, Q.f_r_R, true);
+    s_r[1].emit2(Q.w_r_B, Q.f_r_B, true);
+    s_r[2].emit2(Q.w_r_NL, Q.f_r_NL, true);
+    merge_second_stage(s_nl[0], s_r[0], Q.f_R);
+    merge_second_stage(s_nl[1], s_r[1], Q.f_B);
+    merge_second_stage(s_nl[2], s_r[2], Q.f_NL);
 
     // ---- split of couplings attached to non-leaf nodes (top-down later)
     SplitPlan& SP = p.split[l];

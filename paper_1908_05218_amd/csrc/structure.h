@@ -83,7 +83,14 @@ struct LevelPlan {
   TaskList G1, G1c, Y, G2, Yc, G2c, D, G3, Q, G3c;
   TaskList PA, PB, AhatNL, PAS, AhatR, BhatNL, SBP, BhatR;
   TaskList c1X, c1_R, c1_B;
-  TaskList t_nl_R, t_nl_B, t_nl_NL, t_r_R, t_r_B, t_r_NL;  // triples: A-type x target class
+  // triples by A-type and target class, re-associated.  NL x R: W_o = sum_J Ahat_IJ S^B_JK
+  // (w_nl_*, output o = slot), then target += W_o P^B_K (f_nl_*); R x NL:
+  // W_o = sum_J S^A_IJ Bhat_JK (w_r_*), then target += P^A_I W_o (f_r_*)
+  TaskList w_nl_R, w_nl_B, w_nl_NL, f_nl_R, f_nl_B, f_nl_NL;
+  TaskList w_r_R, w_r_B, w_r_NL, f_r_R, f_r_B, f_r_NL;
+  // both second stages of a target class in one list (when the two inner
+  // dimensions agree): per target W_nl P^B (selector 0) and P^A W_r (selector 1)
+  TaskList f_R, f_B, f_NL;
   int n_blue_tiles = 0;              // case-1 parents at level l-1 (tiles of Acc_l)
 };
 

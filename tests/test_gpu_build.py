@@ -1,0 +1,89 @@
+"""h2_build (the library's native construction) against the input builder:
+identical tree and block partition, bases, transfers, couplings and dense
+blocks equal to rounding, and products that agree."""
+import numpy as np
+import pytest
+
+import paper_1908_05218_amd as h2
+from h2inputs import configs, points
+from h2inputs.build import LaplaceKernel, chebyshev_h2
+from h2inputs.h2data import H2Matrix
+from h2inputs.structure import BlockTree, ClusterTree
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = h2.Context(0)
+    yield c
+    c.close()
+
+
+def _workloads():
+    w = {
+        "cube1k": configs.cube1k(),
+        "plates2048": configs.plates_n(2048),
+        "plates4096_grid": configs.plates_n(4096),
+        "cube3000_order4": configs.cube_n(3000, seed=3, leaf=40, order=4),
+    }
+    return w
+
+
+def _ragged():
+    pts = points.plates_random(777, 0.1, 1e-3, 7)
+    t = ClusterTree(pts, 12)
+    return pts, chebyshev_h2(t, BlockTree(t, 1.0), LaplaceKernel(1.0), 2)
+
+
+def _compare(dev, ref):
+    for k in ("leaf_off", "perm", "node_off", "node_row", "node_col", "node_type", "krow", "kcol",
+              "V_off", "Er_off", "S_off", "F_off"):
+        assert np.array_equal(np.asarray(dev[k]), np.asarray(ref[k])), k
+    for k in ("V", "W", "Er", "Ec", "S", "F"):
+        a, b = np.asarray(dev[k]), np.asarray(ref[k])
+        assert a.shape == b.shape, k
+        scale = max(np.abs(b).max(), 1e-300)
+        assert np.abs(a - b).max() <= 1e-13 * scale, (k, np.abs(a - b).max() / scale)
+
+
+@pytest.mark.parametrize("name", list(_workloads()))
+def test_build_matches_input_builder(ctx, name):
+    print(f"case build {name}", flush=True)
+    w = _workloads()[name]
+    ref = w.build().to_flat()
+    M = h2.build(ctx, w.pts, w.leaf_size, w.eta, w.order, w.kernel.self_value)
+    _compare(h2.export(M), ref)
+
+
+def test_build_ragged_and_products(ctx):
+    print("case build ragged777", flush=True)
+    pts, A = _ragged()
+    M = h2.build(ctx, pts, 12, 1.0, 2, 1.0)
+    _compare(h2.export(M), A.to_flat())
+    # a product of built matrices equals the product of the loaded ones
+    dA = h2.load(ctx, A.to_flat())
+    C1 = h2.to_dense(ctx, h2.mmp(ctx, M, M, 1e-6), A.n)
+    C2 = h2.to_dense(ctx, h2.mmp(ctx, dA, dA, 1e-6), A.n)
+    assert np.linalg.norm(C1 - C2) <= 1e-12 * np.linalg.norm(C2)
+    # a second matrix sharing the first one's structure
+    M2 = h2.build(ctx, pts, 12, 1.0, 2, 2.0, share_tree_with=M)
+    h2.mmp(ctx, M, M2, 1e-6)
+
+
+def test_build_errors(ctx):
+    pts = points.cube(64, 0)
+    for args in [(pts, 0, 1.0, 2, 1.0), (pts, 8, 0.0, 2, 1.0), (pts, 8, 1.0, 0, 1.0),
+                 (pts, 8, 1.0, 7, 1.0)]:
+        with pytest.raises(h2.H2Error) as e:
+            h2.build(ctx, *args)
+        assert e.value.code == 1
+    bad = pts.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(h2.H2Error) as e:
+        h2.build(ctx, bad, 8, 1.0, 2, 1.0)
+    assert e.value.code == 1
+    M = h2.build(ctx, pts, 8, 1.0, 2, 1.0)
+    with pytest.raises(h2.H2Error) as e:
+        h2.build(ctx, points.cube(65, 0), 8, 1.0, 2, 1.0, share_tree_with=M)
+    assert e.value.code == 1
