@@ -123,9 +123,13 @@ def run_precision(h2, ctx, dA, n, prec, steps, warmup, eps):
     elif dom == "gram_products":
         alg = prof["gram_flops"]
         roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS}
+    elif dom == "eigensolver":
+        # 9 d^3 per eigen-decomposition of a d x d Gram matrix
+        alg = st["eig_flops"] * K
+        roof = {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS}
     else:
         alg = None
-        roof = {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS}
+        roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK[prec]}
     achieved = (alg / (dms * 1e-3) / 1e12) if (alg and dms > 0) else None
     traffic = measured_traffic() if (dom == "triple_contraction" and prec == "fp32_bulk") else None
     roof.update({"kernel": dom, "achieved": achieved,

@@ -203,6 +203,9 @@ typedef struct {
   double gram_ms, other_ms;
   int64_t eig_launches, gram_launches, other_launches;
   double gram_flops, other_flops; /* executed (padded) flops of those launches */
+  /* algorithmic work of the eigen-decompositions: 9 d^3 per Gram matrix of
+   * dimension d (the children's actual ranks; leaf size at the leaves) */
+  double eig_flops;
 } h2_stats_t;
 h2_status h2_stats(h2_mat M, h2_stats_t* out);
 

@@ -58,7 +58,7 @@ class _Stats(C.Structure):
                 ("bytes_device", C.c_int64), ("gram_ms", C.c_double), ("other_ms", C.c_double),
                 ("eig_launches", C.c_int64), ("gram_launches", C.c_int64),
                 ("other_launches", C.c_int64), ("gram_flops", C.c_double),
-                ("other_flops", C.c_double)]
+                ("other_flops", C.c_double), ("eig_flops", C.c_double)]
 
 
 class _Kernel(C.Structure):
@@ -314,4 +314,4 @@ def stats(M):
                 bytes_device=s.bytes_device, gram_ms=s.gram_ms, other_ms=s.other_ms,
                 eig_launches=s.eig_launches, gram_launches=s.gram_launches,
                 other_launches=s.other_launches, gram_flops=s.gram_flops,
-                other_flops=s.other_flops)
+                other_flops=s.other_flops, eig_flops=s.eig_flops)

@@ -23,8 +23,9 @@
 //      with the forward sweep of the right-hand side); eigenvalues closer than
 //      1e-12 ||T|| are handled as clusters (fresh start, orthogonalisation
 //      against the earlier members between solves);
-//   5. classical Gram-Schmidt with one re-orthogonalisation over all kept
-//      vectors, in descending eigenvalue order;
+//   5. block classical Gram-Schmidt with one re-orthogonalisation over all
+//      kept vectors, in descending eigenvalue order (blocks of 8 projected
+//      by the workgroup, orthonormalised inside by one wave);
 //   6. back-transformation by the reflectors, one wave per four vectors held
 //      in registers, and scatter to the padded row layout.
 // Wave reductions use DPP row operations and lane reads, not LDS permutes.
@@ -85,6 +86,15 @@ __device__ double block_sum(double v, double* red) {
 // start of column j of a packed lower triangle of order n
 __device__ __forceinline__ int cs(int j, int n) { return j * n - (j * (j - 1)) / 2; }
 
+// 1/q from the hardware reciprocal refined by two Newton steps (to about one
+// ulp): the Sturm recurrence below only needs its result to a few ulps, the
+// count being exact for a matrix perturbed at that level
+__device__ __forceinline__ double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return fma(r, fma(-q, r, 1.0), r);
+}
+
 // number of eigenvalues below xa and below xb (Sturm counts, two sequences
 // interleaved)
 __device__ __forceinline__ void sturm2(const double* d, const double* e2, int n, double xa,
@@ -95,8 +105,8 @@ __device__ __forceinline__ void sturm2(const double* d, const double* e2, int n,
     const double di = d[i], ei = e2[i - 1];
     if (fabs(qa) < pivmin) qa = -pivmin;
     if (fabs(qb) < pivmin) qb = -pivmin;
-    qa = (di - xa) - ei / qa;
-    qb = (di - xb) - ei / qb;
+    qa = (di - xa) - ei * recip(qa);
+    qb = (di - xb) - ei * recip(qb);
     na += qa < 0.0;
     nb += qb < 0.0;
   }
@@ -110,7 +120,7 @@ __device__ __forceinline__ int sturm1(const double* d, const double* e2, int n, 
   int cnt = q < 0.0;
   for (int i = 1; i < n; ++i) {
     if (fabs(q) < pivmin) q = -pivmin;
-    q = (d[i] - x) - e2[i - 1] / q;
+    q = (d[i] - x) - e2[i - 1] * recip(q);
     cnt += q < 0.0;
   }
   return cnt;
@@ -253,6 +263,135 @@ __device__ void cgs2(double* Z, int ldz, int n, int m, int q0, double* dots, dou
   __syncthreads();
 }
 
+// Block classical Gram-Schmidt with re-orthogonalisation over the k kept
+// vectors (columns of Z, leading dimension ldz), in blocks of at most 8:
+// two passes project a block on all earlier vectors (whole workgroup), then
+// wave 0 orthonormalises inside the block (each vector twice against the
+// block's earlier members; a vector that loses more than half its norm there
+// is re-orthogonalised twice against every earlier vector; then normalised).  Dc: cap doubles of LDS for the
+// projection coefficients.
+template <int NT>
+__device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int m0 = 0; m0 < k;) {
+    int b = k - m0 < 8 ? k - m0 : 8;
+    if (m0 > 0 && b * m0 > cap) b = cap / m0 > 0 ? cap / m0 : 1;
+    for (int pass = 0; pass < 2 && m0 > 0; ++pass) {
+      for (int e = tid; e < m0 * b; e += NT) {
+        const int q = e % m0, j = e / m0;
+        const double* zq = Z + (long long)q * ldz;
+        const double* zj = Z + (long long)(m0 + j) * ldz;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int r = 0;
+        for (; r + 3 < n; r += 4) {
+          s0 += zq[r] * zj[r];
+          s1 += zq[r + 1] * zj[r + 1];
+          s2 += zq[r + 2] * zj[r + 2];
+          s3 += zq[r + 3] * zj[r + 3];
+        }
+        for (; r < n; ++r) s0 += zq[r] * zj[r];
+        Dc[j * m0 + q] = (s0 + s1) + (s2 + s3);
+      }
+      __syncthreads();
+      for (int e = tid; e < n * b; e += NT) {
+        const int r = e % n, j = e / n;
+        const double* dj = Dc + j * m0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int q = 0;
+        for (; q + 3 < m0; q += 4) {
+          s0 += dj[q] * Z[(long long)q * ldz + r];
+          s1 += dj[q + 1] * Z[(long long)(q + 1) * ldz + r];
+          s2 += dj[q + 2] * Z[(long long)(q + 2) * ldz + r];
+          s3 += dj[q + 3] * Z[(long long)(q + 3) * ldz + r];
+        }
+        for (; q < m0; ++q) s0 += dj[q] * Z[(long long)q * ldz + r];
+        Z[(long long)(m0 + j) * ldz + r] -= (s0 + s1) + (s2 + s3);
+      }
+      __syncthreads();
+    }
+    if (wave == 0) {
+      for (int j = 0; j < b; ++j) {
+        double* zj = Z + (long long)(m0 + j) * ldz;
+        double z[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int r = lane + 64 * s;
+          z[s] = r < n ? zj[r] : 0.0;
+        }
+        double t0 = 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) t0 += z[s] * z[s];
+        const double nb2 = wave_sum(t0);
+        for (int pass = 0; pass < 2 && j > 0; ++pass) {
+          double d[8];
+#pragma unroll
+          for (int jj = 0; jj < 8; ++jj) {
+            double t = 0.0;
+            if (jj < j) {
+              const double* zq = Z + (long long)(m0 + jj) * ldz;
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                const int r = lane + 64 * s;
+                if (r < n) t += zq[r] * z[s];
+              }
+            }
+            d[jj] = wave_sum(t);
+          }
+#pragma unroll
+          for (int jj = 0; jj < 8; ++jj) {
+            if (jj < j) {
+              const double* zq = Z + (long long)(m0 + jj) * ldz;
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                const int r = lane + 64 * s;
+                if (r < n) z[s] -= d[jj] * zq[r];
+              }
+            }
+          }
+        }
+        double t = 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) t += z[s] * z[s];
+        double nrm2 = wave_sum(t);
+        if (nrm2 < 0.25 * nb2) {
+          // the vector was nearly dependent on the block's earlier members:
+          // what is left is rounding noise that still leans on the earlier
+          // blocks, so it is re-orthogonalised against every earlier vector,
+          // twice, before it is normalised
+          for (int pass = 0; pass < 2; ++pass)
+            for (int q = 0; q < m0 + j; ++q) {
+              const double* zq = Z + (long long)q * ldz;
+              double u = 0.0;
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                const int r = lane + 64 * s;
+                if (r < n) u += zq[r] * z[s];
+              }
+              const double dq = wave_sum(u);
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                const int r = lane + 64 * s;
+                if (r < n) z[s] -= dq * zq[r];
+              }
+            }
+          t = 0.0;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) t += z[s] * z[s];
+          nrm2 = wave_sum(t);
+        }
+        const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int r = lane + 64 * s;
+          if (r < n) zj[r] = z[s] * inv;
+        }
+      }
+    }
+    __syncthreads();
+    m0 += b;
+  }
+}
+
 }  // namespace
 
 // LDS layout (doubles): [0, zr) packed triangle, later the eigenvectors |
@@ -261,43 +400,16 @@ __device__ void cgs2(double* Z, int ldz, int n, int m, int q0, double* dots, dou
 // red[8].  Cluster scratch (doubles, sstride >= 7 D^2): [0, D^2) packed
 // reflectors (or the whole packed matrix when it is not in LDS) | 4 D^2
 // factor rows | (D|1) D eigenvectors when they are not in LDS.
-template <int NT>
-__global__ __launch_bounds__(NT) void k_eig(EigArgs p0, EigArgs p1, int zr, int dv) {
+// Phases 1-2 for one cluster: gather and Householder tridiagonalisation.
+// PL: the packed triangle P lives in LDS (the caller passes the LDS base, so
+// every access compiles to an LDS instruction), else P is the scratch copy Pg.
+template <int NT, bool PL>
+__device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* Gc, int n, int k1,
+                                               int half, int D, double* P, double* Pg,
+                                               double* dd, double* ee, double* vv,
+                                               double* ybuf, double* trash) {
   constexpr int NW = NT / 64;
-  extern __shared__ double sm[];
-  const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
-  const int c = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int D = p.D;
-  const int half = p.half;
-  const int k1 = p.k1[(long long)c * p.kstride];
-  const int k2 = p.k2 ? p.k2[(long long)c * p.kstride] : 0;
-  const int n = k1 + k2;
-  double* Uc = p.U + (long long)c * p.ustride;
-  for (long long e = tid; e < (long long)D * D; e += NT) Uc[e] = 0.0;
-  if (n > kEigNmax || n <= 0 || k1 < 0 || k2 < 0 || k1 > half || k2 > D - half || D > dv) {
-    if (tid == 0) {
-      p.rank[c] = 0;
-      if (n != 0) p.status[1] = 1;
-    }
-    return;
-  }
-  const int np = n * (n + 1) / 2;
-  double* S = p.scratch + (long long)c * p.sstride;
-  const long long DD = (long long)D * D;
-  double* Pg = S;
-  const bool lds_p = n <= kEigLdsN && np <= zr;
-  double* P = lds_p ? sm : Pg;
-  double* dd = sm + zr;
-  double* ee = dd + dv;
-  double* vv = ee + dv;
-  double* pv = vv + dv;
-  double* ybuf = pv + dv;
-  double* red = ybuf + NT;
-  const double* Gc = p.G + (long long)c * p.gstride;
-
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // 1. gather the live block, packed lower triangle
   int bad = 0;
   for (int j = wave; j < n; j += NW) {
@@ -395,7 +507,7 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs p0, EigArgs p1, int zr, int 
         ybuf[(t * nslot + slot) * 64 + lane] = (s0 + s1) + (s2 + s3);
       }
     }
-    if (lds_p && wave == NW - 1) {
+    if (PL && wave == NW - 1) {
       // the finished reflector to the cluster's scratch
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -404,7 +516,7 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs p0, EigArgs p1, int zr, int 
       }
     }
     __syncthreads();
-    if (!lds_p && wave == 0) {
+    if (!PL && wave == 0) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int r = i + 1 + lane + 64 * s;
@@ -427,18 +539,41 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs p0, EigArgs p1, int zr, int 
     const double K = wave_sum(part);
 #pragma unroll
     for (int s = 0; s < 4; ++s) wr[s] = pr[s] - K * ur[s];
-    // A22 -= u w^T + w u^T on the lower triangle: waves over columns, lanes
-    // over rows
-    for (int cc = i + 1 + wave; cc < n; cc += NW) {
-      double q = 0.0;
-      for (int t = 0; t < T; ++t) q += ybuf[t * ts + (cc - i - 1)];
-      const double uc = vv[cc];
-      const double wc = 2.0 * q - K * uc;
-      const int base = cs(cc, n) - cc;
+    // A22 -= u w^T + w u^T on the lower triangle: waves over columns
+    // (cc = i+1+wave+NW*j), lanes over rows.  Lane j first forms u and w of
+    // the wave's column j; the loop takes them back by lane reads and keeps
+    // four columns' loads in flight
+    {
+      const int J = (m - wave + NW - 1) / NW;
+      double ucol = 0.0, wcol = 0.0;
+      if (lane < J) {
+        const int cc = i + 1 + wave + NW * lane;
+        double q = 0.0;
+        for (int t = 0; t < T; ++t) q += ybuf[t * ts + (cc - i - 1)];
+        ucol = vv[cc];
+        wcol = 2.0 * q - K * ucol;
+      }
+      // branch-free: lanes outside the triangle load and store a trash slot
+      for (int j = 0; j < J; j += 4) {
+        double pc[4][4], uc[4], wc[4];
+        double* ptr[4][4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int r = i + 1 + lane + 64 * s;
-        if (r >= cc && r < n) P[base + r] -= ur[s] * wc + wr[s] * uc;
+        for (int g = 0; g < 4; ++g) {
+          const int cg = j + g < J ? i + 1 + wave + NW * (j + g) : n;
+          uc[g] = read_lane(ucol, j + g);
+          wc[g] = read_lane(wcol, j + g);
+          const int base = cs(cg < n ? cg : 0, n) - cg;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int r = i + 1 + lane + 64 * s;
+            ptr[g][s] = (r >= cg && r < n) ? P + (base + r) : trash;
+            pc[g][s] = *ptr[g][s];
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) *ptr[g][s] = pc[g][s] - (ur[s] * wc[g] + wr[s] * uc[g]);
       }
     }
     __syncthreads();
@@ -453,91 +588,23 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs p0, EigArgs p1, int zr, int 
     }
   }
   __syncthreads();
-  double* e2 = pv;
-  for (int j = tid; j < n - 1; j += NT) e2[j] = ee[j] * ee[j];
-  __syncthreads();
+}
 
-  // 3. eigenvalues.  Gershgorin interval of T
-  double gl = 1e300, gu = -1e300;
-  for (int j = 0; j < n; ++j) {
-    const double rad = (j > 0 ? fabs(ee[j - 1]) : 0.0) + (j < n - 1 ? fabs(ee[j]) : 0.0);
-    gl = fmin(gl, dd[j] - rad);
-    gu = fmax(gu, dd[j] + rad);
-  }
-  const double bnd = fmax(fabs(gl), fabs(gu));
-  const double tol = 4e-16 * bnd + 1e-300;
-  gl -= tol;
-  gu += tol;
-  const double pivmin = 1e-290;
-  double* lam = vv;
-  int k;
-  double lo0 = gl, hi0 = gu;
-  if (p.exact) {
-    k = n;
-  } else {
-    // lambda_1 by multisection over the whole workgroup
-    double lo = gl, hi = gu;
-    for (int it = 0; it < 64 && hi - lo > tol; ++it) {
-      const double h = hi - lo;
-      const double x = lo + h * (double)(tid + 1) / (double)(NT + 1);
-      const int below = sturm1(dd, e2, n, x, pivmin) < n;
-      const int wc = __popcll(__ballot(below));
-      __syncthreads();
-      if (lane == 0) red[wave] = (double)wc;
-      __syncthreads();
-      int cnt = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) cnt += (int)red[w];
-      const double nlo = cnt > 0 ? lo + h * (double)cnt / (double)(NT + 1) : lo;
-      const double nhi = cnt < NT ? lo + h * (double)(cnt + 1) / (double)(NT + 1) : hi;
-      lo = nlo;
-      hi = nhi;
-    }
-    const double l1 = 0.5 * (lo + hi);
-    hi0 = hi;
-    if (!(l1 > 0.0)) {
-      k = 1;
-    } else {
-      const double thr = p.tau * l1;
-      k = n - sturm1(dd, e2, n, thr, pivmin);
-      k = k < 1 ? 1 : (k > n ? n : k);
-      lo0 = fmin(thr, lo) - tol;
-    }
-  }
-  {
-    int G = 8;
-    while (G > 1 && G * k > NT) G >>= 1;
-    const int Q = 2 * G;
-    const double span = hi0 - lo0;
-    int R = span > tol ? (int)ceil(log2(span / tol) / log2((double)(Q + 1))) : 0;
-    R = R > 200 ? 200 : R;
-    const int g = tid / G, jl = tid % G;
-    if (g < k) {
-      const int jt = n - 1 - g;
-      double lo = lo0, hi = hi0;
-      for (int it = 0; it < R; ++it) {
-        const double h = (hi - lo) / (double)(Q + 1);
-        const double xa = lo + h * (double)(2 * jl + 1);
-        const double xb = lo + h * (double)(2 * jl + 2);
-        int ca, cb;
-        sturm2(dd, e2, n, xa, xb, pivmin, ca, cb);
-        double nlo = lo, nhi = hi;
-        if (ca <= jt) nlo = xa;
-        if (cb <= jt) nlo = xb;
-        if (cb > jt) nhi = xb;
-        if (ca > jt) nhi = xa;
-        lo = group_red<true>(nlo, G);
-        hi = group_red<false>(nhi, G);
-      }
-      if (jl == 0) lam[g] = 0.5 * (lo + hi);
-    }
-  }
-  __syncthreads();
-
+// Phases 4-6 for one cluster: eigenvectors of the tridiagonal matrix by
+// inverse iteration (with cluster handling), block Gram-Schmidt, and the
+// back-transformation into the padded rows of Uc.  Z (column-major, leading
+// dimension ldz) is the LDS base or the cluster's scratch; the caller makes
+// the choice at the call site so that each inlined copy addresses one
+// memory kind directly.
+template <int NT>
+__device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, int n, int k, int D,
+                                        long long DD, double* S, const double* Pg,
+                                        const double* dd, const double* ee, const double* lam,
+                                        double bnd, double* pv, double* red, int dv, int k1,
+                                        int half, double* Uc) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // 4. inverse iteration, lane m owns vector m
-  const int ldz = n | 1;
-  const bool z_lds = (long long)ldz * k <= zr;
-  double* Z = z_lds ? sm : S + 5 * DD;
   double* F0 = S + DD;
   double* F1 = S + 2 * DD;
   double* F2 = S + 3 * DD;
@@ -573,8 +640,9 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs p0, EigArgs p1, int zr, int 
     cgs2<NT>(Z, ldz, n, m, c0, dots, red);
   }
 
-  // 5. Gram-Schmidt with re-orthogonalisation over all kept vectors
-  for (int m = 0; m < k; ++m) cgs2<NT>(Z, ldz, n, m, 0, dots, red);
+  // 5. Gram-Schmidt with re-orthogonalisation over all kept vectors, in
+  // blocks (coefficients in the contiguous pv | ybuf region of LDS)
+  bcgs2<NT>(Z, ldz, n, k, pv, dv + NT);
 
   // 6. back-transformation: z <- H_0 ... H_{n-3} z, four vectors per wave
   for (int b0 = wave * kVB; b0 < k; b0 += NW * kVB) {
@@ -637,37 +705,262 @@ __global__ __launch_bounds__(NT) void k_eig(EigArgs p0, EigArgs p1, int zr, int 
       }
     }
   }
-  if (tid == 0) p.rank[c] = k;
+}
+
+// Per-cluster scratch (doubles, eig_scratch_doubles(D)): [0, D^2) packed
+// reflectors (the whole packed matrix when it is not in LDS) | [D^2, 5D^2)
+// factor rows of the inverse iteration | [5D^2, 6D^2 + D) eigenvectors when
+// they are not in LDS | d[D], e[D], lambda[D] and the kept count, handed from
+// one kernel to the next.
+struct ClusterView {
+  int c, D, half, k1, k2, n;
+  bool ok;
+  double* S;
+  double* tri;  // d | e | lambda | k
+};
+
+__device__ __forceinline__ ClusterView cluster_view(const EigArgs& p) {
+  ClusterView v;
+  v.c = blockIdx.x;
+  v.D = p.D;
+  v.half = p.half;
+  v.k1 = p.k1[(long long)v.c * p.kstride];
+  v.k2 = p.k2 ? p.k2[(long long)v.c * p.kstride] : 0;
+  v.n = v.k1 + v.k2;
+  v.ok = !(v.n > kEigNmax || v.n <= 0 || v.k1 < 0 || v.k2 < 0 || v.k1 > v.half ||
+           v.k2 > v.D - v.half);
+  v.S = p.scratch + (long long)v.c * p.sstride;
+  v.tri = v.S + 6LL * v.D * v.D + v.D;
+  return v;
+}
+
+// Kernel 1: gather and tridiagonalise; zero the output columns.  LDS: packed
+// triangle [zr] | d[dv] | e[dv] | v[dv] | p-partials[NT] | red[8].
+template <int NT>
+__global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, int dv) {
+  extern __shared__ double sm[];
+  const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
+  const ClusterView v = cluster_view(p);
+  const int tid = threadIdx.x;
+  double* Uc = p.U + (long long)v.c * p.ustride;
+  for (long long e = tid; e < (long long)v.D * v.D; e += NT) Uc[e] = 0.0;
+  if (!v.ok || v.D > dv) {
+    if (tid == 0) {
+      p.rank[v.c] = 0;
+      if (v.n != 0) p.status[1] = 1;
+    }
+    return;
+  }
+  const int n = v.n;
+  const int np = n * (n + 1) / 2;
+  double* dd = sm + zr;
+  double* ee = dd + dv;
+  double* vv = ee + dv;
+  double* ybuf = vv + dv;
+  const double* Gc = p.G + (long long)v.c * p.gstride;
+  // trash slot of the update: the unused reduction slots in LDS, or the unused
+  // factor area of the scratch when the triangle is not in LDS
+  if (n <= kEigLdsN && np <= zr)
+    gather_tridiag<NT, true>(p, Gc, n, v.k1, v.half, v.D, sm, v.S, dd, ee, vv, ybuf, ybuf + NT);
+  else
+    gather_tridiag<NT, false>(p, Gc, n, v.k1, v.half, v.D, v.S, v.S, dd, ee, vv, ybuf,
+                              v.S + (long long)v.D * v.D);
+  for (int j = tid; j < n; j += NT) {
+    v.tri[j] = dd[j];
+    v.tri[v.D + j] = j < n - 1 ? ee[j] : 0.0;
+  }
+}
+
+// Gershgorin bound of the tridiagonal matrix (d, e)
+__device__ __forceinline__ void gershgorin(const double* dd, const double* ee, int n, double& gl,
+                                           double& gu) {
+  gl = 1e300;
+  gu = -1e300;
+  for (int j = 0; j < n; ++j) {
+    const double rad = (j > 0 ? fabs(ee[j - 1]) : 0.0) + (j < n - 1 ? fabs(ee[j]) : 0.0);
+    gl = fmin(gl, dd[j] - rad);
+    gu = fmax(gu, dd[j] + rad);
+  }
+}
+
+// Kernel 2: eigenvalues and the kept count.  LDS: d | e | e^2 | lambda (dv
+// each) | red[8].
+template <int NT>
+__global__ __launch_bounds__(NT) void k_eig_val(EigArgs p0, EigArgs p1, int dv) {
+  constexpr int NW = NT / 64;
+  extern __shared__ double sm[];
+  const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
+  const ClusterView v = cluster_view(p);
+  if (!v.ok || v.D > dv) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = v.n;
+  double* dd = sm;
+  double* ee = dd + dv;
+  double* e2 = ee + dv;
+  double* lam = e2 + dv;
+  double* red = lam + dv;
+  for (int j = tid; j < n; j += NT) {
+    dd[j] = v.tri[j];
+    ee[j] = v.tri[v.D + j];
+    e2[j] = ee[j] * ee[j];
+  }
+  __syncthreads();
+  double gl, gu;
+  gershgorin(dd, ee, n, gl, gu);
+  const double bnd = fmax(fabs(gl), fabs(gu));
+  const double tol = 4e-16 * bnd + 1e-300;
+  gl -= tol;
+  gu += tol;
+  const double pivmin = 1e-290;
+  int k;
+  double lo0 = gl, hi0 = gu;
+  if (p.exact) {
+    k = n;
+  } else {
+    // lambda_1 by multisection over the whole workgroup
+    double lo = gl, hi = gu;
+    for (int it = 0; it < 64 && hi - lo > tol; ++it) {
+      const double h = hi - lo;
+      const double x = lo + h * (double)(tid + 1) / (double)(NT + 1);
+      const int below = sturm1(dd, e2, n, x, pivmin) < n;
+      const int wc = __popcll(__ballot(below));
+      __syncthreads();
+      if (lane == 0) red[wave] = (double)wc;
+      __syncthreads();
+      int cnt = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) cnt += (int)red[w];
+      const double nlo = cnt > 0 ? lo + h * (double)cnt / (double)(NT + 1) : lo;
+      const double nhi = cnt < NT ? lo + h * (double)(cnt + 1) / (double)(NT + 1) : hi;
+      lo = nlo;
+      hi = nhi;
+    }
+    const double l1 = 0.5 * (lo + hi);
+    hi0 = hi;
+    if (!(l1 > 0.0)) {
+      k = 1;
+    } else {
+      const double thr = p.tau * l1;
+      k = n - sturm1(dd, e2, n, thr, pivmin);
+      k = k < 1 ? 1 : (k > n ? n : k);
+      lo0 = fmin(thr, lo) - tol;
+    }
+  }
+  // the k leading eigenvalues by grouped multisection
+  {
+    int G = 8;
+    while (G > 1 && G * k > NT) G >>= 1;
+    const int Q = 2 * G;
+    const double span = hi0 - lo0;
+    int R = span > tol ? (int)ceil(log2(span / tol) / log2((double)(Q + 1))) : 0;
+    R = R > 200 ? 200 : R;
+    const int g = tid / G, jl = tid % G;
+    if (g < k) {
+      const int jt = n - 1 - g;
+      double lo = lo0, hi = hi0;
+      for (int it = 0; it < R; ++it) {
+        const double h = (hi - lo) / (double)(Q + 1);
+        const double xa = lo + h * (double)(2 * jl + 1);
+        const double xb = lo + h * (double)(2 * jl + 2);
+        int ca, cb;
+        sturm2(dd, e2, n, xa, xb, pivmin, ca, cb);
+        double nlo = lo, nhi = hi;
+        if (ca <= jt) nlo = xa;
+        if (cb <= jt) nlo = xb;
+        if (cb > jt) nhi = xb;
+        if (ca > jt) nhi = xa;
+        lo = group_red<true>(nlo, G);
+        hi = group_red<false>(nhi, G);
+      }
+      if (jl == 0) v.tri[2 * v.D + g] = 0.5 * (lo + hi);
+    }
+  }
+  if (tid == 0) {
+    v.tri[3 * v.D] = (double)k;
+    p.rank[v.c] = k;
+  }
+}
+
+// Kernel 3: eigenvectors, orthogonalisation and back-transformation.  LDS:
+// eigenvectors [zr] (ZL only) | d | e | lambda (dv each) | coefficients
+// [dv + NT] | red[8].
+// ZL: this launch handles the clusters whose eigenvectors fit the LDS region
+// (the other launch those that do not), so that each kernel holds one copy of
+// the phases
+template <int NT, bool ZL>
+__global__ __launch_bounds__(NT) void k_eig_vec(EigArgs p0, EigArgs p1, int zr, int dv) {
+  extern __shared__ double sm[];
+  const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
+  const ClusterView v = cluster_view(p);
+  if (!v.ok || v.D > dv) return;
+  const int tid = threadIdx.x;
+  const int n = v.n;
+  double* dd = sm + (ZL ? zr : 0);
+  double* ee = dd + dv;
+  double* lam = ee + dv;
+  double* pv = lam + dv;
+  double* red = pv + dv + NT;
+  const int k = (int)v.tri[3 * v.D];
+  if (((long long)(n | 1) * k <= zr) != ZL) return;
+  for (int j = tid; j < n; j += NT) {
+    dd[j] = v.tri[j];
+    ee[j] = v.tri[v.D + j];
+    lam[j] = j < k ? v.tri[2 * v.D + j] : 0.0;
+  }
+  __syncthreads();
+  double gl, gu;
+  gershgorin(dd, ee, n, gl, gu);
+  const double bnd = fmax(fabs(gl), fabs(gu));
+  const long long DD = (long long)v.D * v.D;
+  double* Uc = p.U + (long long)v.c * p.ustride;
+  const int ldz = n | 1;
+  if (ZL)
+    eigvecs<NT>(sm, ldz, p, n, k, v.D, DD, v.S, v.S, dd, ee, lam, bnd, pv, red, dv, v.k1, v.half,
+                Uc);
+  else
+    eigvecs<NT>(v.S + 5 * DD, ldz, p, n, k, v.D, DD, v.S, v.S, dd, ee, lam, bnd, pv, red, dv, v.k1,
+                v.half, Uc);
 }
 
 namespace {
 
 int eig_threads(int D) { return D <= 32 ? 64 : D <= 64 ? 128 : D <= 128 ? 256 : 512; }
 
-// Z/packed-triangle region (doubles) for a launch of padded dimension D
-int eig_zr(int D, int nt) {
-  const int dv = D;
-  const int cap = kLdsBytes / 8 - 4 * dv - nt - 8;
-  const int dl = D < kEigLdsN ? D : kEigLdsN;
-  int zr = dl * (dl + 1) / 2;
-  const int zfull = (D | 1) * D;
-  if (zfull <= 8192 && zfull > zr) zr = zfull;
-  if (D > kEigLdsN) zr = cap;
+// LDS regions (doubles) of the packed triangle (kernel 1) and of the
+// eigenvectors (kernel 3) for a launch of padded dimension D
+int tri_zr(int D, int nt) {
+  const int cap = kLdsBytes / 8 - 3 * D - nt - 8;
+  if (D > kEigLdsN) return cap;
+  const int zr = D * (D + 1) / 2;
   return zr < cap ? zr : cap;
+}
+int vec_zr(int D, int nt) {
+  const int cap = kLdsBytes / 8 - 4 * D - nt - 8;
+  const long long zfull = (long long)(D | 1) * D;
+  return zfull < cap ? (int)zfull : cap;
 }
 
 template <int NT>
 hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, hipStream_t s) {
-  const int zr = eig_zr(D, NT);
-  const size_t lds = sizeof(double) * ((size_t)zr + 4 * (size_t)D + NT + 8);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_eig<NT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    if (e != hipSuccess) return e;
+    for (const void* f : {(const void*)k_eig_tri<NT>, (const void*)k_eig_val<NT>,
+                          (const void*)k_eig_vec<NT, true>, (const void*)k_eig_vec<NT, false>}) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+      if (e != hipSuccess) return e;
+    }
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_eig<NT>, dim3(nclusters, 2), dim3(NT), lds, s, a, b, zr, D);
+  const dim3 grid(nclusters, 2);
+  const int zt = tri_zr(D, NT), zv = vec_zr(D, NT);
+  hipLaunchKernelGGL(k_eig_tri<NT>, grid, dim3(NT), sizeof(double) * ((size_t)zt + 3 * D + NT + 8),
+                     s, a, b, zt, D);
+  hipLaunchKernelGGL(k_eig_val<NT>, grid, dim3(NT), sizeof(double) * (4 * (size_t)D + 8), s, a, b,
+                     D);
+  const size_t lv = sizeof(double) * ((size_t)zv + 4 * D + NT + 8);
+  hipLaunchKernelGGL((k_eig_vec<NT, true>), grid, dim3(NT), lv, s, a, b, zv, D);
+  hipLaunchKernelGGL((k_eig_vec<NT, false>), grid, dim3(NT), sizeof(double) * (4 * D + NT + 8), s,
+                     a, b, zv, D);
   return hipGetLastError();
 }
 
@@ -677,6 +970,8 @@ hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStre
   if (nclusters <= 0) return hipSuccess;
   const int D = a.D > b.D ? a.D : b.D;
   if (D > kEigNmax || D < 1) return hipErrorInvalidValue;
+  if (a.sstride < eig_scratch_doubles(a.D) || b.sstride < eig_scratch_doubles(b.D))
+    return hipErrorInvalidValue;
   switch (eig_threads(D)) {
     case 64: return launch_nt<64>(a, b, nclusters, D, s);
     case 128: return launch_nt<128>(a, b, nclusters, D, s);

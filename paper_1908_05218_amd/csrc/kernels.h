@@ -76,7 +76,7 @@ struct EigArgs {
   const int* k2;   // k2[c*kstride]: live rows of the second child (null: none)
   int kstride;
   int half;
-  double* scratch;  // per cluster 7*D*D doubles
+  double* scratch;  // per cluster eig_scratch_doubles(D) doubles
   long long sstride;
   double tau;
   int exact;
@@ -85,6 +85,8 @@ struct EigArgs {
 
 constexpr int kEigNmax = 256;  // largest Gram dimension
 constexpr int kEigLdsN = 195;  // largest dimension whose packed triangle stays in LDS
+// scratch per cluster (doubles) the eigensolver needs for padded dimension D
+inline long long eig_scratch_doubles(int D) { return 7LL * D * D + 4LL * D + 8; }
 
 template <typename T>
 hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s);

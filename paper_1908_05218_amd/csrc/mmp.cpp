@@ -135,6 +135,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   C->Tc_stride.assign(L, 0);
   C->S.resize(L + 1);
   std::vector<int> cpad(L + 1, 16);
+  double eig_flops = 0.0;
   std::vector<Buf> rank_r(L + 1), rank_c(L + 1);
 
   // ---------------------------------------------------------- step 0: Pi
@@ -177,7 +178,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     Uc_ = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
     rank_r_ = Buf(ctx, (size_t)ncl * sizeof(int));
     rank_c_ = Buf(ctx, (size_t)ncl * sizeof(int));
-    Buf scratch(ctx, (size_t)2 * ncl * 7 * D * D * sizeof(double));
+    const long long ss = h2k::eig_scratch_doubles(D);
+    Buf scratch(ctx, (size_t)2 * ncl * ss * sizeof(double));
     h2k::EigArgs ea[2];
     for (int side = 0; side < 2; ++side) {
       h2k::EigArgs& e = ea[side];
@@ -192,8 +194,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       e.k2 = side ? k2c : k2r;
       e.kstride = kstride;
       e.half = half;
-      e.scratch = scratch.d() + (size_t)side * ncl * 7 * D * D;
-      e.sstride = 7LL * D * D;
+      e.scratch = scratch.d() + (size_t)side * ncl * ss;
+      e.sstride = ss;
       e.tau = tau;
       e.exact = exact ? 1 : 0;
       e.status = status.as<int>();
@@ -281,6 +283,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
               leaf_sizes.as<int>(), nullptr, 1, np);
   }
   c = read_ranks(L, rank_r[L], rank_c[L]);
+  for (int c2 = 0; c2 < nleaf; ++c2) eig_flops += 2.0 * 9.0 * std::pow((double)s.leaf_size[c2], 3);
   cpad[L] = c;
   {
     const Op VC{Ur_L.p(), nullptr, nn2, 0, np}, WC{Uc_L.p(), nullptr, nn2, 0, np};
@@ -426,6 +429,11 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       Gc[k].reset();
     }
     const int cl = read_ranks(l, rank_r[l], rank_c[l]);
+    for (int c2 = 0; c2 < ncl; ++c2) {
+      const double dr = (double)(C->krow[cidx(ch, 2 * c2)] + C->krow[cidx(ch, 2 * c2 + 1)]);
+      const double dc = (double)(C->kcol[cidx(ch, 2 * c2)] + C->kcol[cidx(ch, 2 * c2 + 1)]);
+      eig_flops += 9.0 * (dr * dr * dr + dc * dc * dc);
+    }
     cpad[l] = cl;
     const Op TCr{Ur[l].p(), nullptr, K2, 0, K}, TCc{Uc[l].p(), nullptr, K2, 0, K};
     // projections (nonleafproj)
@@ -652,6 +660,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   C->flop_bkrow = B->krow;
   C->flops_pending = true;
   S.bytes_device = (int64_t)ctx->used;
+  S.eig_flops = eig_flops;
   if (prof.on) {
     double pms[kKindCount], pfl[kKindCount];
     long long pl[kKindCount];
