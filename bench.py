@@ -49,6 +49,60 @@ def cpu_baseline():
 
 
 PEAK = {"fp64": FP64_PEAK_TFLOPS, "fp32_bulk": FP32_PEAK_TFLOPS}
+
+
+def serve_stream(n_req, precision, seed=3):
+    """Served latency: a seeded stream of C = A A requests through the
+    library's request loop (h2_submit / h2_wait).  Recipe: N = round(exp(U[ln
+    4096, ln 32768])), the unit cube or the two-plate family with probability
+    1/2 each (plates: random points on both plates, panel self-term), leaf 32,
+    eta 1, Chebyshev 3x3x3, eps 1e-4 or 1e-6 with probability 1/2,
+    exponential inter-arrival times of mean 50 ms; the points are generated
+    before the clock starts.  Latency = submission to completion (build of A
+    on the device plus the product)."""
+    import math
+    import numpy as np
+    import paper_1908_05218_amd as h2
+    from h2inputs import points
+    from h2inputs.build import panel_self_term
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_req):
+        n = int(round(math.exp(rng.uniform(math.log(4096), math.log(32768)))))
+        cube = rng.random() < 0.5
+        eps = 1e-4 if rng.random() < 0.5 else 1e-6
+        gap = float(rng.exponential(0.05))
+        if cube:
+            pts, sv = points.cube(n, 1000 + i), 1.0
+        else:
+            pts = points.plates_random(n, 0.1, 1e-3, 1000 + i)
+            a = (1.0 / (n // 2)) ** 0.5
+            sv = panel_self_term(a, a)
+        reqs.append((n, eps, gap, pts, sv))
+    ctx = h2.Context(0)
+    n0, eps0, _, p0, s0 = reqs[0]
+    warm = h2.submit(ctx, p0, 32, 1.0, 3, s0, eps0, precision=precision)
+    h2.wait(ctx, warm)
+    h2.release(ctx, warm)
+    tickets = []
+    t0 = time.perf_counter()
+    for n, eps, gap, pts, sv in reqs:
+        time.sleep(gap)
+        tickets.append((h2.submit(ctx, pts, 32, 1.0, 3, sv, eps, precision=precision), n))
+    lat, svc, bad = [], [], 0
+    for t, n in tickets:
+        r = h2.wait(ctx, t)
+        bad += r["status"] != 0
+        lat.append(r["total_ms"])
+        svc.append(r["build_ms"] + r["mmp_ms"])
+        h2.release(ctx, t)
+    wall = time.perf_counter() - t0
+    ctx.close()
+    lat = np.array(lat)
+    return {"precision": precision, "requests": n_req, "failed": int(bad),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_service_ms": float(np.mean(svc)),
+            "unknowns_per_s": float(sum(n for _, n in tickets) / wall)}
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plates64k_fp32bulk_block_products_hbm.md")
 
 
@@ -153,6 +207,8 @@ def main():
                     help="precision of the headline product (the other one is timed beside it)")
     ap.add_argument("--no-compare", action="store_true", help="skip the second precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests of the served-latency stream (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device copies (scale of the HBM byte counters)")
     args = ap.parse_args()
@@ -220,6 +276,8 @@ def main():
                     "device_ms_per_step": other["device_ms"], "eps_rel": other["eps_rel"],
                     "speedup_of_headline": other["ms"] / ms,
                     "breakdown": other["breakdown"], "roofline": other["roofline"]}
+    if args.serve_requests > 0:
+        out["serving"] = {p: serve_stream(args.serve_requests, p) for p in ("fp32_bulk", "fp64")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -39,7 +39,8 @@ typedef enum {
   H2_ERR_STRUCTURE = 4,   /* A and B do not share tree and block partition */
   H2_ERR_NUMERIC = 5,     /* non-finite input or result */
   H2_ERR_UNSUPPORTED = 6, /* a size or feature this build does not handle */
-  H2_ERR_INTERNAL = 7
+  H2_ERR_INTERNAL = 7,
+  H2_ERR_BUSY = 8         /* a served request is not finished yet */
 } h2_status;
 
 typedef struct h2_ctx_s* h2_ctx;
@@ -133,6 +134,51 @@ typedef struct {
  * H2_ERR_DEVICE. */
 h2_status h2_build(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* kernel,
                    const h2_build_opts* opts, h2_mat share_tree_with, h2_mat* out);
+
+/* Serving: a request loop of the context.  A request names a point set and
+ * a kernel (built as by h2_build) and a product C = A A at eps; the context's
+ * worker thread runs the requests one at a time in submission order, each
+ * admitted once its device-memory estimate (about 80 KB per point at rank 27,
+ * scaled by cheb_order^3 / 27) fits the context's hbm_budget next to the
+ * results still held; with no budget every request is admitted at once.
+ * A and C of a finished request stay resident until h2_release.  While
+ * requests are in flight the context's other entry points may still be
+ * called from any thread: every entry point of a context is serialised by
+ * the context's lock.  h2_ctx_destroy stops the worker after the request it
+ * is running and drops the queued ones. */
+typedef struct {
+  const double* xyz;  /* host, n x 3 row-major, original order; copied */
+  int64_t n;
+  h2_kernel kernel;
+  h2_build_opts opts;
+  double eps;
+  int32_t trunc_mode; /* h2_trunc_mode */
+  int32_t precision;  /* h2_precision */
+} h2_request;
+
+typedef struct {
+  h2_status status;   /* outcome of the request (H2_OK or the error of its build/product) */
+  h2_mat A, C;        /* owned by the context until h2_release; NULL on error */
+  double queue_ms;    /* submission to admission */
+  double build_ms;    /* h2_build of A */
+  double mmp_ms;      /* h2_mmp of C = A A (host wall time, synchronised) */
+  double total_ms;    /* submission to completion */
+  char message[160];  /* error text when status != H2_OK */
+} h2_result;
+
+/* Queue a request; *ticket identifies it.  Errors: H2_ERR_ARG (null
+ * pointer, invalid sizes, options or eps), H2_ERR_OOM (its estimate exceeds
+ * the context's whole budget). */
+h2_status h2_submit(h2_ctx ctx, const h2_request* req, uint64_t* ticket);
+/* H2_OK when the request has finished (whatever its own status), H2_ERR_BUSY
+ * while it is queued or running, H2_ERR_ARG for an unknown ticket. */
+h2_status h2_poll(h2_ctx ctx, uint64_t ticket);
+/* Block until the request has finished and fill *out.  Errors: H2_ERR_ARG
+ * (unknown ticket or null out). */
+h2_status h2_wait(h2_ctx ctx, uint64_t ticket, h2_result* out);
+/* Free A and C of a finished request and forget its ticket.  Errors:
+ * H2_ERR_ARG (unknown ticket), H2_ERR_BUSY (not finished). */
+h2_status h2_release(h2_ctx ctx, uint64_t ticket);
 
 /* C = A B (Sections III and IV).  A and B must have been loaded with the
  * same tree (leaf_off, perm) and block partition; C shares them (the

@@ -1,5 +1,6 @@
 """MI355X-native accuracy-controlled H^2 matrix-matrix product (Ma and Jiao,
 arXiv 1908.05218): a C-ABI HIP library (libh2mmp.so, include/h2mmp.h) and
 its ctypes binding."""
-from .binding import (Context, Matrix, H2Error, build, declared_functions,  # noqa: F401
-                      export, lib, load, matvec, mmp, plan_info, stats, to_dense)
+from .binding import (Borrowed, Context, Matrix, H2Error, build,  # noqa: F401
+                      declared_functions, export, lib, load, matvec, mmp, plan_info, poll,
+                      release, stats, submit, to_dense, wait)

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libh2mmp.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "h2mmp.h")
 
 H2_OK = 0
+H2_ERR_BUSY = 8
 STATUS_NAMES = {0: "H2_OK", 1: "H2_ERR_ARG", 2: "H2_ERR_DEVICE", 3: "H2_ERR_OOM",
                 4: "H2_ERR_STRUCTURE", 5: "H2_ERR_NUMERIC", 6: "H2_ERR_UNSUPPORTED",
                 7: "H2_ERR_INTERNAL"}
@@ -71,6 +72,17 @@ class _BuildOpts(C.Structure):
 
 KERNELS = {"laplace": 0}
 
+
+class _Request(C.Structure):
+    _fields_ = [("xyz", C.c_void_p), ("n", C.c_int64), ("kernel", _Kernel), ("opts", _BuildOpts),
+                ("eps", C.c_double), ("trunc_mode", C.c_int32), ("precision", C.c_int32)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("A", C.c_void_p), ("C", C.c_void_p),
+                ("queue_ms", C.c_double), ("build_ms", C.c_double), ("mmp_ms", C.c_double),
+                ("total_ms", C.c_double), ("message", C.c_char * 160)]
+
 _lib = None
 
 
@@ -95,9 +107,14 @@ def lib():
         L.h2_plan_info.argtypes = [C.POINTER(_HostMatrix), C.c_int64, vp, vp, vp, vp]
         L.h2_build.argtypes = [vp, vp, C.c_int64, C.POINTER(_Kernel), C.POINTER(_BuildOpts), vp,
                                C.POINTER(vp)]
+        L.h2_submit.argtypes = [vp, C.POINTER(_Request), C.POINTER(C.c_uint64)]
+        L.h2_poll.argtypes = [vp, C.c_uint64]
+        L.h2_wait.argtypes = [vp, C.c_uint64, C.POINTER(_Result)]
+        L.h2_release.argtypes = [vp, C.c_uint64]
         L.h2_last_error.restype = C.c_char_p
         L.h2_version.restype = C.c_int
-        for f in ("h2_ctx_create", "h2_load", "h2_build", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
+        for f in ("h2_ctx_create", "h2_load", "h2_build", "h2_submit", "h2_poll", "h2_wait",
+                  "h2_release", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
                   "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -233,6 +250,55 @@ def build(ctx, points, leaf_size, eta, order, self_value, kernel="laplace", shar
     _check(lib().h2_build(ctx.h, _ptr(pts), pts.shape[0], C.byref(k), C.byref(o),
                           share_tree_with.h if share_tree_with is not None else None, C.byref(h)))
     return Matrix(ctx, h)
+
+
+class Borrowed:
+    """A matrix owned by the library (a served result); valid until the
+    request is released."""
+
+    def __init__(self, ctx, h):
+        self.ctx = ctx
+        self.h = h
+
+    def free(self):
+        pass
+
+
+def submit(ctx, points, leaf_size, eta, order, self_value, eps, mode="accuracy",
+           precision="fp64"):
+    """Queue C = A A for the H^2 matrix of 1/(4 pi r) over `points`; returns
+    the ticket."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    if pts.ndim != 2 or pts.shape[1] != 3:
+        raise ValueError("points must be n x 3")
+    r = _Request(pts.ctypes.data, pts.shape[0], _Kernel(0, float(self_value)),
+                 _BuildOpts(int(leaf_size), float(eta), int(order)), float(eps), TRUNC[mode],
+                 PREC[precision])
+    t = C.c_uint64()
+    _check(lib().h2_submit(ctx.h, C.byref(r), C.byref(t)))
+    return t.value
+
+
+def poll(ctx, ticket):
+    """True when the request has finished."""
+    code = lib().h2_poll(ctx.h, ticket)
+    if code == H2_ERR_BUSY:
+        return False
+    _check(code)
+    return True
+
+
+def wait(ctx, ticket):
+    res = _Result()
+    _check(lib().h2_wait(ctx.h, ticket, C.byref(res)))
+    return dict(status=res.status, A=Borrowed(ctx, C.c_void_p(res.A)) if res.A else None,
+                C=Borrowed(ctx, C.c_void_p(res.C)) if res.C else None, queue_ms=res.queue_ms,
+                build_ms=res.build_ms, mmp_ms=res.mmp_ms, total_ms=res.total_ms,
+                message=res.message.decode(errors="replace"))
+
+
+def release(ctx, ticket):
+    _check(lib().h2_release(ctx.h, ticket))
 
 
 def mmp(ctx, A, B, eps, mode="accuracy", precision="fp64"):

@@ -271,7 +271,7 @@ static inline long long cidx(int l, int c) { return (1LL << l) - 1 + c; }
 // transform up the column tree, couplings, backward transform down the row
 // tree, dense near field.
 void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64_t nrhs) {
-  g_active_ctx = ctx;
+  ActiveCtx active(ctx);
   const Structure& s = M->st();
   Shape& sh = *M->shape;
   hipStream_t st = ctx->stream;
@@ -416,6 +416,7 @@ void* h2_ctx_s::alloc(size_t bytes, bool is_f32) {
   if (it != pool.end()) {
     void* p = it->second;
     pool.erase(it);
+    pooled -= bytes;
     live[p] = bytes;
     if (is_f32) f32.insert(p);
     return p;
@@ -427,6 +428,7 @@ void* h2_ctx_s::alloc(size_t bytes, bool is_f32) {
       used -= kv.first;
     }
     pool.clear();
+    pooled = 0;
     if (used + bytes > budget)
       throw h2::Error(H2_ERR_OOM, "device memory budget exceeded (" + std::to_string(used + bytes) +
                                       " > " + std::to_string(budget) + " bytes)");
@@ -438,6 +440,7 @@ void* h2_ctx_s::alloc(size_t bytes, bool is_f32) {
       used -= kv.first;
     }
     pool.clear();
+    pooled = 0;
     if (hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
       throw h2::Error(H2_ERR_OOM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
@@ -453,6 +456,7 @@ void h2_ctx_s::release(void* p) {
   auto it = live.find(p);
   if (it == live.end()) return;
   pool.emplace(it->second, p);
+  pooled += it->second;
   live.erase(it);
   f32.erase(p);
 }
@@ -488,10 +492,15 @@ h2_status h2_ctx_create(int device, size_t hbm_budget, h2_ctx* out) {
   return H2_OK;
 }
 
-void h2_ctx_destroy(h2_ctx ctx) { delete ctx; }
+void h2_ctx_destroy(h2_ctx ctx) {
+  if (!ctx) return;
+  h2::stop_server(ctx);
+  delete ctx;
+}
 
 h2_status h2_set_profiling(h2_ctx ctx, int on) {
   if (!ctx) return h2::set_error(H2_ERR_ARG, "null context");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   ctx->profiling = on != 0;
   return H2_OK;
 }
@@ -505,6 +514,8 @@ namespace h2 {
 // not read).
 h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_mat* out) {
   if (!ctx || !m || !out) return set_error(H2_ERR_ARG, "null argument");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ActiveCtx active(ctx);
   if (m->is_complex) return set_error(H2_ERR_UNSUPPORTED, "complex matrices are not supported");
   try {
     hipSetDevice(ctx->device);
@@ -669,6 +680,8 @@ h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int
   if (precision < 0 || precision > 1) return set_error(H2_ERR_ARG, "bad precision");
   if (A->shape != B->shape && !A->st().same_as(B->st()))
     return set_error(H2_ERR_STRUCTURE, "A and B differ in tree or block partition");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ActiveCtx active(ctx);
   try {
     hipSetDevice(ctx->device);
     return mmp_impl(ctx, A, B, eps, trunc_mode, precision, C_out);
@@ -684,6 +697,8 @@ h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nr
                     int x_on_device) {
   using namespace h2;
   if (!ctx || !M || !x || !y || nrhs < 1) return set_error(H2_ERR_ARG, "bad argument");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ActiveCtx active(ctx);
   try {
     hipSetDevice(ctx->device);
     const long long n = M->st().n;
@@ -707,6 +722,8 @@ h2_status h2_to_dense(h2_ctx ctx, h2_mat M, double* out, int64_t ld) {
   const long long n = M->st().n;
   if (ld < n) return set_error(H2_ERR_ARG, "ld < n");
   if (n > 16384) return set_error(H2_ERR_UNSUPPORTED, "to_dense is limited to n <= 16384");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ActiveCtx active(ctx);
   try {
     hipSetDevice(ctx->device);
     std::vector<double> eye((size_t)n * n, 0.0);
@@ -751,6 +768,13 @@ h2_status h2_export_size(h2_mat M, h2_export_sizes* sz) {
 }
 
 h2_status h2_export(h2_mat M, const h2_export_buffers* o) {
+  if (M && M->ctx) M->ctx->mu.lock();
+  struct Unlock {
+    h2_mat m;
+    ~Unlock() {
+      if (m && m->ctx) m->ctx->mu.unlock();
+    }
+  } unlock_{M};
   using namespace h2;
   if (!M || !o) return set_error(H2_ERR_ARG, "null argument");
   try {
@@ -853,6 +877,8 @@ h2_status h2_export(h2_mat M, const h2_export_buffers* o) {
 
 h2_status h2_stats(h2_mat M, h2_stats_t* out) {
   if (!M || !out) return h2::set_error(H2_ERR_ARG, "null argument");
+  std::unique_lock<std::recursive_mutex> lk;
+  if (M->ctx) lk = std::unique_lock<std::recursive_mutex>(M->ctx->mu);
   if (M->flops_pending) {
     M->stats.flops = h2::canonical_flops(M->st(), M->flop_akcol, M->flop_bkrow, *M);
     M->flops_pending = false;
@@ -863,7 +889,16 @@ h2_status h2_stats(h2_mat M, h2_stats_t* out) {
   return H2_OK;
 }
 
-void h2_free(h2_mat M) { delete M; }
+void h2_free(h2_mat M) {
+  if (!M) return;
+  h2_ctx c = M->ctx;
+  if (c) {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    delete M;
+  } else {
+    delete M;
+  }
+}
 
 h2_status h2_plan_info(const h2_host_matrix* m, int64_t max_levels, int64_t* triples,
                        int64_t* blue, int64_t* merged, int64_t* lmin) {

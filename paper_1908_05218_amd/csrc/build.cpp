@@ -180,6 +180,8 @@ void lagrange_3d(const std::array<std::vector<double>, 3>& ax, const double* x, 
 h2_status build_impl(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* kernel,
                      const h2_build_opts* opts, h2_mat share, h2_mat* out) {
   if (!ctx || !xyz || !kernel || !opts || !out) return set_error(H2_ERR_ARG, "null argument");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ActiveCtx active(ctx);
   if (n < 1 || opts->leaf_size < 1 || !(opts->eta > 0.0) || opts->cheb_order < 1 ||
       opts->cheb_order > 6)
     return set_error(H2_ERR_ARG, "need n >= 1, leaf_size >= 1, eta > 0, 1 <= cheb_order <= 6");

@@ -4,6 +4,7 @@
 
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
@@ -34,10 +35,18 @@ inline int pad16(long long x) { return (int)(x <= 16 ? 16 : ((x + 15) / 16) * 16
 
 }  // namespace h2
 
+namespace h2 {
+struct Server;
+}
+
 struct h2_ctx_s {
   int device = 0;
   size_t budget = 0;
-  size_t used = 0;
+  size_t used = 0;    // bytes held from the device (live + pooled)
+  size_t pooled = 0;  // of which cached in the pool
+  // serialises every entry point of the context (and its serving worker)
+  std::recursive_mutex mu;
+  h2::Server* server = nullptr;  // serving worker, started by the first h2_submit
   hipStream_t stream = nullptr;
   bool profiling = false;
   std::multimap<size_t, void*> pool;
@@ -189,6 +198,16 @@ std::unique_ptr<DevPlan> upload_plan(h2_ctx ctx, const Plan& p);
 void scan_limits(const TaskList& t, DevList& d);
 // context whose allocations bound-check the launches of the current call
 extern thread_local h2_ctx g_active_ctx;
+// installs the context of an entry point for the duration of the call and
+// restores the previous one (so no thread keeps a pointer to a context that
+// may be destroyed later)
+struct ActiveCtx {
+  h2_ctx prev;
+  explicit ActiveCtx(h2_ctx c) : prev(g_active_ctx) { g_active_ctx = c; }
+  ~ActiveCtx() { g_active_ctx = prev; }
+  ActiveCtx(const ActiveCtx&) = delete;
+  ActiveCtx& operator=(const ActiveCtx&) = delete;
+};
 // FP32-bulk arithmetic for the bulk GEMM kinds during the current product
 extern thread_local bool g_bulk_f32;
 struct BulkScope {
@@ -197,6 +216,9 @@ struct BulkScope {
 };
 
 h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C);
+// stop a context's serving worker (after its current request) and drop the
+// requests still queued; no-op without one
+void stop_server(h2_ctx ctx);
 void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64_t nrhs);
 
 }  // namespace h2

@@ -75,7 +75,7 @@ double canonical_flops(const Structure& s, const std::vector<int64_t>& a_kcol,
 }
 
 h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C_out) {
-  g_active_ctx = ctx;
+  ActiveCtx active(ctx);
   // FP32-bulk: block products on FP32 MFMA over float copies of the operands;
   // Gram sums accumulate in FP64 (the truncation thresholds eigenvalues at
   // eps^2 lambda_1, far below FP32 rounding of a squared quantity), and the
