@@ -243,6 +243,9 @@ typedef struct {
   int64_t contraction_launches;
   double contraction_flops;
   double eig_ms;
+  /* peak device bytes held by live allocations of the context during the
+   * product (operands, the product and its temporaries; blocks cached by
+   * the context's pool are not counted) */
   int64_t bytes_device;
   /* per kernel class (with h2_set_profiling on): summed device ms and
    * launches of the Gram-sum products and of all remaining batched products */

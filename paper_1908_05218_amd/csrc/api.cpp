@@ -410,14 +410,30 @@ void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64
 }  // namespace h2
 
 // ------------------------------------------------------------------ context
+// Allocation sizes are rounded to classes: whole pages up to 1 MiB, above
+// that eight classes per power of two (at most 12.5% rounding), so that the
+// per-level temporaries of one product, and products of nearby sizes, reuse
+// each other's cached blocks.
+static size_t size_class(size_t b) {
+  b = (b + 4095) & ~(size_t)4095;
+  if (b <= ((size_t)1 << 20)) return b;
+  const int e = 63 - __builtin_clzll((unsigned long long)b);
+  const size_t step = (size_t)1 << (e - 3);
+  return (b + step - 1) & ~(step - 1);
+}
+
 void* h2_ctx_s::alloc(size_t bytes, bool is_f32) {
-  bytes = (bytes + 4095) & ~(size_t)4095;
-  auto it = pool.find(bytes);
-  if (it != pool.end()) {
+  bytes = size_class(bytes);
+  // best fit among the cached blocks, wasting at most a quarter
+  auto it = pool.lower_bound(bytes);
+  if (it != pool.end() && it->first <= bytes + bytes / 4) {
     void* p = it->second;
+    const size_t got = it->first;
     pool.erase(it);
-    pooled -= bytes;
-    live[p] = bytes;
+    pooled -= got;
+    live[p] = got;
+    live_bytes += got;
+    peak_live = std::max(peak_live, live_bytes);
     if (is_f32) f32.insert(p);
     return p;
   }
@@ -435,6 +451,9 @@ void* h2_ctx_s::alloc(size_t bytes, bool is_f32) {
   }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
+    // the failed call leaves its error as the thread's last error, which the
+    // next launch check would report: clear it before the retry
+    (void)hipGetLastError();
     for (auto& kv : pool) {
       hipFree(kv.second);
       used -= kv.first;
@@ -448,8 +467,27 @@ void* h2_ctx_s::alloc(size_t bytes, bool is_f32) {
   }
   used += bytes;
   live[p] = bytes;
+  live_bytes += bytes;
+  peak_live = std::max(peak_live, live_bytes);
   if (is_f32) f32.insert(p);
   return p;
+}
+
+void h2_ctx_s::trim(size_t keep) {
+  if (pooled <= keep) return;
+  if (stream) hipStreamSynchronize(stream);
+  while (pooled > keep && !pool.empty()) {
+    auto it = std::prev(pool.end());
+    hipFree(it->second);
+    used -= it->first;
+    pooled -= it->first;
+    pool.erase(it);
+  }
+}
+
+void h2_ctx_s::end_call(size_t start) {
+  const size_t base = std::min(start, live_bytes);
+  trim(2 * (peak_live > base ? peak_live - base : 0));
 }
 
 void h2_ctx_s::release(void* p) {
@@ -457,6 +495,7 @@ void h2_ctx_s::release(void* p) {
   if (it == live.end()) return;
   pool.emplace(it->second, p);
   pooled += it->second;
+  live_bytes -= it->second;
   live.erase(it);
   f32.erase(p);
 }
@@ -682,15 +721,20 @@ h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int
     return set_error(H2_ERR_STRUCTURE, "A and B differ in tree or block partition");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   ActiveCtx active(ctx);
+  const size_t start = ctx->live_bytes;
+  ctx->mark();
+  h2_status r;
   try {
     hipSetDevice(ctx->device);
-    return mmp_impl(ctx, A, B, eps, trunc_mode, precision, C_out);
+    r = mmp_impl(ctx, A, B, eps, trunc_mode, precision, C_out);
   } catch (const Error& e) {
     (void)hipGetLastError();
-    return set_error(e.code, e.msg);
+    r = set_error(e.code, e.msg);
   } catch (const std::exception& e) {
-    return set_error(H2_ERR_INTERNAL, e.what());
+    r = set_error(H2_ERR_INTERNAL, e.what());
   }
+  ctx->end_call(start);
+  return r;
 }
 
 h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nrhs,

@@ -5,7 +5,8 @@
 // kept count follows from the truncation threshold tau * lambda_1.
 //
 // One workgroup per cluster (NT = 64..512 lanes chosen from the padded
-// dimension), FP64 throughout:
+// dimension D <= 512; each lane holds up to SL = 4 or 8 rows of a column, so
+// one wave covers a whole column), FP64 throughout:
 //   1. gather the live rows/columns (the children's actual ranks) into a
 //      packed lower triangle: in LDS for n <= kEigLdsN, else in the cluster's
 //      scratch;
@@ -270,7 +271,7 @@ __device__ void cgs2(double* Z, int ldz, int n, int m, int q0, double* dots, dou
 // block's earlier members; a vector that loses more than half its norm there
 // is re-orthogonalised twice against every earlier vector; then normalised).  Dc: cap doubles of LDS for the
 // projection coefficients.
-template <int NT>
+template <int NT, int SL>
 __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int m0 = 0; m0 < k;) {
@@ -312,15 +313,15 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
     if (wave == 0) {
       for (int j = 0; j < b; ++j) {
         double* zj = Z + (long long)(m0 + j) * ldz;
-        double z[4];
+        double z[SL];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < SL; ++s) {
           const int r = lane + 64 * s;
           z[s] = r < n ? zj[r] : 0.0;
         }
         double t0 = 0.0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) t0 += z[s] * z[s];
+        for (int s = 0; s < SL; ++s) t0 += z[s] * z[s];
         const double nb2 = wave_sum(t0);
         for (int pass = 0; pass < 2 && j > 0; ++pass) {
           double d[8];
@@ -330,7 +331,7 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
             if (jj < j) {
               const double* zq = Z + (long long)(m0 + jj) * ldz;
 #pragma unroll
-              for (int s = 0; s < 4; ++s) {
+              for (int s = 0; s < SL; ++s) {
                 const int r = lane + 64 * s;
                 if (r < n) t += zq[r] * z[s];
               }
@@ -342,7 +343,7 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
             if (jj < j) {
               const double* zq = Z + (long long)(m0 + jj) * ldz;
 #pragma unroll
-              for (int s = 0; s < 4; ++s) {
+              for (int s = 0; s < SL; ++s) {
                 const int r = lane + 64 * s;
                 if (r < n) z[s] -= d[jj] * zq[r];
               }
@@ -351,7 +352,7 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
         }
         double t = 0.0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) t += z[s] * z[s];
+        for (int s = 0; s < SL; ++s) t += z[s] * z[s];
         double nrm2 = wave_sum(t);
         if (nrm2 < 0.25 * nb2) {
           // the vector was nearly dependent on the block's earlier members:
@@ -363,25 +364,25 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
               const double* zq = Z + (long long)q * ldz;
               double u = 0.0;
 #pragma unroll
-              for (int s = 0; s < 4; ++s) {
+              for (int s = 0; s < SL; ++s) {
                 const int r = lane + 64 * s;
                 if (r < n) u += zq[r] * z[s];
               }
               const double dq = wave_sum(u);
 #pragma unroll
-              for (int s = 0; s < 4; ++s) {
+              for (int s = 0; s < SL; ++s) {
                 const int r = lane + 64 * s;
                 if (r < n) z[s] -= dq * zq[r];
               }
             }
           t = 0.0;
 #pragma unroll
-          for (int s = 0; s < 4; ++s) t += z[s] * z[s];
+          for (int s = 0; s < SL; ++s) t += z[s] * z[s];
           nrm2 = wave_sum(t);
         }
         const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < SL; ++s) {
           const int r = lane + 64 * s;
           if (r < n) zj[r] = z[s] * inv;
         }
@@ -403,7 +404,7 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
 // Phases 1-2 for one cluster: gather and Householder tridiagonalisation.
 // PL: the packed triangle P lives in LDS (the caller passes the LDS base, so
 // every access compiles to an LDS instruction), else P is the scratch copy Pg.
-template <int NT, bool PL>
+template <int NT, int SL, bool PL>
 __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* Gc, int n, int k1,
                                                int half, int D, double* P, double* Pg,
                                                double* dd, double* ee, double* vv,
@@ -430,10 +431,10 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
   for (int i = 0; i + 2 < n; ++i) {
     const int m = n - i - 1;
     const int ci = cs(i, n);
-    double xr[4], ur[4];
+    double xr[SL], ur[SL];
     double part = 0.0;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < SL; ++s) {
       const int r = i + 1 + lane + 64 * s;
       xr[s] = r < n ? P[ci + r - i] : 0.0;
       part += xr[s] * xr[s];
@@ -444,7 +445,7 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
     if (!(nx > 0.0)) {  // column already reduced: H_i = I
       if (wave == 0) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < SL; ++s) {
           const int r = i + 1 + lane + 64 * s;
           if (r < n) Pg[ci + r - i] = 0.0;
         }
@@ -460,13 +461,13 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
     const double v0 = x0 - alpha;
     const double vn = sqrt(xx - x0 * x0 + v0 * v0);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < SL; ++s) {
       const int r = i + 1 + lane + 64 * s;
       ur[s] = r < n ? (r == i + 1 ? v0 : xr[s]) / vn : 0.0;
     }
     if (wave == 0) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < SL; ++s) {
         const int r = i + 1 + lane + 64 * s;
         if (r < n) vv[r] = ur[s];
       }
@@ -510,7 +511,7 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
     if (PL && wave == NW - 1) {
       // the finished reflector to the cluster's scratch
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < SL; ++s) {
         const int r = i + 1 + lane + 64 * s;
         if (r < n) Pg[ci + r - i] = ur[s];
       }
@@ -518,17 +519,17 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
     __syncthreads();
     if (!PL && wave == 0) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < SL; ++s) {
         const int r = i + 1 + lane + 64 * s;
         if (r < n) Pg[ci + r - i] = ur[s];
       }
     }
     // K = u . p and w = p - K u, by every wave
     const int ts = nslot * 64;
-    double pr[4], wr[4];
+    double pr[SL], wr[SL];
     part = 0.0;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < SL; ++s) {
       const int r = i + 1 + lane + 64 * s;
       double q = 0.0;
       if (r < n)
@@ -538,7 +539,7 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
     }
     const double K = wave_sum(part);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) wr[s] = pr[s] - K * ur[s];
+    for (int s = 0; s < SL; ++s) wr[s] = pr[s] - K * ur[s];
     // A22 -= u w^T + w u^T on the lower triangle: waves over columns
     // (cc = i+1+wave+NW*j), lanes over rows.  Lane j first forms u and w of
     // the wave's column j; the loop takes them back by lane reads and keeps
@@ -555,8 +556,8 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
       }
       // branch-free: lanes outside the triangle load and store a trash slot
       for (int j = 0; j < J; j += 4) {
-        double pc[4][4], uc[4], wc[4];
-        double* ptr[4][4];
+        double pc[4][SL], uc[4], wc[4];
+        double* ptr[4][SL];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
           const int cg = j + g < J ? i + 1 + wave + NW * (j + g) : n;
@@ -564,7 +565,7 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
           wc[g] = read_lane(wcol, j + g);
           const int base = cs(cg < n ? cg : 0, n) - cg;
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
+          for (int s = 0; s < SL; ++s) {
             const int r = i + 1 + lane + 64 * s;
             ptr[g][s] = (r >= cg && r < n) ? P + (base + r) : trash;
             pc[g][s] = *ptr[g][s];
@@ -573,7 +574,7 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
 #pragma unroll
         for (int g = 0; g < 4; ++g)
 #pragma unroll
-          for (int s = 0; s < 4; ++s) *ptr[g][s] = pc[g][s] - (ur[s] * wc[g] + wr[s] * uc[g]);
+          for (int s = 0; s < SL; ++s) *ptr[g][s] = pc[g][s] - (ur[s] * wc[g] + wr[s] * uc[g]);
       }
     }
     __syncthreads();
@@ -596,7 +597,7 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
 // dimension ldz) is the LDS base or the cluster's scratch; the caller makes
 // the choice at the call site so that each inlined copy addresses one
 // memory kind directly.
-template <int NT>
+template <int NT, int SL>
 __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, int n, int k, int D,
                                         long long DD, double* S, const double* Pg,
                                         const double* dd, const double* ee, const double* lam,
@@ -642,35 +643,35 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
 
   // 5. Gram-Schmidt with re-orthogonalisation over all kept vectors, in
   // blocks (coefficients in the contiguous pv | ybuf region of LDS)
-  bcgs2<NT>(Z, ldz, n, k, pv, dv + NT);
+  bcgs2<NT, SL>(Z, ldz, n, k, pv, dv + NT);
 
   // 6. back-transformation: z <- H_0 ... H_{n-3} z, four vectors per wave
   for (int b0 = wave * kVB; b0 < k; b0 += NW * kVB) {
-    double z[kVB][4];
+    double z[kVB][SL];
 #pragma unroll
     for (int v = 0; v < kVB; ++v)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < SL; ++s) {
         const int r = lane + 64 * s;
         z[v][s] = (b0 + v < k && r < n) ? Z[(long long)(b0 + v) * ldz + r] : 0.0;
       }
-    double un[4];
+    double un[SL];
     if (n >= 3) {
       const int ci = cs(n - 3, n);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < SL; ++s) {
         const int r = lane + 64 * s;
         un[s] = (r > n - 3 && r < n) ? Pg[ci + r - (n - 3)] : 0.0;
       }
     }
     for (int i = n - 3; i >= 0; --i) {
-      double u[4];
+      double u[SL];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) u[s] = un[s];
+      for (int s = 0; s < SL; ++s) u[s] = un[s];
       if (i > 0) {  // fetch the next reflector while this one is applied
         const int cn = cs(i - 1, n);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < SL; ++s) {
           const int r = lane + 64 * s;
           un[s] = (r > i - 1 && r < n) ? Pg[cn + r - (i - 1)] : 0.0;
         }
@@ -680,7 +681,7 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
       for (int v = 0; v < kVB; ++v) {
         double t = 0.0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) t += u[s] * z[v][s];
+        for (int s = 0; s < SL; ++s) t += u[s] * z[v][s];
         d[v] = t;
       }
 #pragma unroll
@@ -688,14 +689,14 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
 #pragma unroll
       for (int v = 0; v < kVB; ++v)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) z[v][s] -= d[v] * u[s];
+        for (int s = 0; s < SL; ++s) z[v][s] -= d[v] * u[s];
     }
 #pragma unroll
     for (int v = 0; v < kVB; ++v) {
       const int m = b0 + v;
       if (m < k) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < SL; ++s) {
           const int r = lane + 64 * s;
           if (r < n) {
             const int orow = r < k1 ? r : half + (r - k1);
@@ -736,7 +737,7 @@ __device__ __forceinline__ ClusterView cluster_view(const EigArgs& p) {
 
 // Kernel 1: gather and tridiagonalise; zero the output columns.  LDS: packed
 // triangle [zr] | d[dv] | e[dv] | v[dv] | p-partials[NT] | red[8].
-template <int NT>
+template <int NT, int SL>
 __global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, int dv) {
   extern __shared__ double sm[];
   const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
@@ -761,9 +762,9 @@ __global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, 
   // trash slot of the update: the unused reduction slots in LDS, or the unused
   // factor area of the scratch when the triangle is not in LDS
   if (n <= kEigLdsN && np <= zr)
-    gather_tridiag<NT, true>(p, Gc, n, v.k1, v.half, v.D, sm, v.S, dd, ee, vv, ybuf, ybuf + NT);
+    gather_tridiag<NT, SL, true>(p, Gc, n, v.k1, v.half, v.D, sm, v.S, dd, ee, vv, ybuf, ybuf + NT);
   else
-    gather_tridiag<NT, false>(p, Gc, n, v.k1, v.half, v.D, v.S, v.S, dd, ee, vv, ybuf,
+    gather_tridiag<NT, SL, false>(p, Gc, n, v.k1, v.half, v.D, v.S, v.S, dd, ee, vv, ybuf,
                               v.S + (long long)v.D * v.D);
   for (int j = tid; j < n; j += NT) {
     v.tri[j] = dd[j];
@@ -887,7 +888,7 @@ __global__ __launch_bounds__(NT) void k_eig_val(EigArgs p0, EigArgs p1, int dv) 
 // ZL: this launch handles the clusters whose eigenvectors fit the LDS region
 // (the other launch those that do not), so that each kernel holds one copy of
 // the phases
-template <int NT, bool ZL>
+template <int NT, int SL, bool ZL>
 __global__ __launch_bounds__(NT) void k_eig_vec(EigArgs p0, EigArgs p1, int zr, int dv) {
   extern __shared__ double sm[];
   const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
@@ -915,10 +916,10 @@ __global__ __launch_bounds__(NT) void k_eig_vec(EigArgs p0, EigArgs p1, int zr, 
   double* Uc = p.U + (long long)v.c * p.ustride;
   const int ldz = n | 1;
   if (ZL)
-    eigvecs<NT>(sm, ldz, p, n, k, v.D, DD, v.S, v.S, dd, ee, lam, bnd, pv, red, dv, v.k1, v.half,
+    eigvecs<NT, SL>(sm, ldz, p, n, k, v.D, DD, v.S, v.S, dd, ee, lam, bnd, pv, red, dv, v.k1, v.half,
                 Uc);
   else
-    eigvecs<NT>(v.S + 5 * DD, ldz, p, n, k, v.D, DD, v.S, v.S, dd, ee, lam, bnd, pv, red, dv, v.k1,
+    eigvecs<NT, SL>(v.S + 5 * DD, ldz, p, n, k, v.D, DD, v.S, v.S, dd, ee, lam, bnd, pv, red, dv, v.k1,
                 v.half, Uc);
 }
 
@@ -940,12 +941,13 @@ int vec_zr(int D, int nt) {
   return zfull < cap ? (int)zfull : cap;
 }
 
-template <int NT>
+template <int NT, int SL>
 hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    for (const void* f : {(const void*)k_eig_tri<NT>, (const void*)k_eig_val<NT>,
-                          (const void*)k_eig_vec<NT, true>, (const void*)k_eig_vec<NT, false>}) {
+    for (const void* f : {(const void*)k_eig_tri<NT, SL>, (const void*)k_eig_val<NT>,
+                          (const void*)k_eig_vec<NT, SL, true>,
+                          (const void*)k_eig_vec<NT, SL, false>}) {
       hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
       if (e != hipSuccess) return e;
     }
@@ -953,13 +955,13 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
   }
   const dim3 grid(nclusters, 2);
   const int zt = tri_zr(D, NT), zv = vec_zr(D, NT);
-  hipLaunchKernelGGL(k_eig_tri<NT>, grid, dim3(NT), sizeof(double) * ((size_t)zt + 3 * D + NT + 8),
+  hipLaunchKernelGGL((k_eig_tri<NT, SL>), grid, dim3(NT), sizeof(double) * ((size_t)zt + 3 * D + NT + 8),
                      s, a, b, zt, D);
   hipLaunchKernelGGL(k_eig_val<NT>, grid, dim3(NT), sizeof(double) * (4 * (size_t)D + 8), s, a, b,
                      D);
   const size_t lv = sizeof(double) * ((size_t)zv + 4 * D + NT + 8);
-  hipLaunchKernelGGL((k_eig_vec<NT, true>), grid, dim3(NT), lv, s, a, b, zv, D);
-  hipLaunchKernelGGL((k_eig_vec<NT, false>), grid, dim3(NT), sizeof(double) * (4 * D + NT + 8), s,
+  hipLaunchKernelGGL((k_eig_vec<NT, SL, true>), grid, dim3(NT), lv, s, a, b, zv, D);
+  hipLaunchKernelGGL((k_eig_vec<NT, SL, false>), grid, dim3(NT), sizeof(double) * (4 * D + NT + 8), s,
                      a, b, zv, D);
   return hipGetLastError();
 }
@@ -972,11 +974,13 @@ hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStre
   if (D > kEigNmax || D < 1) return hipErrorInvalidValue;
   if (a.sstride < eig_scratch_doubles(a.D) || b.sstride < eig_scratch_doubles(b.D))
     return hipErrorInvalidValue;
+  // SL row slots per lane: a wave holds a column of up to 64 SL rows
+  if (D > 256) return launch_nt<512, 8>(a, b, nclusters, D, s);
   switch (eig_threads(D)) {
-    case 64: return launch_nt<64>(a, b, nclusters, D, s);
-    case 128: return launch_nt<128>(a, b, nclusters, D, s);
-    case 256: return launch_nt<256>(a, b, nclusters, D, s);
-    default: return launch_nt<512>(a, b, nclusters, D, s);
+    case 64: return launch_nt<64, 4>(a, b, nclusters, D, s);
+    case 128: return launch_nt<128, 4>(a, b, nclusters, D, s);
+    case 256: return launch_nt<256, 4>(a, b, nclusters, D, s);
+    default: return launch_nt<512, 4>(a, b, nclusters, D, s);
   }
 }
 

@@ -42,8 +42,10 @@ struct Server;
 struct h2_ctx_s {
   int device = 0;
   size_t budget = 0;
-  size_t used = 0;    // bytes held from the device (live + pooled)
-  size_t pooled = 0;  // of which cached in the pool
+  size_t used = 0;        // bytes held from the device (live + pooled)
+  size_t pooled = 0;      // of which cached in the pool
+  size_t live_bytes = 0;  // of which held by live allocations
+  size_t peak_live = 0;   // high-water mark of live_bytes since the last mark()
   // serialises every entry point of the context (and its serving worker)
   std::recursive_mutex mu;
   h2::Server* server = nullptr;  // serving worker, started by the first h2_submit
@@ -56,6 +58,15 @@ struct h2_ctx_s {
   // element size of the live allocation starting at p (4 or 8)
   size_t elt(const void* p) const { return f32.count(const_cast<void*>(p)) ? 4 : 8; }
   void release(void* p);
+  // start a call's high-water mark of live bytes
+  void mark() { peak_live = live_bytes; }
+  // return cached blocks to the device, largest first, until at most keep
+  // bytes stay cached
+  void trim(size_t keep);
+  // end of a call that started at live bytes `start`: keep in the pool at
+  // most twice the call's peak temporaries (so a repeated call of the same
+  // shape finds its blocks), never more than the budget allows
+  void end_call(size_t start);
   ~h2_ctx_s();
 };
 

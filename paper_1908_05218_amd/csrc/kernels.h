@@ -83,7 +83,7 @@ struct EigArgs {
   int* status;  // [0] non-finite, [1] dimension over limit
 };
 
-constexpr int kEigNmax = 256;  // largest Gram dimension
+constexpr int kEigNmax = 512;  // largest Gram dimension
 constexpr int kEigLdsN = 195;  // largest dimension whose packed triangle stays in LDS
 // scratch per cluster (doubles) the eigensolver needs for padded dimension D
 inline long long eig_scratch_doubles(int D) { return 7LL * D * D + 4LL * D + 8; }

@@ -164,6 +164,11 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
                        Buf& rank_c_, const int* k1r, const int* k2r, const int* k1c,
                        const int* k2c, int kstride, int half) {
     const int ncl = 1 << l;
+    if (D > h2k::kEigNmax)
+      throw Error(H2_ERR_UNSUPPORTED, "the Gram matrices at level " + std::to_string(l) +
+                                          " have dimension " + std::to_string(D) +
+                                          ", beyond the eigensolver limit of " +
+                                          std::to_string(h2k::kEigNmax));
     Buf Gnr(ctx, (size_t)ncl * D * D * sizeof(double)), Gnc(ctx, (size_t)ncl * D * D * sizeof(double));
     for (int side = 0; side < 2; ++side) {
       h2k::GramNormArgs ga{};
@@ -659,7 +664,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   C->flop_akcol = A->kcol;
   C->flop_bkrow = B->krow;
   C->flops_pending = true;
-  S.bytes_device = (int64_t)ctx->used;
+  S.bytes_device = (int64_t)ctx->peak_live;
   S.eig_flops = eig_flops;
   if (prof.on) {
     double pms[kKindCount], pfl[kKindCount];

@@ -87,3 +87,26 @@ def test_build_errors(ctx):
     with pytest.raises(h2.H2Error) as e:
         h2.build(ctx, points.cube(65, 0), 8, 1.0, 2, 1.0, share_tree_with=M)
     assert e.value.code == 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_high_rank_cube_product(ctx, precision):
+    """A cube whose product ranks pass 128 below l_min, so that the Gram
+    matrices of the level above have dimension 2 * 176 > 256 (the eigensolver's
+    eight-slot path).  Checked by the relative error criterion of Section V
+    with the exact H^2 mat-vec: 2 eps as for the plates family (plus the FP32
+    slack of the bulk products)."""
+    print(f"case high-rank cube12000 eps 1e-5 {precision}", flush=True)
+    n, eps = 12000, 1e-5
+    A = h2.build(ctx, points.cube(n, 5), 32, 1.0, 3, 1.0)
+    C = h2.mmp(ctx, A, A, eps, precision=precision)
+    st = h2.stats(C)
+    pad = [((r + 15) // 16) * 16 for r in st["rank_max_r"]]
+    assert any(p > 128 for p in pad[st["lmin"] + 1:]), st["rank_max_r"]
+    rng = np.random.default_rng(5)
+    bound = 2 * eps + (2e-6 if precision == "fp32_bulk" else 0.0)
+    for _ in range(2):
+        x = rng.standard_normal(n)
+        ref = h2.matvec(ctx, A, h2.matvec(ctx, A, x))
+        e = np.linalg.norm(h2.matvec(ctx, C, x) - ref) / np.linalg.norm(ref)
+        assert e <= bound, e
