@@ -51,10 +51,11 @@ def cpu_baseline():
 PEAK = {"fp64": FP64_PEAK_TFLOPS, "fp32_bulk": FP32_PEAK_TFLOPS}
 
 
-def serve_stream(n_req, precision, seed=3):
+def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192):
     """Served latency: a seeded stream of C = A A requests through the
-    library's request loop (h2_submit / h2_wait).  Recipe: N = round(exp(U[ln
-    4096, ln 32768])), the unit cube or the two-plate family with probability
+    library's request loop (h2_submit / h2_wait) with `slots` requests on the
+    device at once, admitted against a device-memory budget of budget_gib.
+    Recipe: N = round(exp(U[ln 4096, ln 32768])), the unit cube or the two-plate family with probability
     1/2 each (plates: random points on both plates, panel self-term), leaf 32,
     eta 1, Chebyshev 3x3x3, eps 1e-4 or 1e-6 with probability 1/2,
     exponential inter-arrival times of mean 50 ms; the points are generated
@@ -79,7 +80,8 @@ def serve_stream(n_req, precision, seed=3):
             a = (1.0 / (n // 2)) ** 0.5
             sv = panel_self_term(a, a)
         reqs.append((n, eps, gap, pts, sv))
-    ctx = h2.Context(0)
+    ctx = h2.Context(0, hbm_budget=int(budget_gib * 2**30))
+    h2.serve_slots(ctx, slots)
     n0, eps0, _, p0, s0 = reqs[0]
     warm = h2.submit(ctx, p0, 32, 1.0, 3, s0, eps0, precision=precision)
     h2.wait(ctx, warm)
@@ -99,7 +101,8 @@ def serve_stream(n_req, precision, seed=3):
     wall = time.perf_counter() - t0
     ctx.close()
     lat = np.array(lat)
-    return {"precision": precision, "requests": n_req, "failed": int(bad),
+    return {"precision": precision, "requests": n_req, "failed": int(bad), "slots": slots,
+            "budget_gib": budget_gib,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_service_ms": float(np.mean(svc)),
             "unknowns_per_s": float(sum(n for _, n in tickets) / wall)}
@@ -207,6 +210,8 @@ def main():
                     help="precision of the headline product (the other one is timed beside it)")
     ap.add_argument("--no-compare", action="store_true", help="skip the second precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-slots", type=int, default=2,
+                    help="concurrent requests of the serving loop")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the served-latency stream (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -277,7 +282,8 @@ def main():
                     "speedup_of_headline": other["ms"] / ms,
                     "breakdown": other["breakdown"], "roofline": other["roofline"]}
     if args.serve_requests > 0:
-        out["serving"] = {p: serve_stream(args.serve_requests, p) for p in ("fp32_bulk", "fp64")}
+        out["serving"] = {p: serve_stream(args.serve_requests, p, slots=args.serve_slots)
+                          for p in ("fp32_bulk", "fp64")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -135,17 +135,29 @@ typedef struct {
 h2_status h2_build(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* kernel,
                    const h2_build_opts* opts, h2_mat share_tree_with, h2_mat* out);
 
-/* Serving: a request loop of the context.  A request names a point set and
- * a kernel (built as by h2_build) and a product C = A A at eps; the context's
- * worker thread runs the requests one at a time in submission order, each
- * admitted once its device-memory estimate (about 80 KB per point at rank 27,
- * scaled by cheb_order^3 / 27) fits the context's hbm_budget next to the
- * results still held; with no budget every request is admitted at once.
- * A and C of a finished request stay resident until h2_release.  While
- * requests are in flight the context's other entry points may still be
- * called from any thread: every entry point of a context is serialised by
- * the context's lock.  h2_ctx_destroy stops the worker after the request it
- * is running and drops the queued ones. */
+/* Serving: a request loop of the context with continuous batching.  A
+ * request names a point set and a kernel (built as by h2_build) and a
+ * product C = A A at eps.  The loop runs up to `slots` requests at once
+ * (h2_serve_slots, default 2), each on a slot context of its own (same
+ * device, own stream and memory pool), so that the device work of one request
+ * overlaps the host-side steps of another.  Requests start in submission
+ * order: the first queued request starts once a slot is free and its
+ * device-memory estimate fits the context's hbm_budget next to the bytes of
+ * the results still held and the estimates of the requests running.  The
+ * estimate is kappa N^1.5 (cheb_order / 3)^3 bytes plus 64 MiB, kappa per
+ * precision starting at 9000 (FP64) and 7000 (FP32-bulk) and raised to the
+ * largest value a finished request has shown; with no budget, requests only
+ * wait for a slot.  A request that runs out of device memory while another
+ * runs is queued again once, first in line, to run alone.  Results do not
+ * depend on what runs beside them (every kernel is deterministic).  A and C of
+ * a finished request stay resident until h2_release; they can be passed to
+ * h2_matvec, h2_to_dense, h2_export and h2_stats with the submitting context,
+ * to h2_mmp together with other matrices of the same request (not with
+ * matrices of the context itself), and must not be freed with h2_free.  A
+ * product of served matrices belongs to the request's slot: free it with
+ * h2_free before h2_ctx_destroy, like every matrix of the context.
+ * h2_ctx_destroy stops the loop after the requests it is running and drops
+ * the queued ones. */
 typedef struct {
   const double* xyz;  /* host, n x 3 row-major, original order; copied */
   int64_t n;
@@ -164,8 +176,13 @@ typedef struct {
   double mmp_ms;      /* h2_mmp of C = A A (host wall time, synchronised) */
   double total_ms;    /* submission to completion */
   char message[160];  /* error text when status != H2_OK */
+  int64_t bytes;      /* device bytes held by A and C until h2_release */
 } h2_result;
 
+/* Number of concurrent requests of the serving loop (1..8), before the first
+ * h2_submit.  Errors: H2_ERR_ARG (out of range), H2_ERR_BUSY (the loop has
+ * started). */
+h2_status h2_serve_slots(h2_ctx ctx, int slots);
 /* Queue a request; *ticket identifies it.  Errors: H2_ERR_ARG (null
  * pointer, invalid sizes, options or eps), H2_ERR_OOM (its estimate exceeds
  * the context's whole budget). */

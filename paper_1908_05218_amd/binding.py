@@ -81,7 +81,7 @@ class _Request(C.Structure):
 class _Result(C.Structure):
     _fields_ = [("status", C.c_int), ("A", C.c_void_p), ("C", C.c_void_p),
                 ("queue_ms", C.c_double), ("build_ms", C.c_double), ("mmp_ms", C.c_double),
-                ("total_ms", C.c_double), ("message", C.c_char * 160)]
+                ("total_ms", C.c_double), ("message", C.c_char * 160), ("bytes", C.c_int64)]
 
 _lib = None
 
@@ -111,11 +111,12 @@ def lib():
         L.h2_poll.argtypes = [vp, C.c_uint64]
         L.h2_wait.argtypes = [vp, C.c_uint64, C.POINTER(_Result)]
         L.h2_release.argtypes = [vp, C.c_uint64]
+        L.h2_serve_slots.argtypes = [vp, C.c_int]
         L.h2_last_error.restype = C.c_char_p
         L.h2_version.restype = C.c_int
         for f in ("h2_ctx_create", "h2_load", "h2_build", "h2_submit", "h2_poll", "h2_wait",
                   "h2_release", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
-                  "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling"):
+                  "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling", "h2_serve_slots"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -264,6 +265,12 @@ class Borrowed:
         pass
 
 
+def serve_slots(ctx, slots):
+    """Concurrent requests of the context's serving loop (before the first
+    submit)."""
+    _check(lib().h2_serve_slots(ctx.h, int(slots)))
+
+
 def submit(ctx, points, leaf_size, eta, order, self_value, eps, mode="accuracy",
            precision="fp64"):
     """Queue C = A A for the H^2 matrix of 1/(4 pi r) over `points`; returns
@@ -294,7 +301,7 @@ def wait(ctx, ticket):
     return dict(status=res.status, A=Borrowed(ctx, C.c_void_p(res.A)) if res.A else None,
                 C=Borrowed(ctx, C.c_void_p(res.C)) if res.C else None, queue_ms=res.queue_ms,
                 build_ms=res.build_ms, mmp_ms=res.mmp_ms, total_ms=res.total_ms,
-                message=res.message.decode(errors="replace"))
+                message=res.message.decode(errors="replace"), bytes=res.bytes)
 
 
 def release(ctx, ticket):

@@ -719,6 +719,12 @@ h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int
   if (precision < 0 || precision > 1) return set_error(H2_ERR_ARG, "bad precision");
   if (A->shape != B->shape && !A->st().same_as(B->st()))
     return set_error(H2_ERR_STRUCTURE, "A and B differ in tree or block partition");
+  {
+    h2_ctx ha = home_of(ctx, A), hb = home_of(ctx, B);
+    if (!ha || ha != hb)
+      return set_error(H2_ERR_ARG, "A and B must both belong to ctx (or to one served result)");
+    ctx = ha;
+  }
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   ActiveCtx active(ctx);
   const size_t start = ctx->live_bytes;
@@ -741,6 +747,8 @@ h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nr
                     int x_on_device) {
   using namespace h2;
   if (!ctx || !M || !x || !y || nrhs < 1) return set_error(H2_ERR_ARG, "bad argument");
+  ctx = home_of(ctx, M);
+  if (!ctx) return set_error(H2_ERR_ARG, "M belongs to another context");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   ActiveCtx active(ctx);
   try {
@@ -766,6 +774,8 @@ h2_status h2_to_dense(h2_ctx ctx, h2_mat M, double* out, int64_t ld) {
   const long long n = M->st().n;
   if (ld < n) return set_error(H2_ERR_ARG, "ld < n");
   if (n > 16384) return set_error(H2_ERR_UNSUPPORTED, "to_dense is limited to n <= 16384");
+  ctx = home_of(ctx, M);
+  if (!ctx) return set_error(H2_ERR_ARG, "M belongs to another context");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   ActiveCtx active(ctx);
   try {

@@ -190,6 +190,8 @@ h2_status build_impl(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* 
   for (int64_t i = 0; i < 3 * n; ++i)
     if (!std::isfinite(xyz[i])) return set_error(H2_ERR_ARG, "non-finite coordinate");
   if (share && share->st().n != n) return set_error(H2_ERR_ARG, "share_tree_with has another size");
+  if (share && share->ctx != ctx)
+    return set_error(H2_ERR_ARG, "share_tree_with belongs to another context");
   const int p = opts->cheb_order, p3 = p * p * p;
   const Tree t = make_tree(xyz, n, opts->leaf_size);
   const Blocks bl = make_blocks(t, opts->eta);

@@ -48,7 +48,11 @@ struct h2_ctx_s {
   size_t peak_live = 0;   // high-water mark of live_bytes since the last mark()
   // serialises every entry point of the context (and its serving worker)
   std::recursive_mutex mu;
-  h2::Server* server = nullptr;  // serving worker, started by the first h2_submit
+  h2::Server* server = nullptr;  // serving loop, started by the first h2_submit
+  int serve_slots = 2;            // concurrent requests of the serving loop
+  // a serving slot's context: the context whose h2_submit created it (its
+  // results are used through the parent)
+  h2_ctx_s* parent = nullptr;
   hipStream_t stream = nullptr;
   bool profiling = false;
   std::multimap<size_t, void*> pool;
@@ -227,6 +231,12 @@ struct BulkScope {
 };
 
 h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C);
+// the context whose pool holds M: ctx itself or one of ctx's serving slots
+// (nullptr when M belongs to neither)
+inline h2_ctx home_of(h2_ctx ctx, const h2_mat_s* M) {
+  if (!ctx || !M || !M->ctx) return nullptr;
+  return (M->ctx == ctx || M->ctx->parent == ctx) ? M->ctx : nullptr;
+}
 // stop a context's serving worker (after its current request) and drop the
 // requests still queued; no-op without one
 void stop_server(h2_ctx ctx);

@@ -1,8 +1,10 @@
 """Serving (h2_submit / h2_poll / h2_wait / h2_release): requests of mixed
-size, family, eps and precision run through the context's worker; every
-result meets the product's relative error criterion (equation `error`); the
-HBM budget admits requests only next to the results still held."""
+size, family, eps and precision run through the context's slots; every
+result meets the product's relative error criterion (equation `error`) and
+equals the same request run alone; the HBM budget admits requests only next
+to the results held and the requests running."""
 import math
+import time
 
 import numpy as np
 import pytest
@@ -60,29 +62,109 @@ def test_serving_mixed_requests():
         ctx.close()
 
 
+def _estimate(n, precision="fp64", order=3):
+    # the loop's starting estimate: kappa N^1.5 (order / 3)^3 + 64 MiB
+    kappa = {"fp64": 9000.0, "fp32_bulk": 7000.0}[precision]
+    return int(kappa * n * math.sqrt(n) * (order / 3.0) ** 3) + (64 << 20)
+
+
 def test_serving_admission_by_budget():
-    # estimate per request: 80 KB per point (rank 27) + 64 MiB
-    est = 2048 * 80e3 + (64 << 20)
-    budget = int(4.5 * est)
-    ctx = h2.Context(0, hbm_budget=budget)
+    """A request starts only when its estimate fits the budget next to the
+    results held and the requests running: with the budget between one
+    estimate and one estimate plus one held result, the second of two equal
+    requests waits for the release of the first."""
+    n = 2048
+    pts = points.cube(n, 0)
+    free = h2.Context(0)
+    try:
+        t = h2.submit(free, pts, 32, 1.0, 3, 1.0, 1e-4)
+        held = h2.wait(free, t)["bytes"]
+        h2.release(free, t)
+    finally:
+        free.close()
+    assert held > 0
+    est = _estimate(n)
+    ctx = h2.Context(0, hbm_budget=est + held // 2)
     try:
         with pytest.raises(h2.H2Error) as e:
             h2.submit(ctx, points.cube(65536, 0), 32, 1.0, 3, 1.0, 1e-4)
         assert e.value.code == 3
-        tickets = [h2.submit(ctx, points.cube(2048, i), 32, 1.0, 3, 1.0, 1e-4) for i in range(5)]
+        tickets = [h2.submit(ctx, pts, 32, 1.0, 3, 1.0, 1e-4) for _ in range(2)]
         print("submitted", tickets, flush=True)
-        for t in tickets[:4]:
-            assert h2.wait(ctx, t)["status"] == 0
-        # four results are held: the fifth waits for a release
-        assert not h2.poll(ctx, tickets[4])
+        first = h2.wait(ctx, tickets[0])
+        assert first["status"] == 0 and first["bytes"] == held
+        time.sleep(0.5)
+        assert not h2.poll(ctx, tickets[1])
         with pytest.raises(h2.H2Error) as e:
-            h2.release(ctx, tickets[4])
+            h2.release(ctx, tickets[1])
         assert e.value.code == 8
         h2.release(ctx, tickets[0])
-        res = h2.wait(ctx, tickets[4])
-        assert res["status"] == 0 and res["queue_ms"] > 0
-        for t in tickets[1:]:
+        res = h2.wait(ctx, tickets[1])
+        assert res["status"] == 0 and res["queue_ms"] >= first["total_ms"]
+        h2.release(ctx, tickets[1])
+    finally:
+        ctx.close()
+
+
+def _export_arrays(M):
+    d = h2.export(M)
+    return {k: np.asarray(v).copy() for k, v in d.items()}
+
+
+def test_serving_results_same_alone_and_in_the_mix():
+    """Requests that share the device through three slots give the same
+    products as the same requests run alone, one after another, through
+    h2_build and h2_mmp (every kernel is deterministic: equal bits)."""
+    reqs = [_request(i) for i in range(6)]
+    ctx = h2.Context(0)
+    try:
+        h2.serve_slots(ctx, 3)
+        tickets = [h2.submit(ctx, p, 32, 1.0, 3, sv, eps, precision=prec)
+                   for p, sv, eps, prec in reqs]
+        print("submitted", tickets, flush=True)
+        mixed = []
+        for t in tickets:
+            res = h2.wait(ctx, t)
+            assert res["status"] == 0, res["message"]
+            mixed.append(_export_arrays(res["C"]))
+        with pytest.raises(h2.H2Error) as e:
+            h2.serve_slots(ctx, 2)
+        assert e.value.code == 8
+        for t in tickets:
             h2.release(ctx, t)
+    finally:
+        ctx.close()
+    alone = h2.Context(0)
+    try:
+        for (p, sv, eps, prec), m in zip(reqs, mixed):
+            A = h2.build(alone, p, 32, 1.0, 3, sv)
+            C = h2.mmp(alone, A, A, eps, precision=prec)
+            a = _export_arrays(C)
+            assert a.keys() == m.keys()
+            for k in a:
+                assert np.array_equal(a[k], m[k]), k
+    finally:
+        alone.close()
+
+
+def test_served_results_stay_with_their_request():
+    """A served result cannot be mixed with the context's own matrices in a
+    product or shared as a tree."""
+    ctx = h2.Context(0)
+    try:
+        pts = points.cube(1024, 1)
+        t = h2.submit(ctx, pts, 32, 1.0, 3, 1.0, 1e-4)
+        res = h2.wait(ctx, t)
+        own = h2.build(ctx, pts, 32, 1.0, 3, 1.0)
+        with pytest.raises(h2.H2Error) as e:
+            h2.mmp(ctx, own, res["A"], 1e-4)
+        assert e.value.code == 1
+        with pytest.raises(h2.H2Error) as e:
+            h2.build(ctx, pts, 32, 1.0, 3, 1.0, share_tree_with=res["A"])
+        assert e.value.code == 1
+        C2 = h2.mmp(ctx, res["A"], res["A"], 1e-4)
+        assert np.array_equal(np.asarray(h2.export(C2)["S"]), np.asarray(h2.export(res["C"])["S"]))
+        h2.release(ctx, t)
     finally:
         ctx.close()
 
