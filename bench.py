@@ -106,25 +106,26 @@ def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192):
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_service_ms": float(np.mean(svc)),
             "unknowns_per_s": float(sum(n for _, n in tickets) / wall)}
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plates64k_fp32bulk_block_products_hbm.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plates64k_fp32bulk_hbm_by_class.md")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the FP32-bulk block-product kernels from the
-    committed FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
-    has changed since those counters were taken."""
+def measured_traffic(kind):
+    """HBM bytes per launch of kernel class `kind` in FP32-bulk products of
+    plates64k, from the committed FETCH_SIZE/WRITE_SIZE summary, or None when
+    the kernel sources have changed since those counters were taken."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
-    src = os.path.join(ROOT, "paper_1908_05218_amd", "csrc", "kernels.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    csrc = os.path.join(ROOT, "paper_1908_05218_amd", "csrc")
+    blob = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("kernels.hip", "eig.hip"))
+    h = hashlib.sha256(blob).hexdigest()[:16]
     val, rec = None, None
     for line in text.splitlines():
-        if line.startswith("traffic_bytes_per_launch:"):
+        if line.startswith(f"traffic_bytes_per_launch[{kind}]:"):
             val = float(line.split(":")[1])
-        if line.startswith("kernels.hip sha256 (first 16 hex):"):
+        if line.startswith("kernel sources sha256 (first 16 hex):"):
             rec = line.split(":")[1].strip()
     return val if (val is not None and rec == h) else None
 
@@ -188,7 +189,7 @@ def run_precision(h2, ctx, dA, n, prec, steps, warmup, eps):
         alg = None
         roof = {"bound": "mfma", "unit": "TFLOP/s", "peak": PEAK[prec]}
     achieved = (alg / (dms * 1e-3) / 1e12) if (alg and dms > 0) else None
-    traffic = measured_traffic() if (dom == "triple_contraction" and prec == "fp32_bulk") else None
+    traffic = measured_traffic(dom) if prec == "fp32_bulk" else None
     roof.update({"kernel": dom, "achieved": achieved,
                  "frac": (achieved / roof["peak"]) if achieved else None,
                  "traffic": traffic, "traffic_unit": "bytes per launch",
