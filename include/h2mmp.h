@@ -222,6 +222,7 @@ h2_status h2_to_dense(h2_ctx ctx, h2_mat M, double* out, int64_t ld);
 typedef struct {
   int64_t n, L, nnodes;
   int64_t len_V, len_W, len_Er, len_Ec, len_S, len_F;
+  int64_t is_complex; /* lengths count complex elements (two doubles each) */
 } h2_export_sizes;
 h2_status h2_export_size(h2_mat M, h2_export_sizes* sz);
 

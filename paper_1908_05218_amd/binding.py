@@ -38,7 +38,7 @@ class _HostMatrix(C.Structure):
 
 class _ExportSizes(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("n", "L", "nnodes", "len_V", "len_W", "len_Er",
-                                          "len_Ec", "len_S", "len_F")]
+                                          "len_Ec", "len_S", "len_F", "is_complex")]
 
 
 class _ExportBuffers(C.Structure):
@@ -187,10 +187,13 @@ _F64 = ("V", "W", "Er", "Ec", "S", "F")
 
 
 def _host_matrix(flat, keep):
+    """Complex data (is_complex, or complex arrays) go as interleaved
+    (real, imaginary) pairs."""
     hm = _HostMatrix()
     hm.n = int(flat["n"])
     hm.L = int(flat["L"])
-    hm.is_complex = int(flat.get("is_complex", 0))
+    cplx = bool(int(flat.get("is_complex", 0))) or any(np.iscomplexobj(flat[k]) for k in _F64)
+    hm.is_complex = 1 if cplx else 0
     for k in _I64:
         keep[k] = np.ascontiguousarray(flat[k], dtype=np.int64)
         setattr(hm, k, keep[k].ctypes.data)
@@ -198,7 +201,10 @@ def _host_matrix(flat, keep):
         keep[k] = np.ascontiguousarray(flat[k], dtype=np.int32)
         setattr(hm, k, keep[k].ctypes.data)
     for k in _F64:
-        keep[k] = np.ascontiguousarray(flat[k], dtype=np.float64)
+        if cplx:
+            keep[k] = np.ascontiguousarray(flat[k], dtype=np.complex128).view(np.float64)
+        else:
+            keep[k] = np.ascontiguousarray(flat[k], dtype=np.float64)
         setattr(hm, k, keep[k].ctypes.data if keep[k].size else None)
     return hm
 
@@ -220,19 +226,7 @@ def load(ctx, flat):
     """Upload an H^2 matrix given in the flat interchange layout (a dict of
     arrays as described in include/h2mmp.h)."""
     keep = {}
-    hm = _HostMatrix()
-    hm.n = int(flat["n"])
-    hm.L = int(flat["L"])
-    hm.is_complex = int(flat.get("is_complex", 0))
-    for k in _I64:
-        keep[k] = np.ascontiguousarray(flat[k], dtype=np.int64)
-        setattr(hm, k, keep[k].ctypes.data)
-    for k in _I32:
-        keep[k] = np.ascontiguousarray(flat[k], dtype=np.int32)
-        setattr(hm, k, keep[k].ctypes.data)
-    for k in _F64:
-        keep[k] = np.ascontiguousarray(flat[k], dtype=np.float64)
-        setattr(hm, k, keep[k].ctypes.data if keep[k].size else None)
+    hm = _host_matrix(flat, keep)
     h = C.c_void_p()
     _check(lib().h2_load(ctx.h, C.byref(hm), C.byref(h)))
     return Matrix(ctx, h)
@@ -314,9 +308,30 @@ def mmp(ctx, A, B, eps, mode="accuracy", precision="fp64"):
     return Matrix(ctx, h)
 
 
+def is_complex(M):
+    sz = _ExportSizes()
+    _check(lib().h2_export_size(M.h, C.byref(sz)))
+    return bool(sz.is_complex)
+
+
 def matvec(ctx, M, x):
     """y = M x.  x: numpy array (host) or a torch tensor on the GPU
-    (float64, n or n x nrhs, column-major for nrhs > 1 means x.T contiguous)."""
+    (float64, n or n x nrhs, column-major for nrhs > 1 means x.T contiguous).
+    Complex matrices: numpy x (complex), passed planar (real parts, then
+    imaginary parts)."""
+    if is_complex(M):
+        x = np.asarray(x, dtype=np.complex128)
+        vec = x.ndim == 1
+        X = x.reshape(x.shape[0], -1)
+        nrhs = X.shape[1]
+        P = np.concatenate([np.asfortranarray(X.real).ravel(order="F"),
+                            np.asfortranarray(X.imag).ravel(order="F")])
+        Q = np.empty_like(P)
+        _check(lib().h2_matvec(ctx.h, M.h, P.ctypes.data_as(C.c_void_p),
+                               Q.ctypes.data_as(C.c_void_p), nrhs, 0))
+        m = X.shape[0] * nrhs
+        Y = (Q[:m] + 1j * Q[m:]).reshape(X.shape, order="F")
+        return Y[:, 0] if vec else Y
     try:
         import torch
         is_t = isinstance(x, torch.Tensor)
@@ -342,7 +357,7 @@ def matvec(ctx, M, x):
 
 
 def to_dense(ctx, M, n):
-    out = np.empty((n, n), dtype=np.float64, order="F")
+    out = np.empty((n, n), dtype=np.complex128 if is_complex(M) else np.float64, order="F")
     _check(lib().h2_to_dense(ctx.h, M.h, out.ctypes.data_as(C.c_void_p), n))
     return out
 
@@ -353,13 +368,14 @@ def export(M):
     _check(lib().h2_export_size(M.h, C.byref(sz)))
     nleaf = 1 << sz.L
     ncl = (2 << sz.L) - 1
+    fdt = np.complex128 if sz.is_complex else np.float64
     out = dict(
         leaf_off=np.zeros(nleaf + 1, np.int64), perm=np.zeros(sz.n, np.int64),
         node_off=np.zeros(sz.L + 2, np.int64), node_row=np.zeros(sz.nnodes, np.int32),
         node_col=np.zeros(sz.nnodes, np.int32), node_type=np.zeros(sz.nnodes, np.int32),
         krow=np.zeros(ncl, np.int64), kcol=np.zeros(ncl, np.int64),
-        V=np.zeros(sz.len_V), W=np.zeros(sz.len_W), Er=np.zeros(sz.len_Er),
-        Ec=np.zeros(sz.len_Ec), S=np.zeros(sz.len_S), F=np.zeros(sz.len_F),
+        V=np.zeros(sz.len_V, fdt), W=np.zeros(sz.len_W, fdt), Er=np.zeros(sz.len_Er, fdt),
+        Ec=np.zeros(sz.len_Ec, fdt), S=np.zeros(sz.len_S, fdt), F=np.zeros(sz.len_F, fdt),
         V_off=np.zeros(nleaf + 1, np.int64), W_off=np.zeros(nleaf + 1, np.int64),
         Er_off=np.zeros(ncl + 1, np.int64), Ec_off=np.zeros(ncl + 1, np.int64),
         S_off=np.zeros(sz.nnodes + 1, np.int64), F_off=np.zeros(sz.nnodes + 1, np.int64))
@@ -369,7 +385,7 @@ def export(M):
     _check(lib().h2_export(M.h, C.byref(eb)))
     out["n"] = np.int64(sz.n)
     out["L"] = np.int64(sz.L)
-    out["is_complex"] = np.int64(0)
+    out["is_complex"] = np.int64(1 if sz.is_complex else 0)
     return out
 
 

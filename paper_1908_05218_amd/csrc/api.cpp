@@ -74,6 +74,11 @@ static void check_extent(const void* base, long long stride, int maxtile, long l
   if (it == g_active_ctx->live.end())
     throw Error(H2_ERR_INTERNAL, std::string(what) + ": operand is not a live allocation");
   const long long need = (long long)maxtile * stride + sub_r + sub_c + (rows - 1) + (cols - 1) * ld + 1;
+  // a complex allocation is checked against its real plane (the imaginary
+  // plane has the same layout one plane further)
+  const long long pl = g_active_ctx->plane(base);
+  if (pl > 0 && need > pl)
+    throw Error(H2_ERR_INTERNAL, std::string(what) + ": block extent beyond its plane");
   if ((size_t)need * elt > it->second)
     throw Error(H2_ERR_INTERNAL, std::string(what) + ": block extent beyond its allocation (" +
                                      std::to_string(need * elt) + " > " +
@@ -131,9 +136,20 @@ static void launch_gemm(hipStream_t s, Profiler* prof, int kind, const DevList& 
   if (prof) prof->end(ev, kind, fl);
 }
 
+// operand with its base pointers moved to the imaginary planes
+static Op imag_of(const Op& o) {
+  Op r = o;
+  const long long p0 = g_active_ctx->plane(o.base0);
+  r.base0 = (const double*)o.base0 + p0;
+  if (o.base1) r.base1 = (const double*)o.base1 + g_active_ctx->plane(o.base1);
+  return r;
+}
+
+static bool is_cplx(const void* p) { return g_active_ctx && p && g_active_ctx->plane(p) > 0; }
+
 void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int n, int k,
           const Op& A, bool tA, const Op& B, bool tB, void* C, long long cstride, int ldc,
-          long long csub_r, long long csub_c, double alpha, double beta) {
+          long long csub_r, long long csub_c, double alpha, double beta, int conj) {
   if (tl.nout == 0) return;
   if (k % 16 != 0 || m <= 0 || n <= 0) throw Error(H2_ERR_INTERNAL, "gemm shape");
   {
@@ -150,6 +166,26 @@ void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int
                  elt_of(b1), "gemm B(sel)");
     check_extent(C, cstride, tl.max_out, csub_r, csub_c, m, n, ldc, elt_of(C), "gemm C");
   }
+  if (is_cplx(C)) {
+    // (Ar + i sa Ai)(Br + i sb Bi): real part Ar Br - sa sb Ai Bi, imaginary
+    // part sb Ar Bi + sa Ai Br; beta applies once per plane
+    const bool ok = is_cplx(A.base0) && is_cplx(B.base0) && (!A.base1 || is_cplx(A.base1)) &&
+                    (!B.base1 || is_cplx(B.base1));
+    if (!ok) throw Error(H2_ERR_INTERNAL, "complex product with a real operand");
+    const double sa = (conj & kConjA) ? -1.0 : 1.0, sb = (conj & kConjB) ? -1.0 : 1.0;
+    const Op Ai = imag_of(A), Bi = imag_of(B);
+    double* Cr = (double*)C;
+    double* Ci = Cr + g_active_ctx->plane(C);
+    auto run = [&](const Op& x, const Op& y, double* c, double al, double be) {
+      launch_gemm<double>(s, prof, kind, tl, m, n, k, x, tA, y, tB, c, cstride, ldc, csub_r, csub_c,
+                          al, be);
+    };
+    run(A, B, Cr, alpha, beta);
+    run(Ai, Bi, Cr, -alpha * sa * sb, 1.0);
+    run(A, Bi, Ci, alpha * sb, beta);
+    run(Ai, B, Ci, alpha * sa, 1.0);
+    return;
+  }
   if (g_bulk_f32 && kind != kKindGram)
     launch_gemm<float>(s, prof, kind, tl, m, n, k, A, tA, B, tB, C, cstride, ldc, csub_r, csub_c,
                        alpha, beta);
@@ -158,12 +194,9 @@ void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int
                         alpha, beta);
 }
 
-void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, void* C,
-            long long cstride, int ldc, long long csub_r, long long csub_c, double beta) {
-  if (tl.nout == 0) return;
-  if (elt_of(A.base0) != 8 || elt_of(C) != 8) throw Error(H2_ERR_INTERNAL, "segsum: FP64 only");
-  check_extent(A.base0, A.stride0, tl.max_a[0], A.sub_r, A.sub_c, m, n, A.ld, 8, "segsum A");
-  check_extent(C, cstride, tl.max_out, csub_r, csub_c, m, n, ldc, 8, "segsum C");
+static void launch_segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, void* C,
+                          long long cstride, int ldc, long long csub_r, long long csub_c,
+                          double beta) {
   h2k::SegsumArgs<double> a{};
   a.m = m;
   a.n = n;
@@ -181,8 +214,21 @@ void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, void* C
   H2_HIP(h2k::launch_segsum<double>(a, s));
 }
 
+void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, void* C,
+            long long cstride, int ldc, long long csub_r, long long csub_c, double beta) {
+  if (tl.nout == 0) return;
+  if (elt_of(A.base0) != 8 || elt_of(C) != 8) throw Error(H2_ERR_INTERNAL, "segsum: FP64 only");
+  check_extent(A.base0, A.stride0, tl.max_a[0], A.sub_r, A.sub_c, m, n, A.ld, 8, "segsum A");
+  check_extent(C, cstride, tl.max_out, csub_r, csub_c, m, n, ldc, 8, "segsum C");
+  if (is_cplx(C) != is_cplx(A.base0)) throw Error(H2_ERR_INTERNAL, "segsum: mixed complex and real");
+  launch_segsum(s, tl, m, n, A, C, cstride, ldc, csub_r, csub_c, beta);
+  if (is_cplx(C))
+    launch_segsum(s, tl, m, n, imag_of(A), (double*)C + g_active_ctx->plane(C), cstride, ldc,
+                  csub_r, csub_c, beta);
+}
+
 void zero(hipStream_t s, void* p, long long n) {
-  if (n > 0) H2_HIP(hipMemsetAsync(p, 0, (size_t)n * elt_of(p), s));
+  if (n > 0) H2_HIP(hipMemsetAsync(p, 0, (size_t)n * elt_of(p) * (is_cplx(p) ? 2 : 1), s));
 }
 
 const h2_mat_s& f32_shadow(h2_ctx ctx, h2_mat M, hipStream_t s) {
@@ -279,14 +325,18 @@ void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64
   const int lo = M->product ? s.lmin : s.lmin;  // no admissible block above lmin
   const long long nt = (long long)nleaf * np;
   const int R = (int)nrhs;
-  Buf xt(ctx, nt * R * sizeof(double)), yt(ctx, nt * R * sizeof(double));
+  // complex: x and y planar (n x nrhs real parts, then the imaginary parts),
+  // gathered and scattered as 2 nrhs real columns
+  const int nc = M->cplx ? 2 : 1;
+  const bool cx = M->cplx;
+  Buf xt(ctx, nt * R * nc * sizeof(double), false, cx), yt(ctx, nt * R * nc * sizeof(double), false, cx);
   H2_HIP(h2k::launch_gather_rows(x_dev, xt.d(), sh.d_perm.as<long long>(),
-                                 sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R, st));
+                                 sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R * nc, st));
   // identity task lists built on the fly (small)
   std::vector<Buf> xh(L + 1), yh(L + 1);
   for (int l = lo; l <= L; ++l) {
-    xh[l] = Buf(ctx, (size_t)(1 << l) * M->rc[l] * R * sizeof(double));
-    yh[l] = Buf(ctx, (size_t)(1 << l) * M->rr[l] * R * sizeof(double));
+    xh[l] = Buf(ctx, (size_t)(1 << l) * M->rc[l] * R * nc * sizeof(double), false, cx);
+    yh[l] = Buf(ctx, (size_t)(1 << l) * M->rr[l] * R * nc * sizeof(double), false, cx);
     zero(st, yh[l].d(), (long long)(1 << l) * M->rr[l] * R);
   }
   // temporary device task lists
@@ -403,7 +453,7 @@ void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64
          1.0);
   }
   H2_HIP(h2k::launch_scatter_rows(yt.d(), y_dev, sh.d_perm.as<long long>(),
-                                  sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R, st));
+                                  sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R * nc, st));
   H2_HIP(hipStreamSynchronize(st));
 }
 
@@ -422,7 +472,13 @@ static size_t size_class(size_t b) {
   return (b + step - 1) & ~(step - 1);
 }
 
-void* h2_ctx_s::alloc(size_t bytes, bool is_f32) {
+void* h2_ctx_s::alloc(size_t bytes, bool is_f32, bool is_cplx) {
+  void* p = alloc_raw(bytes, is_f32);
+  if (is_cplx) planes[p] = (long long)(bytes / 16);
+  return p;
+}
+
+void* h2_ctx_s::alloc_raw(size_t bytes, bool is_f32) {
   bytes = size_class(bytes);
   // best fit among the cached blocks, wasting at most a quarter
   auto it = pool.lower_bound(bytes);
@@ -498,6 +554,7 @@ void h2_ctx_s::release(void* p) {
   live_bytes -= it->second;
   live.erase(it);
   f32.erase(p);
+  planes.erase(p);
 }
 
 h2_ctx_s::~h2_ctx_s() {
@@ -555,7 +612,6 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
   if (!ctx || !m || !out) return set_error(H2_ERR_ARG, "null argument");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   ActiveCtx active(ctx);
-  if (m->is_complex) return set_error(H2_ERR_UNSUPPORTED, "complex matrices are not supported");
   try {
     hipSetDevice(ctx->device);
     auto shape = std::make_shared<Shape>();
@@ -571,6 +627,16 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
     auto M = std::make_unique<h2_mat_s>();
     M->ctx = ctx;
     M->shape = shape;
+    M->cplx = m->is_complex != 0;
+    // complex input: interleaved (real, imaginary) pairs; on the device two
+    // planes [real | imaginary] per buffer
+    const int nc = M->cplx ? 2 : 1;
+    auto upload = [&](const std::vector<double>& h) {
+      Buf b(ctx, h.size() * sizeof(double), false, M->cplx);
+      if (!h.empty())
+        H2_HIP(hipMemcpy(b.d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+      return b;
+    };
     M->krow.assign(m->krow, m->krow + ncl);
     M->kcol.assign(m->kcol, m->kcol + ncl);
     M->rr.assign(L + 1, 16);
@@ -591,16 +657,19 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
     auto upload_leaf = [&](const double* src, const int64_t* off, const std::vector<int64_t>& kk,
                            int rpad, Buf& dst, long long& stride, const char* what) {
       stride = (long long)np * rpad;
-      std::vector<double> h((size_t)stride * nleaf, 0.0);
+      const size_t pl = (size_t)stride * nleaf;
+      std::vector<double> h(pl * nc, 0.0);
       for (int c = 0; c < nleaf; ++c) {
-        const int nc = s.leaf_size[c];
+        const int nr = s.leaf_size[c];
         const int k = (int)kk[cidx(L, c)];
-        need(off, c, (long long)nc * k, what);
+        need(off, c, (long long)nr * k, what);
         for (int j = 0; j < k; ++j)
-          for (int i = 0; i < nc; ++i) h[(size_t)c * stride + i + (size_t)j * np] = src[off[c] + i + (size_t)j * nc];
+          for (int i = 0; i < nr; ++i)
+            for (int part = 0; part < nc; ++part)
+              h[part * pl + (size_t)c * stride + i + (size_t)j * np] =
+                  src[(off[c] + i + (size_t)j * nr) * nc + part];
       }
-      dst = Buf(ctx, h.size() * sizeof(double));
-      H2_HIP(hipMemcpy(dst.d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+      dst = upload(h);
     };
     upload_leaf(m->V, m->V_off, M->krow, M->rr[L], M->V, M->V_stride, "V");
     upload_leaf(m->W, m->W_off, M->kcol, M->rc[L], M->W, M->W_stride, "W");
@@ -613,7 +682,8 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
       for (int l = 0; l < L; ++l) {
         const int ld = 2 * rp[l + 1];
         stride[l] = (long long)ld * rp[l];
-        std::vector<double> h((size_t)stride[l] * (1 << l), 0.0);
+        const size_t pl = (size_t)stride[l] * (1 << l);
+        std::vector<double> h(pl * nc, 0.0);
         for (int I = 0; I < (1 << l); ++I)
           for (int a = 0; a < 2; ++a) {
             const int c = 2 * I + a;
@@ -623,11 +693,11 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
             if (kc_ * kp && !src) throw Error(H2_ERR_ARG, "null transfer array");
             for (int j = 0; j < kp; ++j)
               for (int i = 0; i < kc_; ++i)
-                h[(size_t)I * stride[l] + a * rp[l + 1] + i + (size_t)j * ld] =
-                    src[off[fi] + i + (size_t)j * kc_];
+                for (int part = 0; part < nc; ++part)
+                  h[part * pl + (size_t)I * stride[l] + a * rp[l + 1] + i + (size_t)j * ld] =
+                      src[(off[fi] + i + (size_t)j * kc_) * nc + part];
           }
-        dst[l] = Buf(ctx, h.size() * sizeof(double));
-        H2_HIP(hipMemcpy(dst[l].d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+        dst[l] = upload(h);
       }
     };
     upload_tr(m->Er, m->Er_off, M->krow, M->rr, M->Tr, M->Tr_stride, "Er");
@@ -636,12 +706,13 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
     for (int l = 0; l <= L; ++l) {
       const LevelNodes& ln = s.lev[l];
       const long long bs = (long long)M->rr[l] * M->rc[l];
+      const size_t pl = (size_t)bs * std::max(1, ln.size());
       if (device_blocks) {
-        M->S[l] = Buf(ctx, (size_t)bs * std::max(1, ln.size()) * sizeof(double));
-        zero(ctx->stream, M->S[l].p(), bs * std::max(1, ln.size()));
+        M->S[l] = Buf(ctx, pl * nc * sizeof(double), false, M->cplx);
+        zero(ctx->stream, M->S[l].p(), (long long)pl);
         continue;
       }
-      std::vector<double> h((size_t)bs * std::max(1, ln.size()), 0.0);
+      std::vector<double> h(pl * nc, 0.0);
       for (int q = 0; q < ln.size(); ++q) {
         const long long g = s.node_base[l] + q;
         if (ln.type[q] != kR) {
@@ -652,19 +723,21 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
         need(m->S_off, g, (long long)kr * kc, "S");
         for (int j = 0; j < kc; ++j)
           for (int i = 0; i < kr; ++i)
-            h[(size_t)q * bs + i + (size_t)j * M->rr[l]] = m->S[m->S_off[g] + i + (size_t)j * kr];
+            for (int part = 0; part < nc; ++part)
+              h[part * pl + (size_t)q * bs + i + (size_t)j * M->rr[l]] =
+                  m->S[(m->S_off[g] + i + (size_t)j * kr) * nc + part];
       }
-      M->S[l] = Buf(ctx, h.size() * sizeof(double));
-      H2_HIP(hipMemcpy(M->S[l].d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+      M->S[l] = upload(h);
     }
     if (device_blocks) {
       const long long nb = (long long)np * np * s.lev[L].size();
-      M->F = Buf(ctx, (size_t)nb * sizeof(double));
+      M->F = Buf(ctx, (size_t)nb * nc * sizeof(double), false, M->cplx);
       zero(ctx->stream, M->F.p(), nb);
     } else {
       const LevelNodes& ln = s.lev[L];
       const long long bs = (long long)np * np;
-      std::vector<double> h((size_t)bs * ln.size(), 0.0);
+      const size_t pl = (size_t)bs * ln.size();
+      std::vector<double> h(pl * nc, 0.0);
       for (int q = 0; q < ln.size(); ++q) {
         const long long g = s.node_base[L] + q;
         if (ln.type[q] != kF) {
@@ -675,14 +748,14 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
         need(m->F_off, g, (long long)ni * nj, "F");
         if (!m->F) throw Error(H2_ERR_ARG, "null F");
         for (int j = 0; j < nj; ++j)
-          for (int i = 0; i < ni; ++i) {
-            const double v = m->F[m->F_off[g] + i + (size_t)j * ni];
-            if (!std::isfinite(v)) throw Error(H2_ERR_NUMERIC, "non-finite dense entry");
-            h[(size_t)q * bs + i + (size_t)j * np] = v;
-          }
+          for (int i = 0; i < ni; ++i)
+            for (int part = 0; part < nc; ++part) {
+              const double v = m->F[(m->F_off[g] + i + (size_t)j * ni) * nc + part];
+              if (!std::isfinite(v)) throw Error(H2_ERR_NUMERIC, "non-finite dense entry");
+              h[part * pl + (size_t)q * bs + i + (size_t)j * np] = v;
+            }
       }
-      M->F = Buf(ctx, h.size() * sizeof(double));
-      H2_HIP(hipMemcpy(M->F.d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+      M->F = upload(h);
     }
     shape->d_perm = Buf(ctx, s.n * sizeof(long long));
     shape->d_leaf_off = Buf(ctx, (nleaf + 1) * sizeof(long long));
@@ -754,13 +827,14 @@ h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nr
   try {
     hipSetDevice(ctx->device);
     const long long n = M->st().n;
+    const long long len = n * nrhs * (M->cplx ? 2 : 1);
     if (x_on_device) {
       matvec_impl(ctx, M, x, y, nrhs);
     } else {
-      Buf xd(ctx, n * nrhs * sizeof(double)), yd(ctx, n * nrhs * sizeof(double));
-      H2_HIP(hipMemcpy(xd.d(), x, n * nrhs * sizeof(double), hipMemcpyHostToDevice));
+      Buf xd(ctx, len * sizeof(double)), yd(ctx, len * sizeof(double));
+      H2_HIP(hipMemcpy(xd.d(), x, len * sizeof(double), hipMemcpyHostToDevice));
       matvec_impl(ctx, M, xd.d(), yd.d(), nrhs);
-      H2_HIP(hipMemcpy(y, yd.d(), n * nrhs * sizeof(double), hipMemcpyDeviceToHost));
+      H2_HIP(hipMemcpy(y, yd.d(), len * sizeof(double), hipMemcpyDeviceToHost));
     }
     return H2_OK;
   } catch (const Error& e) {
@@ -780,13 +854,19 @@ h2_status h2_to_dense(h2_ctx ctx, h2_mat M, double* out, int64_t ld) {
   ActiveCtx active(ctx);
   try {
     hipSetDevice(ctx->device);
-    std::vector<double> eye((size_t)n * n, 0.0);
+    // complex: the identity's imaginary plane is zero; out holds interleaved pairs
+    const int nc = M->cplx ? 2 : 1;
+    const size_t nn = (size_t)n * n;
+    std::vector<double> eye(nn * nc, 0.0);
     for (long long i = 0; i < n; ++i) eye[(size_t)i * n + i] = 1.0;
-    Buf xd(ctx, n * n * sizeof(double)), yd(ctx, n * n * sizeof(double));
-    H2_HIP(hipMemcpy(xd.d(), eye.data(), n * n * sizeof(double), hipMemcpyHostToDevice));
+    Buf xd(ctx, nn * nc * sizeof(double)), yd(ctx, nn * nc * sizeof(double));
+    H2_HIP(hipMemcpy(xd.d(), eye.data(), nn * nc * sizeof(double), hipMemcpyHostToDevice));
     matvec_impl(ctx, M, xd.d(), yd.d(), n);
-    H2_HIP(hipMemcpy(eye.data(), yd.d(), n * n * sizeof(double), hipMemcpyDeviceToHost));
-    for (long long j = 0; j < n; ++j) memcpy(out + j * ld, eye.data() + j * n, n * sizeof(double));
+    H2_HIP(hipMemcpy(eye.data(), yd.d(), nn * nc * sizeof(double), hipMemcpyDeviceToHost));
+    for (long long j = 0; j < n; ++j)
+      for (long long i = 0; i < n; ++i)
+        for (int part = 0; part < nc; ++part)
+          out[(j * ld + i) * nc + part] = eye[part * nn + (size_t)j * n + i];
     return H2_OK;
   } catch (const Error& e) {
     return set_error(e.code, e.msg);
@@ -802,6 +882,7 @@ h2_status h2_export_size(h2_mat M, h2_export_sizes* sz) {
   sz->n = s.n;
   sz->L = L;
   sz->nnodes = s.node_base[L + 1];
+  sz->is_complex = M->cplx ? 1 : 0;
   for (int c = 0; c < (1 << L); ++c) {
     sz->len_V += (int64_t)s.leaf_size[c] * M->krow[cidx(L, c)];
     sz->len_W += (int64_t)s.leaf_size[c] * M->kcol[cidx(L, c)];
@@ -849,11 +930,20 @@ h2_status h2_export(h2_mat M, const h2_export_buffers* o) {
       }
     memcpy(o->krow, M->krow.data(), ncl * sizeof(int64_t));
     memcpy(o->kcol, M->kcol.data(), ncl * sizeof(int64_t));
+    // complex matrices: device planes [real | imaginary] out as interleaved
+    // pairs; offsets count complex elements
+    const int nc = M->cplx ? 2 : 1;
+    size_t pl = 0;  // plane length of the buffer fetched last
     auto fetch = [&](const Buf& b) {
       std::vector<double> h(b.bytes() / sizeof(double));
+      pl = h.size() / nc;
       if (!h.empty())
         H2_HIP(hipMemcpy(h.data(), b.d(), h.size() * sizeof(double), hipMemcpyDeviceToHost));
       return h;
+    };
+    auto put = [&](double* dst, int64_t& p, const std::vector<double>& h, size_t idx) {
+      for (int part = 0; part < nc; ++part) dst[p * nc + part] = h[part * pl + idx];
+      ++p;
     };
     auto leaf = [&](const Buf& b, long long stride, const std::vector<int64_t>& kk, double* dst,
                     int64_t* off) {
@@ -861,9 +951,9 @@ h2_status h2_export(h2_mat M, const h2_export_buffers* o) {
       int64_t p = 0;
       for (int c = 0; c < nleaf; ++c) {
         off[c] = p;
-        const int nc = s.leaf_size[c], k = (int)kk[cidx(L, c)];
+        const int nr = s.leaf_size[c], k = (int)kk[cidx(L, c)];
         for (int j = 0; j < k; ++j)
-          for (int i = 0; i < nc; ++i) dst[p++] = h[(size_t)c * stride + i + (size_t)j * np];
+          for (int i = 0; i < nr; ++i) put(dst, p, h, (size_t)c * stride + i + (size_t)j * np);
       }
       off[nleaf] = p;
     };
@@ -884,7 +974,7 @@ h2_status h2_export(h2_mat M, const h2_export_buffers* o) {
           const int kc_ = (int)kk[fi], kp = (int)kk[cidx(l, c >> 1)];
           for (int j = 0; j < kp; ++j)
             for (int i = 0; i < kc_; ++i)
-              dst[p++] = h[(size_t)(c >> 1) * stride[l] + (c & 1) * rp[l + 1] + i + (size_t)j * ld];
+              put(dst, p, h, (size_t)(c >> 1) * stride[l] + (c & 1) * rp[l + 1] + i + (size_t)j * ld);
         }
       }
       off[ncl] = p;
@@ -895,14 +985,16 @@ h2_status h2_export(h2_mat M, const h2_export_buffers* o) {
     for (int l = 0; l <= L; ++l) {
       const LevelNodes& ln = s.lev[l];
       std::vector<double> hs = M->S[l].bytes() ? fetch(M->S[l]) : std::vector<double>();
+      const size_t pls = pl;
       const long long bs = (long long)M->rr[l] * M->rc[l];
       for (int q = 0; q < ln.size(); ++q) {
         const long long g = s.node_base[l] + q;
         o->S_off[g] = ps;
         if (ln.type[q] == kR) {
           const int kr = (int)M->krow[cidx(l, ln.row[q])], kc = (int)M->kcol[cidx(l, ln.col[q])];
+          pl = pls;
           for (int j = 0; j < kc; ++j)
-            for (int i = 0; i < kr; ++i) o->S[ps++] = hs[(size_t)q * bs + i + (size_t)j * M->rr[l]];
+            for (int i = 0; i < kr; ++i) put(o->S, ps, hs, (size_t)q * bs + i + (size_t)j * M->rr[l]);
         }
       }
     }
@@ -918,7 +1010,7 @@ h2_status h2_export(h2_mat M, const h2_export_buffers* o) {
         if (ln.type[q] == kF) {
           const int ni = s.leaf_size[ln.row[q]], nj = s.leaf_size[ln.col[q]];
           for (int j = 0; j < nj; ++j)
-            for (int i = 0; i < ni; ++i) o->F[pf++] = hf[(size_t)q * np * np + i + (size_t)j * np];
+            for (int i = 0; i < ni; ++i) put(o->F, pf, hf, (size_t)q * np * np + i + (size_t)j * np);
         }
       }
       o->F_off[s.node_base[L + 1]] = pf;
@@ -934,7 +1026,8 @@ h2_status h2_stats(h2_mat M, h2_stats_t* out) {
   std::unique_lock<std::recursive_mutex> lk;
   if (M->ctx) lk = std::unique_lock<std::recursive_mutex>(M->ctx->mu);
   if (M->flops_pending) {
-    M->stats.flops = h2::canonical_flops(M->st(), M->flop_akcol, M->flop_bkrow, *M);
+    // a complex block product is four real ones
+    M->stats.flops = h2::canonical_flops(M->st(), M->flop_akcol, M->flop_bkrow, *M) * (M->cplx ? 4.0 : 1.0);
     M->flops_pending = false;
     std::vector<int64_t>().swap(M->flop_akcol);
     std::vector<int64_t>().swap(M->flop_bkrow);

@@ -984,4 +984,140 @@ hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStre
   }
 }
 
+// ------------------------------------------------ complex Hermitian Grams
+namespace {
+
+__device__ __forceinline__ int live_row(int r, int k1, int half) {
+  return r < k1 ? r : half + (r - k1);
+}
+
+__global__ __launch_bounds__(256) void k_ceig_embed(CEigArgs p0, CEigArgs p1) {
+  const CEigArgs& p = blockIdx.y == 0 ? p0 : p1;
+  const int c = blockIdx.x, D = p.D, D2 = 2 * D, tid = threadIdx.x;
+  __shared__ double red[8];
+  const int k1 = p.k1[(long long)c * p.kstride];
+  const int k2 = p.k2 ? p.k2[(long long)c * p.kstride] : 0;
+  const int n = k1 + k2;
+  const long long gs = (long long)c * D * D;
+  double w[3];
+  for (int m = 0; m < 3; ++m) {
+    double t = 0.0;
+    for (int i = tid; i < D; i += 256) t += p.G[m][gs + i + (long long)i * D];
+    t = block_sum<256>(t, red);
+    w[m] = t > 0.0 ? 1.0 / t : 0.0;
+  }
+  double* E = p.E + (long long)c * D2 * D2;
+  for (long long e = tid; e < (long long)D2 * D2; e += 256) E[e] = 0.0;
+  __syncthreads();
+  int bad = 0;
+  for (int e = tid; e < n * n; e += 256) {
+    const int r = e % n, q = e / n;
+    const long long a = gs + live_row(r, k1, p.half) + (long long)live_row(q, k1, p.half) * D;
+    const long long b = gs + live_row(q, k1, p.half) + (long long)live_row(r, k1, p.half) * D;
+    double xr = 0.0, xi = 0.0;
+    for (int m = 0; m < 3; ++m) {
+      const double* g = p.G[m];
+      xr += w[m] * 0.5 * (g[a] + g[b]);
+      xi += w[m] * 0.5 * (g[p.gplane + a] - g[p.gplane + b]);
+    }
+    if (!(xr == xr) || xr - xr != 0.0 || !(xi == xi) || xi - xi != 0.0) bad = 1;
+    E[r + (long long)q * D2] = xr;
+    E[(D + r) + (long long)(D + q) * D2] = xr;
+    E[(D + r) + (long long)q * D2] = xi;
+    E[r + (long long)(D + q) * D2] = -xi;
+  }
+  if (bad) p.status[0] = 1;
+  if (tid == 0) p.nlive[c] = n;
+}
+
+__global__ __launch_bounds__(256) void k_ceig_extract(CEigArgs p0, CEigArgs p1) {
+  constexpr int NT = 256, NW = NT / 64;
+  const CEigArgs& p = blockIdx.y == 0 ? p0 : p1;
+  const int c = blockIdx.x, D = p.D, D2 = 2 * D, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  __shared__ double zr[256], zi[256], cr[256], ci[256], red[8];
+  const int k1 = p.k1[(long long)c * p.kstride];
+  const int k2 = p.k2 ? p.k2[(long long)c * p.kstride] : 0;
+  const int n = k1 + k2;
+  const int ke = p.rank_e[c];
+  const double* Ue = p.Ue + (long long)c * D2 * D2;
+  double* Ur = p.U + (long long)c * D * D;
+  double* Ui = Ur + p.uplane;
+  for (long long e = tid; e < (long long)D * D; e += NT) {
+    Ur[e] = 0.0;
+    Ui[e] = 0.0;
+  }
+  __syncthreads();
+  int acc = 0;
+  for (int m = 0; m < ke && acc < n; ++m) {
+    for (int r = tid; r < n; r += NT) {
+      zr[r] = Ue[r + (long long)m * D2];
+      zi[r] = Ue[D + r + (long long)m * D2];
+    }
+    __syncthreads();
+    for (int pass = 0; pass < 2 && acc > 0; ++pass) {
+      // coefficients <u_j, z> = sum conj(u_j) z
+      for (int j = wave; j < acc; j += NW) {
+        double sr = 0.0, si = 0.0;
+        for (int r = lane; r < n; r += 64) {
+          const long long o = live_row(r, k1, p.half) + (long long)j * D;
+          const double ur = Ur[o], ui = Ui[o];
+          sr += ur * zr[r] + ui * zi[r];
+          si += ur * zi[r] - ui * zr[r];
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) {
+          cr[j] = sr;
+          ci[j] = si;
+        }
+      }
+      __syncthreads();
+      for (int r = tid; r < n; r += NT) {
+        const int pr = live_row(r, k1, p.half);
+        double dr = 0.0, di = 0.0;
+        for (int j = 0; j < acc; ++j) {
+          const double ur = Ur[pr + (long long)j * D], ui = Ui[pr + (long long)j * D];
+          dr += cr[j] * ur - ci[j] * ui;
+          di += cr[j] * ui + ci[j] * ur;
+        }
+        zr[r] -= dr;
+        zi[r] -= di;
+      }
+      __syncthreads();
+    }
+    double t = 0.0;
+    for (int r = tid; r < n; r += NT) t += zr[r] * zr[r] + zi[r] * zi[r];
+    const double nrm2 = block_sum<NT>(t, red);
+    if (nrm2 > 0.5) {
+      const double inv = 1.0 / sqrt(nrm2);
+      for (int r = tid; r < n; r += NT) {
+        const long long o = live_row(r, k1, p.half) + (long long)acc * D;
+        Ur[o] = zr[r] * inv;
+        Ui[o] = zi[r] * inv;
+      }
+      ++acc;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) p.rank[c] = acc;
+}
+
+}  // namespace
+
+hipError_t launch_ceig_embed(const CEigArgs& a, const CEigArgs& b, int nclusters, hipStream_t s) {
+  if (nclusters <= 0) return hipSuccess;
+  if (2 * (a.D > b.D ? a.D : b.D) > kEigNmax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ceig_embed, dim3(nclusters, 2), dim3(256), 0, s, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_ceig_extract(const CEigArgs& a, const CEigArgs& b, int nclusters,
+                               hipStream_t s) {
+  if (nclusters <= 0) return hipSuccess;
+  if (a.D > 256 || b.D > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ceig_extract, dim3(nclusters, 2), dim3(256), 0, s, a, b);
+  return hipGetLastError();
+}
+
 }  // namespace h2k

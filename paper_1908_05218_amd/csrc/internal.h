@@ -58,7 +58,16 @@ struct h2_ctx_s {
   std::multimap<size_t, void*> pool;
   std::unordered_map<void*, size_t> live;
   std::unordered_set<void*> f32;  // live allocations that hold float elements
-  void* alloc(size_t bytes, bool is_f32 = false);
+  // live complex allocations: [real plane | imaginary plane] of doubles, the
+  // value is the plane's length in elements
+  std::unordered_map<void*, long long> planes;
+  void* alloc(size_t bytes, bool is_f32 = false, bool is_cplx = false);
+  void* alloc_raw(size_t bytes, bool is_f32);
+  // imaginary-plane offset (elements) of the complex allocation starting at p, else 0
+  long long plane(const void* p) const {
+    auto it = planes.find(const_cast<void*>(p));
+    return it == planes.end() ? 0 : it->second;
+  }
   // element size of the live allocation starting at p (4 or 8)
   size_t elt(const void* p) const { return f32.count(const_cast<void*>(p)) ? 4 : 8; }
   void release(void* p);
@@ -80,8 +89,9 @@ namespace h2 {
 class Buf {
  public:
   Buf() = default;
-  Buf(h2_ctx c, size_t bytes, bool is_f32 = false) : ctx_(c), bytes_(bytes) {
-    p_ = bytes ? c->alloc(bytes, is_f32) : nullptr;
+  // is_cplx: bytes / 16 complex elements stored as two planes of doubles
+  Buf(h2_ctx c, size_t bytes, bool is_f32 = false, bool is_cplx = false) : ctx_(c), bytes_(bytes) {
+    p_ = bytes ? c->alloc(bytes, is_f32, is_cplx) : nullptr;
   }
   ~Buf() { reset(); }
   Buf(const Buf&) = delete;
@@ -157,6 +167,7 @@ struct h2_mat_s {
   std::vector<h2::Buf> S;          // per level, flat by node, rr[l] x rc[l]
   h2::Buf F;                       // leaf level, flat by node, npad x npad
   h2_stats_t stats{};
+  bool cplx = false;  // complex128 data (every block buffer holds two planes)
   // ranks of the operands a product's canonical flop count needs (counted
   // on the first h2_stats call)
   std::vector<int64_t> flop_akcol, flop_bkrow;
@@ -199,12 +210,18 @@ struct Profiler {
 
 // Batched segmented product.  The arithmetic is FP32 for the bulk kinds
 // (kKindOther, kKindTriple) while g_bulk_f32 is set, FP64 otherwise (always for
-// kKindGram); operands and C may be float or double allocations.
+// kKindGram); operands and C may be float or double allocations.  When C is a
+// complex allocation, A and B must be complex too: the product runs as four
+// real products over the planes; conj bit 0 / bit 1 conjugates A / B (after
+// the transposition flags, so tA with bit 0 is A^H).
+constexpr int kConjA = 1, kConjB = 2;
 void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int n, int k,
           const Op& A, bool tA, const Op& B, bool tB, void* C, long long cstride, int ldc,
-          long long csub_r, long long csub_c, double alpha, double beta);
+          long long csub_r, long long csub_c, double alpha, double beta, int conj = 0);
+// segmented sums (both planes of complex allocations)
 void segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, void* C,
             long long cstride, int ldc, long long csub_r, long long csub_c, double beta);
+// n elements (both planes of a complex allocation)
 void zero(hipStream_t s, void* p, long long n);
 // float copy of M's data for FP32-bulk products (cached in M->f32)
 const h2_mat_s& f32_shadow(h2_ctx ctx, h2_mat M, hipStream_t s);

@@ -83,6 +83,39 @@ struct EigArgs {
   int* status;  // [0] non-finite, [1] dimension over limit
 };
 
+// Complex Hermitian Gram matrices through the real eigensolver.  A Hermitian
+// H = X + iY has the same eigenvalues as the real symmetric [[X, -Y], [Y, X]],
+// each twice; an eigenvector [a; b] of the embedding gives the complex
+// eigenvector a + ib, and the two copies of an eigenvalue give the same
+// complex direction (up to a phase).
+//  embed: H = sum_m G_m / Re tr(G_m) (Hermitian part) of cluster c, rows and
+//    columns restricted to [0,k1) and [half, half+k2) and compacted to n live
+//    rows, into E (2D x 2D): [0,n) real block, [D, D+n) imaginary block;
+//    nlive[c] = n;
+//  extract: the kept real eigenvectors (column m of Ue, rank_e[c] of them)
+//    mapped to a + ib and orthonormalised in order by complex Gram-Schmidt
+//    (twice); a vector left with less than half its norm repeats an accepted
+//    direction and is dropped.  The accepted vectors go to U (D x D, planes
+//    [real | imaginary] at +uplane, padded rows), rank[c] = their count.
+struct CEigArgs {
+  const double* G[3];  // complex Gram components (cluster stride D*D, planes at +gplane)
+  long long gplane;
+  int D, half;
+  const int* k1;
+  const int* k2;  // null: none
+  int kstride;
+  double* E;      // 2D x 2D per cluster
+  int* nlive;
+  const double* Ue;  // 2D x 2D per cluster: real eigenvectors of E
+  const int* rank_e;
+  double* U;
+  long long uplane;
+  int* rank;
+  int* status;
+};
+hipError_t launch_ceig_embed(const CEigArgs& a, const CEigArgs& b, int nclusters, hipStream_t s);
+hipError_t launch_ceig_extract(const CEigArgs& a, const CEigArgs& b, int nclusters, hipStream_t s);
+
 constexpr int kEigNmax = 512;  // largest Gram dimension
 constexpr int kEigLdsN = 195;  // largest dimension whose packed triangle stays in LDS
 // scratch per cluster (doubles) the eigensolver needs for padded dimension D

@@ -81,7 +81,14 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   // eps^2 lambda_1, far below FP32 rounding of a squared quantity), and the
   // eigen-decompositions and bases stay FP64
   const bool bulk = prec == H2_PREC_FP32_BULK;
-  const size_t eb = bulk ? sizeof(float) : sizeof(double);
+  // complex128 (Section II allows complex kernels): every block buffer holds a
+  // real and an imaginary plane; products run as four real products and the
+  // new bases come from the Hermitian Gram sums
+  const bool cplx = A->cplx;
+  if (B->cplx != cplx) throw Error(H2_ERR_ARG, "A and B must both be real or both complex");
+  if (cplx && bulk) throw Error(H2_ERR_UNSUPPORTED, "complex products run in FP64 only");
+  const size_t eb = cplx ? 2 * sizeof(double) : bulk ? sizeof(float) : sizeof(double);
+  const size_t gb = cplx ? 2 * sizeof(double) : sizeof(double);  // Gram-side element
   BulkScope bulk_scope(bulk);
   const auto t_sym0 = std::chrono::steady_clock::now();
   Shape& sh = *A->shape;
@@ -140,18 +147,18 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
 
   // ---------------------------------------------------------- step 0: Pi
   std::vector<Buf> Pi(L + 1);
-  Pi[L] = Buf(ctx, (size_t)nleaf * rcA[L] * rrB[L] * eb, bulk);
+  Pi[L] = Buf(ctx, (size_t)nleaf * rcA[L] * rrB[L] * eb, bulk, cplx);
   gemm(st, pp, kKindOther, dl(P.pi.leaf), rcA[L], rrB[L], np,
        Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, true, Op{Bd->V.p(), nullptr, B->V_stride, 0, np},
        false, Pi[L].p(), (long long)rcA[L] * rrB[L], rcA[L], 0, 0, 1.0, 0.0);
   for (int l = L - 1; l >= lmin; --l) {
     const int ch = l + 1;
-    Buf X(ctx, (size_t)(2 << l) * rcA[ch] * rrB[l] * eb, bulk);
+    Buf X(ctx, (size_t)(2 << l) * rcA[ch] * rrB[l] * eb, bulk, cplx);
     gemm(st, pp, kKindOther, dl(P.pi.X[l]), rcA[ch], rrB[l], rrB[ch],
          Op{Pi[ch].p(), nullptr, (long long)rcA[ch] * rrB[ch], 0, rcA[ch]}, false,
          Op{Bd->Tr[l].p(), nullptr, B->Tr_stride[l], 0, 2 * rrB[ch], rrB[ch], 0}, false, X.p(),
          (long long)rcA[ch] * rrB[l], rcA[ch], 0, 0, 1.0, 0.0);
-    Pi[l] = Buf(ctx, (size_t)(1 << l) * rcA[l] * rrB[l] * eb, bulk);
+    Pi[l] = Buf(ctx, (size_t)(1 << l) * rcA[l] * rrB[l] * eb, bulk, cplx);
     gemm(st, pp, kKindOther, dl(P.pi.S[l]), rcA[l], rrB[l], rcA[ch],
          Op{Ad->Tc[l].p(), nullptr, A->Tc_stride[l], 0, 2 * rcA[ch], rcA[ch], 0}, true,
          Op{X.p(), nullptr, (long long)rcA[ch] * rrB[l], 0, rcA[ch]}, false, Pi[l].p(),
@@ -164,11 +171,74 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
                        Buf& rank_c_, const int* k1r, const int* k2r, const int* k1c,
                        const int* k2c, int kstride, int half) {
     const int ncl = 1 << l;
-    if (D > h2k::kEigNmax)
+    if ((cplx ? 2 * D : D) > h2k::kEigNmax)
       throw Error(H2_ERR_UNSUPPORTED, "the Gram matrices at level " + std::to_string(l) +
                                           " have dimension " + std::to_string(D) +
+                                          (cplx ? " (complex)" : "") +
                                           ", beyond the eigensolver limit of " +
-                                          std::to_string(h2k::kEigNmax));
+                                          std::to_string(cplx ? h2k::kEigNmax / 2 : h2k::kEigNmax));
+    if (cplx) {
+      // Hermitian Grams through their real embedding (dimension 2D)
+      const int D2 = 2 * D;
+      Buf E[2] = {Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double)),
+                  Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double))};
+      Buf Ue[2] = {Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double)),
+                   Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double))};
+      Buf nlive(ctx, (size_t)2 * ncl * sizeof(int)), rank_e(ctx, (size_t)2 * ncl * sizeof(int));
+      Ur_ = Buf(ctx, (size_t)ncl * D * D * gb, false, true);
+      Uc_ = Buf(ctx, (size_t)ncl * D * D * gb, false, true);
+      rank_r_ = Buf(ctx, (size_t)ncl * sizeof(int));
+      rank_c_ = Buf(ctx, (size_t)ncl * sizeof(int));
+      h2k::CEigArgs ca[2];
+      for (int side = 0; side < 2; ++side) {
+        h2k::CEigArgs& a = ca[side];
+        a = h2k::CEigArgs{};
+        for (int c = 0; c < 3; ++c) a.G[c] = (side ? Gc : Gr)[c].d();
+        a.gplane = ctx->plane((side ? Gc : Gr)[0].p());
+        a.D = D;
+        a.half = half;
+        a.k1 = side ? k1c : k1r;
+        a.k2 = side ? k2c : k2r;
+        a.kstride = kstride;
+        a.E = E[side].d();
+        a.nlive = nlive.as<int>() + side * ncl;
+        a.Ue = Ue[side].d();
+        a.rank_e = rank_e.as<int>() + side * ncl;
+        a.U = (side ? Uc_ : Ur_).d();
+        a.uplane = ctx->plane((side ? Uc_ : Ur_).p());
+        a.rank = (side ? rank_c_ : rank_r_).as<int>();
+        a.status = status.as<int>();
+      }
+      H2_HIP(h2k::launch_ceig_embed(ca[0], ca[1], ncl, st));
+      const long long ss = h2k::eig_scratch_doubles(D2);
+      Buf scratch(ctx, (size_t)2 * ncl * ss * sizeof(double));
+      h2k::EigArgs ea[2];
+      for (int side = 0; side < 2; ++side) {
+        h2k::EigArgs& e = ea[side];
+        e = h2k::EigArgs{};
+        e.G = E[side].d();
+        e.gstride = (long long)D2 * D2;
+        e.D = D2;
+        e.U = Ue[side].d();
+        e.ustride = (long long)D2 * D2;
+        e.rank = rank_e.as<int>() + side * ncl;
+        e.k1 = nlive.as<int>() + side * ncl;
+        e.k2 = nlive.as<int>() + side * ncl;
+        e.kstride = 1;
+        e.half = D;
+        e.scratch = scratch.d() + (size_t)side * ncl * ss;
+        e.sstride = ss;
+        e.tau = tau;
+        e.exact = exact ? 1 : 0;
+        e.status = status.as<int>();
+      }
+      hipEvent_t ev = nullptr;
+      prof.begin(kKindEig, 0, &ev);
+      H2_HIP(h2k::launch_eig(ea[0], ea[1], ncl, st));
+      H2_HIP(h2k::launch_ceig_extract(ca[0], ca[1], ncl, st));
+      prof.end(ev, kKindEig, 0);
+      return;
+    }
     Buf Gnr(ctx, (size_t)ncl * D * D * sizeof(double)), Gnc(ctx, (size_t)ncl * D * D * sizeof(double));
     for (int side = 0; side < 2; ++side) {
       h2k::GramNormArgs ga{};
@@ -247,42 +317,42 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   {
     Buf G[3], Gc[3];
     for (int k = 0; k < 3; ++k) {
-      G[k] = Buf(ctx, (size_t)nleaf * nn2 * sizeof(double));
-      Gc[k] = Buf(ctx, (size_t)nleaf * nn2 * sizeof(double));
+      G[k] = Buf(ctx, (size_t)nleaf * nn2 * gb, false, cplx);
+      Gc[k] = Buf(ctx, (size_t)nleaf * nn2 * gb, false, cplx);
     }
     {
-      Buf b1(ctx, nnL * nn2 * sizeof(double)), b2(ctx, nnL * nn2 * sizeof(double)),
-          b3(ctx, nnL * nn2 * sizeof(double));
+      Buf b1(ctx, nnL * nn2 * gb, false, cplx), b2(ctx, nnL * nn2 * gb, false, cplx),
+          b3(ctx, nnL * nn2 * gb, false, cplx);
       const Op FA{Ad->F.p(), nullptr, nn2, 0, np}, FB{Bd->F.p(), nullptr, nn2, 0, np};
       const Op o1{b1.p(), nullptr, nn2, 0, np}, o2{b2.p(), nullptr, nn2, 0, np},
           o3{b3.p(), nullptr, nn2, 0, np};
       // row Gram, case 1: sum_j F^A_ij (sum_k F^B_jk F^B_jk^T) F^A_ij^T over
       // dense products with an admissible or blue target (equation Gr1L)
-      gemm(st, pp, kKindGram, dl(LP.gB), np, np, np, FB, false, FB, true, b1.p(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.gB), np, np, np, FB, false, FB, true, b1.p(), nn2, np, 0, 0, 1, 0, kConjB);
       segsum(st, dl(LP.H), np, np, o1, b2.p(), nn2, np, 0, 0, 0.0);
       gemm(st, pp, kKindGram, dl(LP.X1), np, np, np, FA, false, o2, false, b3.p(), nn2, np, 0, 0, 1, 0);
-      gemm(st, pp, kKindGram, dl(LP.G1), np, np, np, o3, false, FA, true, G[0].p(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G1), np, np, np, o3, false, FA, true, G[0].p(), nn2, np, 0, 0, 1, 0, kConjB);
       // column Gram, case 1 (equation case1-ch)
-      gemm(st, pp, kKindGram, dl(LP.hA), np, np, np, FA, true, FA, false, b1.p(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.hA), np, np, np, FA, true, FA, false, b1.p(), nn2, np, 0, 0, 1, 0, kConjB);
       segsum(st, dl(LP.Hc), np, np, o1, b2.p(), nn2, np, 0, 0, 0.0);
       gemm(st, pp, kKindGram, dl(LP.X1c), np, np, np, FB, true, o2, false, b3.p(), nn2, np, 0, 0, 1, 0);
-      gemm(st, pp, kKindGram, dl(LP.G1c), np, np, np, o3, false, FB, false, Gc[0].p(), nn2, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindGram, dl(LP.G1c), np, np, np, o3, false, FB, false, Gc[0].p(), nn2, np, 0, 0, 1, 0, kConjB);
       // case 2: F^A_ij V^B_j (Gr2L) and (W^A_j^T F^B_jk)^T (case2-ch)
-      Buf Z(ctx, (size_t)nnL * np * std::max(rrB[L], rcA[L]) * sizeof(double));
+      Buf Z(ctx, (size_t)nnL * np * std::max(rrB[L], rcA[L]) * gb, false, cplx);
       const long long zs = (long long)np * rrB[L], zcs = (long long)np * rcA[L];
       gemm(st, pp, kKindGram, dl(LP.Z), np, rrB[L], np, FA, false,
            Op{Bd->V.p(), nullptr, B->V_stride, 0, np}, false, Z.p(), zs, np, 0, 0, 1, 0);
       gemm(st, pp, kKindGram, dl(LP.G2), np, np, rrB[L], Op{Z.p(), nullptr, zs, 0, np}, false,
-           Op{Z.p(), nullptr, zs, 0, np}, true, G[1].p(), nn2, np, 0, 0, 1, 0);
+           Op{Z.p(), nullptr, zs, 0, np}, true, G[1].p(), nn2, np, 0, 0, 1, 0, kConjB);
       gemm(st, pp, kKindGram, dl(LP.Zc), np, rcA[L], np, FB, true,
            Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, false, Z.p(), zcs, np, 0, 0, 1, 0);
       gemm(st, pp, kKindGram, dl(LP.G2c), np, np, rcA[L], Op{Z.p(), nullptr, zcs, 0, np}, false,
-           Op{Z.p(), nullptr, zcs, 0, np}, true, Gc[1].p(), nn2, np, 0, 0, 1, 0);
+           Op{Z.p(), nullptr, zcs, 0, np}, true, Gc[1].p(), nn2, np, 0, 0, 1, 0, kConjB);
       // case 3/4: the old bases V^A_i V^A_i^T (Gr3L) and W^B_k W^B_k^T (case3-ch)
       gemm(st, pp, kKindGram, dl(LP.G3), np, np, rrA[L], Op{Ad->V.p(), nullptr, A->V_stride, 0, np},
-           false, Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, true, G[2].p(), nn2, np, 0, 0, 1, 0);
+           false, Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, true, G[2].p(), nn2, np, 0, 0, 1, 0, kConjB);
       gemm(st, pp, kKindGram, dl(LP.G3c), np, np, rcB[L], Op{Bd->W.p(), nullptr, B->W_stride, 0, np},
-           false, Op{Bd->W.p(), nullptr, B->W_stride, 0, np}, true, Gc[2].p(), nn2, np, 0, 0, 1, 0);
+           false, Op{Bd->W.p(), nullptr, B->W_stride, 0, np}, true, Gc[2].p(), nn2, np, 0, 0, 1, 0, kConjB);
     }
     eig_level(L, np, G, Gc, Ur_L, Uc_L, rank_r[L], rank_c[L], leaf_sizes.as<int>(), nullptr,
               leaf_sizes.as<int>(), nullptr, 1, np);
@@ -294,19 +364,19 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     const Op VC{Ur_L.p(), nullptr, nn2, 0, np}, WC{Uc_L.p(), nullptr, nn2, 0, np};
     const Op FA{Ad->F.p(), nullptr, nn2, 0, np}, FB{Bd->F.p(), nullptr, nn2, 0, np};
     // projections (leafproj)
-    PA_L = Buf(ctx, (size_t)nleaf * c * rrA[L] * eb, bulk);
-    PB_L = Buf(ctx, (size_t)nleaf * rcB[L] * c * eb, bulk);
+    PA_L = Buf(ctx, (size_t)nleaf * c * rrA[L] * eb, bulk, cplx);
+    PB_L = Buf(ctx, (size_t)nleaf * rcB[L] * c * eb, bulk, cplx);
     gemm(st, pp, kKindOther, dl(LP.PA), c, rrA[L], np, VC, true,
-         Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, false, PA_L.p(), (long long)c * rrA[L], c, 0, 0, 1, 0);
+         Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, false, PA_L.p(), (long long)c * rrA[L], c, 0, 0, 1, 0, kConjA);
     gemm(st, pp, kKindOther, dl(LP.PB), rcB[L], c, np, Op{Bd->W.p(), nullptr, B->W_stride, 0, np},
-         true, WC, false, PB_L.p(), (long long)rcB[L] * c, rcB[L], 0, 0, 1, 0);
+         true, WC, false, PB_L.p(), (long long)rcB[L] * c, rcB[L], 0, 0, 1, 0, kConjB);
     // leaf-coordinate left / right operands of every leaf block
     const long long las = (long long)c * np;
-    Buf LA(ctx, (size_t)nnL * las * eb, bulk), RB(ctx, (size_t)nnL * las * eb, bulk);
+    Buf LA(ctx, (size_t)nnL * las * eb, bulk, cplx), RB(ctx, (size_t)nnL * las * eb, bulk, cplx);
     {
-      Buf PS(ctx, (size_t)nnL * c * rcA[L] * eb, bulk);
-      Buf SP(ctx, (size_t)nnL * rrB[L] * c * eb, bulk);
-      gemm(st, pp, kKindOther, dl(LP.LA_F), c, np, np, VC, true, FA, false, LA.p(), las, c, 0, 0, 1, 0);
+      Buf PS(ctx, (size_t)nnL * c * rcA[L] * eb, bulk, cplx);
+      Buf SP(ctx, (size_t)nnL * rrB[L] * c * eb, bulk, cplx);
+      gemm(st, pp, kKindOther, dl(LP.LA_F), c, np, np, VC, true, FA, false, LA.p(), las, c, 0, 0, 1, 0, kConjA);
       gemm(st, pp, kKindOther, dl(LP.PS), c, rcA[L], rrA[L],
            Op{PA_L.p(), nullptr, (long long)c * rrA[L], 0, c}, false,
            Op{Ad->S[L].p(), nullptr, (long long)rrA[L] * rcA[L], 0, rrA[L]}, false, PS.p(),
@@ -314,7 +384,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       gemm(st, pp, kKindOther, dl(LP.LA_R), c, np, rcA[L],
            Op{PS.p(), nullptr, (long long)c * rcA[L], 0, c}, false,
            Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, true, LA.p(), las, c, 0, 0, 1, 0);
-      gemm(st, pp, kKindOther, dl(LP.RB_F), np, c, np, FB, false, WC, false, RB.p(), las, np, 0, 0, 1, 0);
+      gemm(st, pp, kKindOther, dl(LP.RB_F), np, c, np, FB, false, WC, false, RB.p(), las, np, 0, 0, 1, 0, kConjB);
       gemm(st, pp, kKindOther, dl(LP.SP), rrB[L], c, rcB[L],
            Op{Bd->S[L].p(), nullptr, (long long)rrB[L] * rcB[L], 0, rrB[L]}, false,
            Op{PB_L.p(), nullptr, (long long)rcB[L] * c, 0, rcB[L]}, false, SP.p(),
@@ -326,8 +396,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     // collected leaf blocks for the level above (Fcollect; 2x2 grouped)
     if (L >= 1) {
       const int ntile = s.lev[L - 1].n_nl;
-      Ahat_L = Buf(ctx, (size_t)ntile * 4 * c * rrB[L] * eb, bulk);
-      Bhat_L = Buf(ctx, (size_t)ntile * 4 * rcA[L] * c * eb, bulk);
+      Ahat_L = Buf(ctx, (size_t)ntile * 4 * c * rrB[L] * eb, bulk, cplx);
+      Bhat_L = Buf(ctx, (size_t)ntile * 4 * rcA[L] * c * eb, bulk, cplx);
       gemm(st, pp, kKindOther, dl(LP.Ahat), c, rrB[L], np, Op{LA.p(), nullptr, las, 0, c}, false,
            Op{Bd->V.p(), nullptr, B->V_stride, 0, np}, false, Ahat_L.p(), 4LL * c * rrB[L], 2 * c,
            c, (long long)rrB[L] * 2 * c, 1, 0);
@@ -336,10 +406,10 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
            rcA[L], (long long)c * 2 * rcA[L], 1, 0);
     }
     // products into admissible and blue targets (leafcoup_simple)
-    C->S[L] = Buf(ctx, (size_t)nnL * c * c * eb, bulk);
+    C->S[L] = Buf(ctx, (size_t)nnL * c * c * eb, bulk, cplx);
     zero(st, C->S[L].p(), (long long)nnL * c * c);
     const int nbt = std::max(1, LP.n_blue_tiles);
-    Acc_L = Buf(ctx, (size_t)nbt * 4 * c * c * eb, bulk);
+    Acc_L = Buf(ctx, (size_t)nbt * 4 * c * c * eb, bulk, cplx);
     zero(st, Acc_L.p(), (long long)nbt * 4 * c * c);
     gemm(st, pp, kKindTriple, dl(LP.adm_R), c, c, np, Op{LA.p(), nullptr, las, 0, c}, false,
          Op{RB.p(), nullptr, las, 0, np}, false, C->S[L].p(), (long long)c * c, c, 0, 0, 1, 1);
@@ -349,11 +419,11 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   }
   {
     // dense targets: exact leaf products with admissible factors densified
-    FC = Buf(ctx, (size_t)nnL * nn2 * eb, bulk);
+    FC = Buf(ctx, (size_t)nnL * nn2 * eb, bulk, cplx);
     zero(st, FC.p(), nnL * nn2);
-    Buf DA(ctx, (size_t)nnL * nn2 * eb, bulk), DB(ctx, (size_t)nnL * nn2 * eb, bulk);
+    Buf DA(ctx, (size_t)nnL * nn2 * eb, bulk, cplx), DB(ctx, (size_t)nnL * nn2 * eb, bulk, cplx);
     {
-      Buf T(ctx, (size_t)nnL * np * std::max(rcA[L], rcB[L]) * eb, bulk);
+      Buf T(ctx, (size_t)nnL * np * std::max(rcA[L], rcB[L]) * eb, bulk, cplx);
       gemm(st, pp, kKindOther, dl(LP.densA1), np, rcA[L], rrA[L],
            Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, false,
            Op{Ad->S[L].p(), nullptr, (long long)rrA[L] * rcA[L], 0, rrA[L]}, false, T.p(),
@@ -390,42 +460,42 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     const Op AccT{Acc_ch.p(), nullptr, 4LL * cc * cc, 0, K};
     Buf G[3], Gc[3];
     for (int k = 0; k < 3; ++k) {
-      G[k] = Buf(ctx, (size_t)ncl * K2 * sizeof(double));
-      Gc[k] = Buf(ctx, (size_t)ncl * K2 * sizeof(double));
+      G[k] = Buf(ctx, (size_t)ncl * K2 * gb, false, cplx);
+      Gc[k] = Buf(ctx, (size_t)ncl * K2 * gb, false, cplx);
     }
     // case 1: merged children couplings M_IK (nonleafA; case1-ch-nl)
-    gemm(st, pp, kKindGram, dl(Q.G1), K, K, K, AccT, false, AccT, true, G[0].p(), K2, K, 0, 0, 1, 0);
-    gemm(st, pp, kKindGram, dl(Q.G1c), K, K, K, AccT, true, AccT, false, Gc[0].p(), K2, K, 0, 0, 1, 0);
+    gemm(st, pp, kKindGram, dl(Q.G1), K, K, K, AccT, false, AccT, true, G[0].p(), K2, K, 0, 0, 1, 0, kConjB);
+    gemm(st, pp, kKindGram, dl(Q.G1c), K, K, K, AccT, true, AccT, false, Gc[0].p(), K2, K, 0, 0, 1, 0, kConjB);
     // case 2: (NL^A)_coll T^B_J (case2-ch-nl) and its column mirror
     const long long ys = (long long)K * rrB[l], ycs = (long long)rcA[l] * K;
-    Buf Y(ctx, (size_t)std::max(1, nn) * ys * sizeof(double));
-    Buf Yc(ctx, (size_t)std::max(1, nn) * ycs * sizeof(double));
+    Buf Y(ctx, (size_t)std::max(1, nn) * ys * gb, false, cplx);
+    Buf Yc(ctx, (size_t)std::max(1, nn) * ycs * gb, false, cplx);
     gemm(st, pp, kKindGram, dl(Q.Y), K, rrB[l], 2 * rrB[ch],
          Op{Ahat_ch.p(), nullptr, 4LL * cc * rrB[ch], 0, K}, false,
          Op{Bd->Tr[l].p(), nullptr, B->Tr_stride[l], 0, 2 * rrB[ch]}, false, Y.p(), ys, K, 0, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.G2), K, K, rrB[l], Op{Y.p(), nullptr, ys, 0, K}, false,
-         Op{Y.p(), nullptr, ys, 0, K}, true, G[1].p(), K2, K, 0, 0, 1, 0);
+         Op{Y.p(), nullptr, ys, 0, K}, true, G[1].p(), K2, K, 0, 0, 1, 0, kConjB);
     gemm(st, pp, kKindGram, dl(Q.Yc), rcA[l], K, 2 * rcA[ch],
          Op{Ad->Tc[l].p(), nullptr, A->Tc_stride[l], 0, 2 * rcA[ch]}, true,
          Op{Bhat_ch.p(), nullptr, 4LL * rcA[ch] * cc, 0, 2 * rcA[ch]}, false, Yc.p(), ycs, rcA[l],
          0, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.G2c), K, K, rcA[l], Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, true,
-         Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, false, Gc[1].p(), K2, K, 0, 0, 1, 0);
+         Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, false, Gc[1].p(), K2, K, 0, 0, 1, 0, kConjB);
     // cases 3/4: old bases projected on the children's new bases (case3-ch-nl)
     const long long ds = (long long)K * rrA[l], qs = (long long)K * rcB[l];
-    Buf Dm(ctx, (size_t)ncl * ds * sizeof(double)), Qm(ctx, (size_t)ncl * qs * sizeof(double));
+    Buf Dm(ctx, (size_t)ncl * ds * gb, false, cplx), Qm(ctx, (size_t)ncl * qs * gb, false, cplx);
     gemm(st, pp, kKindGram, dl(Q.D), cc, rrA[l], rrA[ch],
          Op{PA_ch.p(), nullptr, (long long)cc * rrA[ch], 0, cc}, false,
          Op{Ad->Tr[l].p(), nullptr, A->Tr_stride[l], 0, 2 * rrA[ch], rrA[ch], 0}, false, Dm.p(), ds,
          K, cc, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.G3), K, K, rrA[l], Op{Dm.p(), nullptr, ds, 0, K}, false,
-         Op{Dm.p(), nullptr, ds, 0, K}, true, G[2].p(), K2, K, 0, 0, 1, 0);
+         Op{Dm.p(), nullptr, ds, 0, K}, true, G[2].p(), K2, K, 0, 0, 1, 0, kConjB);
     gemm(st, pp, kKindGram, dl(Q.Q), cc, rcB[l], rcB[ch],
          Op{PB_ch.p(), nullptr, (long long)rcB[ch] * cc, 0, rcB[ch]}, true,
          Op{Bd->Tc[l].p(), nullptr, B->Tc_stride[l], 0, 2 * rcB[ch], rcB[ch], 0}, false, Qm.p(), qs,
          K, cc, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.G3c), K, K, rcB[l], Op{Qm.p(), nullptr, qs, 0, K}, false,
-         Op{Qm.p(), nullptr, qs, 0, K}, true, Gc[2].p(), K2, K, 0, 0, 1, 0);
+         Op{Qm.p(), nullptr, qs, 0, K}, true, Gc[2].p(), K2, K, 0, 0, 1, 0, kConjB);
     // new transfer matrices
     eig_level(l, K, G, Gc, Ur[l], Uc[l], rank_r[l], rank_c[l], rank_r[ch].as<int>(),
               rank_r[ch].as<int>() + 1, rank_c[ch].as<int>(), rank_c[ch].as<int>() + 1, 2, cc);
@@ -442,22 +512,22 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     cpad[l] = cl;
     const Op TCr{Ur[l].p(), nullptr, K2, 0, K}, TCc{Uc[l].p(), nullptr, K2, 0, K};
     // projections (nonleafproj)
-    Buf PA_l(ctx, (size_t)ncl * cl * rrA[l] * eb, bulk);
-    Buf PB_l(ctx, (size_t)ncl * rcB[l] * cl * eb, bulk);
+    Buf PA_l(ctx, (size_t)ncl * cl * rrA[l] * eb, bulk, cplx);
+    Buf PB_l(ctx, (size_t)ncl * rcB[l] * cl * eb, bulk, cplx);
     gemm(st, pp, kKindOther, dl(Q.PA), cl, rrA[l], K, TCr, true, Op{Dm.p(), nullptr, ds, 0, K},
-         false, PA_l.p(), (long long)cl * rrA[l], cl, 0, 0, 1, 0);
+         false, PA_l.p(), (long long)cl * rrA[l], cl, 0, 0, 1, 0, kConjA);
     gemm(st, pp, kKindOther, dl(Q.PB), rcB[l], cl, K, Op{Qm.p(), nullptr, qs, 0, K}, true, TCc,
-         false, PB_l.p(), (long long)rcB[l] * cl, rcB[l], 0, 0, 1, 0);
+         false, PB_l.p(), (long long)rcB[l] * cl, rcB[l], 0, 0, 1, 0, kConjB);
     // collected blocks of this level (NLcollect; admissible ones projected)
     const int ntile = l >= 1 ? s.lev[l - 1].n_nl : 1;
-    Buf Ahat_l(ctx, (size_t)std::max(1, ntile) * 4 * cl * rrB[l] * eb, bulk);
-    Buf Bhat_l(ctx, (size_t)std::max(1, ntile) * 4 * rcA[l] * cl * eb, bulk);
+    Buf Ahat_l(ctx, (size_t)std::max(1, ntile) * 4 * cl * rrB[l] * eb, bulk, cplx);
+    Buf Bhat_l(ctx, (size_t)std::max(1, ntile) * 4 * rcA[l] * cl * eb, bulk, cplx);
     const long long pas_s = (long long)cl * rcA[l], sbp_s = (long long)rrB[l] * cl;
-    Buf PAS(ctx, (size_t)std::max(1, nn) * pas_s * eb, bulk);
-    Buf SBP(ctx, (size_t)std::max(1, nn) * sbp_s * eb, bulk);
+    Buf PAS(ctx, (size_t)std::max(1, nn) * pas_s * eb, bulk, cplx);
+    Buf SBP(ctx, (size_t)std::max(1, nn) * sbp_s * eb, bulk, cplx);
     const long long at_s = 4LL * cl * rrB[l], bt_s = 4LL * rcA[l] * cl;
     gemm(st, pp, kKindOther, dl(Q.AhatNL), cl, rrB[l], K, TCr, true, Op{Y.p(), nullptr, ys, 0, K},
-         false, Ahat_l.p(), at_s, 2 * cl, cl, (long long)rrB[l] * 2 * cl, 1, 0);
+         false, Ahat_l.p(), at_s, 2 * cl, cl, (long long)rrB[l] * 2 * cl, 1, 0, kConjA);
     gemm(st, pp, kKindOther, dl(Q.PAS), cl, rcA[l], rrA[l],
          Op{PA_l.p(), nullptr, (long long)cl * rrA[l], 0, cl}, false,
          Op{Ad->S[l].p(), nullptr, (long long)rrA[l] * rcA[l], 0, rrA[l]}, false, PAS.p(), pas_s,
@@ -466,7 +536,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
          false, Op{Pi[l].p(), nullptr, (long long)rcA[l] * rrB[l], 0, rcA[l]}, false, Ahat_l.p(),
          at_s, 2 * cl, cl, (long long)rrB[l] * 2 * cl, 1, 0);
     gemm(st, pp, kKindOther, dl(Q.BhatNL), rcA[l], cl, K, Op{Yc.p(), nullptr, ycs, 0, rcA[l]},
-         false, TCc, false, Bhat_l.p(), bt_s, 2 * rcA[l], rcA[l], (long long)cl * 2 * rcA[l], 1, 0);
+         false, TCc, false, Bhat_l.p(), bt_s, 2 * rcA[l], rcA[l], (long long)cl * 2 * rcA[l], 1, 0, kConjB);
     gemm(st, pp, kKindOther, dl(Q.SBP), rrB[l], cl, rcB[l],
          Op{Bd->S[l].p(), nullptr, (long long)rrB[l] * rcB[l], 0, rrB[l]}, false,
          Op{PB_l.p(), nullptr, (long long)rcB[l] * cl, 0, rcB[l]}, false, SBP.p(), sbp_s, rrB[l],
@@ -476,24 +546,24 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
          Op{SBP.p(), nullptr, sbp_s, 0, rrB[l]}, false, Bhat_l.p(), bt_s, 2 * rcA[l], rcA[l],
          (long long)cl * 2 * rcA[l], 1, 0);
     // targets of this level
-    C->S[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * eb, bulk);
+    C->S[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * eb, bulk, cplx);
     zero(st, C->S[l].p(), (long long)std::max(1, nn) * cl * cl);
-    SNL[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * eb, bulk);
+    SNL[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * eb, bulk, cplx);
     zero(st, SNL[l].p(), (long long)std::max(1, nn) * cl * cl);
     const int nbt = std::max(1, Q.n_blue_tiles);
-    Buf Acc_l(ctx, (size_t)nbt * 4 * cl * cl * eb, bulk);
+    Buf Acc_l(ctx, (size_t)nbt * 4 * cl * cl * eb, bulk, cplx);
     zero(st, Acc_l.p(), (long long)nbt * 4 * cl * cl);
     const long long cs = (long long)cl * cl, acs = 4LL * cl * cl;
     // case 1: T^C_I^T M_IK T^C_K (nonleafcoup_simple, first case)
     {
-      Buf X1(ctx, (size_t)std::max(1, Q.n_case1) * cl * K * eb, bulk);
+      Buf X1(ctx, (size_t)std::max(1, Q.n_case1) * cl * K * eb, bulk, cplx);
       gemm(st, pp, kKindOther, dl(Q.c1X), cl, K, K, TCr, true, AccT, false, X1.p(),
-           (long long)cl * K, cl, 0, 0, 1, 0);
+           (long long)cl * K, cl, 0, 0, 1, 0, kConjA);
       const Op X1o{X1.p(), nullptr, (long long)cl * K, 0, cl};
       gemm(st, pp, kKindTriple, dl(Q.c1_R), cl, cl, K, X1o, false, TCc, false, C->S[l].p(), cs, cl,
-           0, 0, 1, 1);
+           0, 0, 1, 1, kConjB);
       gemm(st, pp, kKindTriple, dl(Q.c1_B), cl, cl, K, X1o, false, TCc, false, Acc_l.p(), acs,
-           2 * cl, cl, (long long)cl * 2 * cl, 1, 1);
+           2 * cl, cl, (long long)cl * 2 * cl, 1, 1, kConjB);
     }
     // cases 2-4 (nonleafcoup_simple), re-associated: for an admissible B
     // factor sum_J Ahat_IJ (S^B_JK P^B_K) = (sum_J Ahat_IJ S^B_JK) P^B_K, and
@@ -518,12 +588,12 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     auto stage1 = [&](const TaskList& wnl, const TaskList& wr, Buf& Wn, Buf& Wr) {
       const DevList &dn = dl(wnl), &dr = dl(wr);
       if (dn.nout) {
-        Wn = Buf(ctx, (size_t)dn.nout * wns * eb, bulk);
+        Wn = Buf(ctx, (size_t)dn.nout * wns * eb, bulk, cplx);
         gemm(st, pp, kKindTriple, dn, cl, rcB[l], rrB[l], AhatT, false, SBo, false, Wn.p(), wns,
              cl, 0, 0, 1, 0);
       }
       if (dr.nout) {
-        Wr = Buf(ctx, (size_t)dr.nout * wrs * eb, bulk);
+        Wr = Buf(ctx, (size_t)dr.nout * wrs * eb, bulk, cplx);
         gemm(st, pp, kKindTriple, dr, rrA[l], cl, rcA[l], SAo, false, BhatT, false, Wr.p(), wrs,
              rrA[l], 0, 0, 1, 0);
       }
@@ -576,7 +646,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     const int nn = s.lev[l].size();
     if (SP.X.nout() == 0) continue;
     const long long xs = (long long)K * cl;
-    Buf XS(ctx, (size_t)nn * xs * eb, bulk);
+    Buf XS(ctx, (size_t)nn * xs * eb, bulk, cplx);
     gemm(st, pp, kKindOther, dl(SP.X), K, cl, cl, Op{Ur[l].p(), nullptr, (long long)K * K, 0, K},
          false, Op{SNL[l].p(), nullptr, (long long)cl * cl, 0, cl}, false, XS.p(), xs, K, 0, 0, 1, 0);
     const Op XSo{XS.p(), nullptr, xs, 0, K, cc, 0};
@@ -587,8 +657,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       gemm(st, pp, kKindOther, dl(SP.toNL), cc, cc, cl, XSo, false, TCc, true, SNL[ch].p(),
            (long long)cc * cc, cc, 0, 0, 1, 1);
     if (ch == L && SP.toF.nout() > 0) {
-      Buf YF(ctx, (size_t)nnL * cc * cc * eb, bulk);
-      Buf ZF(ctx, (size_t)nnL * np * cc * eb, bulk);
+      Buf YF(ctx, (size_t)nnL * cc * cc * eb, bulk, cplx);
+      Buf ZF(ctx, (size_t)nnL * np * cc * eb, bulk, cplx);
       gemm(st, pp, kKindOther, dl(SP.toF), cc, cc, cl, XSo, false, TCc, true, YF.p(),
            (long long)cc * cc, cc, 0, 0, 1, 0);
       gemm(st, pp, kKindOther, dl(SP.F1), np, cc, cc, Op{Ur[L].p(), nullptr, nn2, 0, np}, false,
@@ -628,6 +698,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     C->rr[l] = cpad[l];
     C->rc[l] = cpad[l];
   }
+  C->cplx = cplx;
   C->V = std::move(Ur[L]);
   C->W = std::move(Uc[L]);
   C->V_stride = nn2;
