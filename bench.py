@@ -106,6 +106,46 @@ def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192):
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_service_ms": float(np.mean(svc)),
             "unknowns_per_s": float(sum(n for _, n in tickets) / wall)}
+def sphere_leg(n, steps, eps=1e-3):
+    """Scattering-shaped complex128 product C = A B on a Fibonacci sphere:
+    exp(-j kappa r)/(4 pi r) with kappa such that the point spacing
+    sqrt(4 pi / N) is a tenth of a wavelength, B at kappa / 2, leaf 64, eta 1,
+    Chebyshev 3x3x3 bases, self-term 1/(2 pi rho) - j kappa/(4 pi) with
+    rho = 2/sqrt(N); both matrices built on the device (h2_build).  Timed
+    products after one warm-up; eps_rel by the exact H^2 mat-vec."""
+    import math
+    import numpy as np
+    import paper_1908_05218_amd as h2
+    from h2inputs import points
+    ctx = h2.Context(0)
+    kappa = 2 * math.pi / (10 * math.sqrt(4 * math.pi / n))
+    rho = 2.0 / math.sqrt(n)
+    pts = points.fibonacci_sphere(n)
+    A = h2.build(ctx, pts, 64, 1.0, 3, 1 / (2 * math.pi * rho) - 1j * kappa / (4 * math.pi),
+                 kernel="helmholtz", wavenumber=kappa)
+    B = h2.build(ctx, pts, 64, 1.0, 3, 1 / (2 * math.pi * rho) - 1j * kappa / (8 * math.pi),
+                 kernel="helmholtz", wavenumber=kappa / 2, share_tree_with=A)
+    h2.mmp(ctx, A, B, eps).free()
+    walls = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        C = h2.mmp(ctx, A, B, eps)
+        walls.append(time.perf_counter() - t0)
+        st = h2.stats(C)
+        if len(walls) < steps:
+            C.free()
+    x = np.random.default_rng(1).standard_normal(n) + 1j * np.random.default_rng(2).standard_normal(n)
+    ref = h2.matvec(ctx, A, h2.matvec(ctx, B, x))
+    erel = float(np.linalg.norm(h2.matvec(ctx, C, x) - ref) / np.linalg.norm(ref))
+    ctx.close()
+    ms = 1e3 * float(np.mean(walls))
+    return {"workload": f"sphere{n // 1024}k", "N": n, "dtype": "complex128", "kappa": kappa,
+            "leaf_size": 64, "basis": "chebyshev 3x3x3 (rank 27)", "eps": eps, "product": "A*B",
+            "ms_per_step": ms, "unknowns_per_s": n / (ms * 1e-3),
+            "gflops": st["flops"] / (ms * 1e-3) / 1e9, "eps_rel": erel,
+            "rank_max": st["rank_max_r"], "peak_bytes": st["bytes_device"]}
+
+
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plates64k_fp32bulk_hbm_by_class.md")
 
 
@@ -215,6 +255,8 @@ def main():
                     help="concurrent requests of the serving loop")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the served-latency stream (0: skip)")
+    ap.add_argument("--sphere-n", type=int, default=16384,
+                    help="points of the complex Helmholtz sphere product (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device copies (scale of the HBM byte counters)")
     args = ap.parse_args()
@@ -282,6 +324,8 @@ def main():
                     "device_ms_per_step": other["device_ms"], "eps_rel": other["eps_rel"],
                     "speedup_of_headline": other["ms"] / ms,
                     "breakdown": other["breakdown"], "roofline": other["roofline"]}
+    if args.sphere_n > 0:
+        out["sphere_complex"] = sphere_leg(args.sphere_n, args.steps)
     if args.serve_requests > 0:
         out["serving"] = {p: serve_stream(args.serve_requests, p, slots=args.serve_slots)
                           for p in ("fp32_bulk", "fp64")}

@@ -100,12 +100,17 @@ typedef struct {
  * H2_ERR_UNSUPPORTED (complex), H2_ERR_OOM. */
 h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out);
 
-/* Kernel of h2_build: H2_KERNEL_LAPLACE is 1/(4 pi r), with self_value where
- * r = 0 (coincident points; e.g. the mean of 1/(4 pi r) over a panel). */
-typedef enum { H2_KERNEL_LAPLACE = 0 } h2_kernel_kind;
+/* Kernel of h2_build: H2_KERNEL_LAPLACE is 1/(4 pi r) (real), with
+ * self_value where r = 0 (coincident points; e.g. the mean of 1/(4 pi r) over
+ * a panel).  H2_KERNEL_HELMHOLTZ is exp(-j kappa r)/(4 pi r) with kappa =
+ * wavenumber (complex128 matrix; the scattering kernel of Section V), with
+ * self_value + j self_value_imag where r = 0. */
+typedef enum { H2_KERNEL_LAPLACE = 0, H2_KERNEL_HELMHOLTZ = 1 } h2_kernel_kind;
 typedef struct {
   int32_t kind;
   double self_value;
+  double wavenumber;      /* Helmholtz only */
+  double self_value_imag; /* Helmholtz only */
 } h2_kernel;
 
 /* Construction options of h2_build.  leaf_size: leaves hold at most this many

@@ -63,14 +63,15 @@ class _Stats(C.Structure):
 
 
 class _Kernel(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("self_value", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("self_value", C.c_double), ("wavenumber", C.c_double),
+                ("self_value_imag", C.c_double)]
 
 
 class _BuildOpts(C.Structure):
     _fields_ = [("leaf_size", C.c_int64), ("eta", C.c_double), ("cheb_order", C.c_int32)]
 
 
-KERNELS = {"laplace": 0}
+KERNELS = {"laplace": 0, "helmholtz": 1}
 
 
 class _Request(C.Structure):
@@ -232,14 +233,17 @@ def load(ctx, flat):
     return Matrix(ctx, h)
 
 
-def build(ctx, points, leaf_size, eta, order, self_value, kernel="laplace", share_tree_with=None):
+def build(ctx, points, leaf_size, eta, order, self_value, kernel="laplace", share_tree_with=None,
+          wavenumber=0.0):
     """h2_build: the H^2 matrix of the kernel over `points` (n x 3), built by
     the library (tree and bases on the host, couplings and dense blocks on
-    the device)."""
+    the device).  kernel "helmholtz": exp(-j wavenumber r)/(4 pi r), complex
+    self_value."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     if pts.ndim != 2 or pts.shape[1] != 3:
         raise ValueError("points must be n x 3")
-    k = _Kernel(KERNELS[kernel], float(self_value))
+    sv = complex(self_value)
+    k = _Kernel(KERNELS[kernel], sv.real, float(wavenumber), sv.imag)
     o = _BuildOpts(int(leaf_size), float(eta), int(order))
     h = C.c_void_p()
     _check(lib().h2_build(ctx.h, _ptr(pts), pts.shape[0], C.byref(k), C.byref(o),
@@ -272,7 +276,7 @@ def submit(ctx, points, leaf_size, eta, order, self_value, eps, mode="accuracy",
     pts = np.ascontiguousarray(points, dtype=np.float64)
     if pts.ndim != 2 or pts.shape[1] != 3:
         raise ValueError("points must be n x 3")
-    r = _Request(pts.ctypes.data, pts.shape[0], _Kernel(0, float(self_value)),
+    r = _Request(pts.ctypes.data, pts.shape[0], _Kernel(0, float(self_value), 0.0, 0.0),
                  _BuildOpts(int(leaf_size), float(eta), int(order)), float(eps), TRUNC[mode],
                  PREC[precision])
     t = C.c_uint64()

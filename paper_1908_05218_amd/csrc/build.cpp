@@ -185,8 +185,12 @@ h2_status build_impl(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* 
   if (n < 1 || opts->leaf_size < 1 || !(opts->eta > 0.0) || opts->cheb_order < 1 ||
       opts->cheb_order > 6)
     return set_error(H2_ERR_ARG, "need n >= 1, leaf_size >= 1, eta > 0, 1 <= cheb_order <= 6");
-  if (kernel->kind != H2_KERNEL_LAPLACE) return set_error(H2_ERR_UNSUPPORTED, "unsupported kernel");
-  if (!std::isfinite(kernel->self_value)) return set_error(H2_ERR_ARG, "non-finite self value");
+  if (kernel->kind != H2_KERNEL_LAPLACE && kernel->kind != H2_KERNEL_HELMHOLTZ)
+    return set_error(H2_ERR_UNSUPPORTED, "unsupported kernel");
+  const bool helm = kernel->kind == H2_KERNEL_HELMHOLTZ;
+  if (!std::isfinite(kernel->self_value) ||
+      (helm && (!std::isfinite(kernel->self_value_imag) || !std::isfinite(kernel->wavenumber))))
+    return set_error(H2_ERR_ARG, "non-finite self value or wavenumber");
   for (int64_t i = 0; i < 3 * n; ++i)
     if (!std::isfinite(xyz[i])) return set_error(H2_ERR_ARG, "non-finite coordinate");
   if (share && share->st().n != n) return set_error(H2_ERR_ARG, "share_tree_with has another size");
@@ -235,10 +239,20 @@ h2_status build_impl(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* 
     }
   const int64_t ncl = (2LL << L) - 1;
   std::vector<int64_t> k(ncl, p3);
+  if (helm) {
+    // complex matrix with real bases: interleave zero imaginary parts
+    auto widen = [](std::vector<double>& v) {
+      std::vector<double> w(2 * v.size(), 0.0);
+      for (size_t i = 0; i < v.size(); ++i) w[2 * i] = v[i];
+      v.swap(w);
+    };
+    widen(V);
+    widen(E);
+  }
   h2_host_matrix hm{};
   hm.n = n;
   hm.L = L;
-  hm.is_complex = 0;
+  hm.is_complex = helm ? 1 : 0;
   hm.leaf_off = t.leaf_off.data();
   hm.perm = t.perm.data();
   hm.node_off = bl.node_off.data();
@@ -305,6 +319,10 @@ h2_status build_impl(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* 
       ca.rc = M->rc[l];
       ca.self_value = kernel->self_value;
       ca.S = M->S[l].d();
+      ca.helmholtz = helm ? 1 : 0;
+      ca.kappa = helm ? kernel->wavenumber : 0.0;
+      ca.self_imag = helm ? kernel->self_value_imag : 0.0;
+      ca.plane = ctx->plane(M->S[l].p());
       H2_HIP(h2k::launch_build_coupling(ca, strm));
       if (l == L) {
         h2k::BuildDenseArgs fa{};
@@ -317,6 +335,10 @@ h2_status build_impl(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* 
         fa.npad = s.npad;
         fa.self_value = kernel->self_value;
         fa.F = M->F.d();
+        fa.helmholtz = ca.helmholtz;
+        fa.kappa = ca.kappa;
+        fa.self_imag = ca.self_imag;
+        fa.plane = ctx->plane(M->F.p());
         H2_HIP(h2k::launch_build_dense(fa, strm));
       }
       // the staging buffers return to the pool only after the launches ran

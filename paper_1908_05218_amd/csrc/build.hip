@@ -18,6 +18,22 @@ __device__ __forceinline__ double laplace(double x0, double x1, double x2, doubl
   return r == 0.0 ? self_value : 1.0 / (4.0 * M_PI * r);
 }
 
+// exp(-j kappa r)/(4 pi r) = (cos(kappa r) - j sin(kappa r))/(4 pi r)
+__device__ __forceinline__ void helmholtz(double x0, double x1, double x2, double y0, double y1,
+                                          double y2, double kappa, double self_re, double self_im,
+                                          double& re, double& im) {
+  const double d0 = x0 - y0, d1 = x1 - y1, d2 = x2 - y2;
+  const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  if (r == 0.0) {
+    re = self_re;
+    im = self_im;
+    return;
+  }
+  const double kr = kappa * r, den = 4.0 * M_PI * r;
+  re = cos(kr) / den;
+  im = -sin(kr) / den;
+}
+
 __global__ void k_build_coupling(BuildCouplingArgs a) {
   const int p = a.p, p3 = p * p * p;
   const long long per = (long long)p3 * p3;
@@ -29,9 +45,17 @@ __global__ void k_build_coupling(BuildCouplingArgs a) {
   const int i = ij % p3, j = ij / p3;
   const double* at = a.axes + (long long)a.rows[q] * 3 * p;
   const double* as = a.axes + (long long)a.cols[q] * 3 * p;
-  const double v = laplace(at[i / (p * p)], at[p + (i / p) % p], at[2 * p + i % p],
-                           as[j / (p * p)], as[p + (j / p) % p], as[2 * p + j % p], a.self_value);
-  a.S[(long long)q * a.rr * a.rc + i + (long long)j * a.rr] = v;
+  const long long o = (long long)q * a.rr * a.rc + i + (long long)j * a.rr;
+  if (a.helmholtz) {
+    double re, im;
+    helmholtz(at[i / (p * p)], at[p + (i / p) % p], at[2 * p + i % p], as[j / (p * p)],
+              as[p + (j / p) % p], as[2 * p + j % p], a.kappa, a.self_value, a.self_imag, re, im);
+    a.S[o] = re;
+    a.S[a.plane + o] = im;
+    return;
+  }
+  a.S[o] = laplace(at[i / (p * p)], at[p + (i / p) % p], at[2 * p + i % p], as[j / (p * p)],
+                   as[p + (j / p) % p], as[2 * p + j % p], a.self_value);
 }
 
 __global__ void k_build_dense(BuildDenseArgs a) {
@@ -46,8 +70,15 @@ __global__ void k_build_dense(BuildDenseArgs a) {
   if (r0 + i >= a.leaf_off[a.rows[q] + 1] || c0 + j >= a.leaf_off[a.cols[q] + 1]) return;
   const double* x = a.pts + 3 * (r0 + i);
   const double* y = a.pts + 3 * (c0 + j);
-  a.F[(long long)q * per + i + (long long)j * a.npad] =
-      laplace(x[0], x[1], x[2], y[0], y[1], y[2], a.self_value);
+  const long long o = (long long)q * per + i + (long long)j * a.npad;
+  if (a.helmholtz) {
+    double re, im;
+    helmholtz(x[0], x[1], x[2], y[0], y[1], y[2], a.kappa, a.self_value, a.self_imag, re, im);
+    a.F[o] = re;
+    a.F[a.plane + o] = im;
+    return;
+  }
+  a.F[o] = laplace(x[0], x[1], x[2], y[0], y[1], y[2], a.self_value);
 }
 
 hipError_t launch_build_coupling(const BuildCouplingArgs& a, hipStream_t s) {

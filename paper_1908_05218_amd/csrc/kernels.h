@@ -140,6 +140,9 @@ struct BuildCouplingArgs {
   int nnodes, p, rr, rc;
   double self_value;
   double* S;
+  int helmholtz;      // exp(-j kappa r)/(4 pi r) into two planes, else 1/(4 pi r)
+  double kappa, self_imag;
+  long long plane;    // imaginary-plane offset of S (Helmholtz)
 };
 struct BuildDenseArgs {
   const double* pts;
@@ -148,6 +151,9 @@ struct BuildDenseArgs {
   int nnodes, npad;
   double self_value;
   double* F;
+  int helmholtz;
+  double kappa, self_imag;
+  long long plane;    // imaginary-plane offset of F (Helmholtz)
 };
 hipError_t launch_build_coupling(const BuildCouplingArgs& a, hipStream_t s);
 hipError_t launch_build_dense(const BuildDenseArgs& a, hipStream_t s);

@@ -110,3 +110,27 @@ def test_complex_errors(ctx):
     with pytest.raises(h2.H2Error) as e:
         h2.mmp(ctx, dA, dR, 1e-4)
     assert e.value.code == 1
+
+
+def test_helmholtz_build_matches_input_builder(ctx):
+    """h2_build with the Helmholtz kernel = the Python input builder (same
+    tree, partition, Chebyshev bases; couplings and dense blocks to
+    rounding), and its products agree with the checker's."""
+    from h2inputs import points
+    print("case helmholtz build sphere1k", flush=True)
+    n, kappa = 1024, 20.0
+    A, _ = cases.helmholtz_sphere(n, 32, 2, kappa)
+    rho = 2.0 / np.sqrt(n)
+    sv = 1 / (2 * np.pi * rho) - 1j * kappa / (4 * np.pi)
+    M = h2.build(ctx, points.fibonacci_sphere(n), 32, 1.0, 2, sv, kernel="helmholtz",
+                 wavenumber=kappa)
+    d, f = h2.export(M), A.to_flat()
+    for k in ("leaf_off", "perm", "node_off", "node_row", "node_col", "node_type", "krow", "kcol"):
+        assert np.array_equal(np.asarray(d[k]), np.asarray(f[k])), k
+    for k in ("V", "W", "Er", "Ec", "S", "F"):
+        a, b = np.asarray(d[k]), np.asarray(f[k], dtype=np.complex128)
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max(), k
+    dA = h2.load(ctx, f)
+    C1 = h2.to_dense(ctx, h2.mmp(ctx, M, M, 1e-4), n)
+    C2 = h2.to_dense(ctx, h2.mmp(ctx, dA, dA, 1e-4), n)
+    assert rel(C1, C2) < 1e-10
