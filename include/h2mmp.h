@@ -16,8 +16,10 @@
  *    (thread-local, valid until the next call on the same thread).
  *  - Host pointers are read during the call only; the library copies what it
  *    keeps.  Device pointers are arguments only where a name says "_dev".
- *  - Matrices are column-major.  Real FP64 only in this version
- *    (is_complex != 0 is rejected with H2_ERR_UNSUPPORTED).
+ *  - Matrices are column-major, real FP64 or complex128.  Complex data at
+ *    the boundary: interleaved (real, imaginary) pairs in h2_load, h2_export
+ *    and h2_to_dense; planar vectors (all real parts, then all imaginary
+ *    parts) in h2_matvec.
  *  - All work runs on the context's own HIP stream (default priority); every
  *    entry point returns after that stream has finished its work.
  */
@@ -95,9 +97,11 @@ typedef struct {
   const int64_t *V_off, *W_off, *Er_off, *Ec_off, *S_off, *F_off;
 } h2_host_matrix;
 
-/* Upload an H^2 matrix to the device (padded per-level layout, FP64).
- * Errors: H2_ERR_ARG (inconsistent offsets, sizes or types),
- * H2_ERR_UNSUPPORTED (complex), H2_ERR_OOM. */
+/* Upload an H^2 matrix to the device (padded per-level layout, FP64; with
+ * is_complex != 0 the arrays V ... F hold interleaved complex pairs, counts
+ * and offsets in complex elements).  Errors: H2_ERR_ARG (inconsistent
+ * offsets, sizes or types), H2_ERR_NUMERIC (non-finite dense entry),
+ * H2_ERR_OOM. */
 h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out);
 
 /* Kernel of h2_build: H2_KERNEL_LAPLACE is 1/(4 pi r) (real), with
@@ -204,7 +208,10 @@ h2_status h2_release(h2_ctx ctx, uint64_t ticket);
 
 /* C = A B (Sections III and IV).  A and B must have been loaded with the
  * same tree (leaf_off, perm) and block partition; C shares them (the
- * product keeps A's partition).  eps >= 0; eps == 0 selects EXACT.
+ * product keeps A's partition).  eps >= 0; eps == 0 selects EXACT.  A and
+ * B both real or both complex (complex: FP64 only; Gram dimension <= 256,
+ * half the real limit, since the Hermitian Grams are solved through their
+ * real embedding).
  * Errors: H2_ERR_STRUCTURE, H2_ERR_ARG (eps < 0, bad mode/precision),
  * H2_ERR_UNSUPPORTED (a cluster whose Gram dimension exceeds the on-chip
  * eigensolver limit, reported in the message), H2_ERR_OOM, H2_ERR_NUMERIC. */
@@ -213,14 +220,17 @@ h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int
 
 /* y = M x for nrhs right-hand sides, x and y n x nrhs column-major in the
  * original point order, host memory (x_on_device = 0) or device memory
- * (x_on_device = 1, both pointers device).  Exact H^2 mat-vec: forward
+ * (x_on_device = 1, both pointers device); complex M: x and y hold the
+ * n x nrhs real parts followed by the n x nrhs imaginary parts (2 n nrhs
+ * doubles).  Exact H^2 mat-vec: forward
  * transform up the column tree, couplings, backward transform down the row
  * tree, dense near field (the reference solution of equation `error`). */
 h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nrhs,
                     int x_on_device);
 
-/* Dense M (original order) into host memory `out` (column-major, ld >= n).
- * Only for n <= 16384 (H2_ERR_UNSUPPORTED above). */
+/* Dense M (original order) into host memory `out` (column-major, ld >= n;
+ * complex M: interleaved pairs, ld in complex elements).  Only for
+ * n <= 16384 (H2_ERR_UNSUPPORTED above). */
 h2_status h2_to_dense(h2_ctx ctx, h2_mat M, double* out, int64_t ld);
 
 /* Sizes of M in the flat layout, for h2_export. */
