@@ -129,10 +129,28 @@ static void launch_gemm(hipStream_t s, Profiler* prof, int kind, const DevList& 
   a.alpha = (T)alpha;
   a.beta = (T)beta;
   a.triple = kind == kKindTriple;
+  const std::string key = tile_key((int)sizeof(T), a.A.f32, a.B.f32, a.triple, tA, tB, m, n, k,
+                                   tl.nout, (long long)tl.ntask);
+  a.tile = tile_for(key);
   hipEvent_t ev = nullptr;
   const double fl = 2.0 * m * n * (double)k * tl.ntask;
   if (prof) prof->begin(kind, fl, &ev);
-  H2_HIP(h2k::launch_bgemm<T>(a, s));
+  if (tile_logging()) {
+    hipEvent_t t0, t1;
+    H2_HIP(hipEventCreate(&t0));
+    H2_HIP(hipEventCreate(&t1));
+    H2_HIP(hipEventRecord(t0, s));
+    H2_HIP(h2k::launch_bgemm<T>(a, s));
+    H2_HIP(hipEventRecord(t1, s));
+    H2_HIP(hipEventSynchronize(t1));
+    float ms = 0;
+    hipEventElapsedTime(&ms, t0, t1);
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    tile_log(key, a.tile, ms);
+  } else {
+    H2_HIP(h2k::launch_bgemm<T>(a, s));
+  }
   if (prof) prof->end(ev, kind, fl);
 }
 

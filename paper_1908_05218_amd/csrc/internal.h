@@ -248,6 +248,12 @@ struct BulkScope {
 };
 
 h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C);
+// measured tile choices of the batched GEMM (tiles.txt), tuning hooks
+std::string tile_key(int tsize, int af32, int bf32, int triple, int tA, int tB, int m, int n, int k,
+                     int nout, long long ntask);
+int tile_for(const std::string& key);  // -1: shape heuristic
+bool tile_logging();
+void tile_log(const std::string& key, int tile, float ms);
 // the context whose pool holds M: ctx itself or one of ctx's serving slots
 // (nullptr when M belongs to neither)
 inline h2_ctx home_of(h2_ctx ctx, const h2_mat_s* M) {

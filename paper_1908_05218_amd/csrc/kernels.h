@@ -35,6 +35,13 @@ struct BgemmArgs {
   const int* b_idx;    // [ntask]
   T alpha, beta;
   int triple;  // launch under the block-product symbol (k_bgemm_triple)
+  int tile;    // workgroup tile (kTile* id), -1: chosen from the output shape
+};
+
+// Workgroup tiles of the batched GEMM (rows x columns of C per workgroup)
+enum {
+  kTile32x32 = 0, kTile96x32 = 1, kTile32x96 = 2, kTile96x96 = 3,
+  kTile32x64 = 4, kTile64x32 = 5, kTile64x64 = 6, kTileCount = 7
 };
 
 template <typename T>

@@ -337,6 +337,16 @@ template <typename T>
 hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s) {
   if (a.nout <= 0) return hipSuccess;
   if (a.c_f32 != (sizeof(T) == sizeof(float))) return hipErrorInvalidValue;  // C has type T
+  switch (a.tile) {  // a measured choice (every tile masks partial edges)
+    case kTile32x32: return launch_tile<T, 32, 32>(a, s);
+    case kTile96x32: return launch_tile<T, 96, 32>(a, s);
+    case kTile32x96: return launch_tile<T, 32, 96>(a, s);
+    case kTile96x96: return launch_tile<T, 96, 96>(a, s);
+    case kTile32x64: return launch_tile<T, 32, 64>(a, s);
+    case kTile64x32: return launch_tile<T, 64, 32>(a, s);
+    case kTile64x64: return launch_tile<T, 64, 64>(a, s);
+    default: break;
+  }
   const int mx = a.m > a.n ? a.m : a.n;
   if (a.m <= 32 && a.n <= 32) return launch_tile<T, 32, 32>(a, s);
   if (a.m > 64 && a.m <= 96 && a.n <= 32) return launch_tile<T, 96, 32>(a, s);
