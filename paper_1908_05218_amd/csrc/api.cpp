@@ -106,7 +106,7 @@ template <typename T>
 static void launch_gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int n,
                         int k, const Op& A, bool tA, const Op& B, bool tB, void* C,
                         long long cstride, int ldc, long long csub_r, long long csub_c,
-                        double alpha, double beta) {
+                        double alpha, double beta, bool lower = false) {
   h2k::BgemmArgs<T> a{};
   a.m = m;
   a.n = n;
@@ -129,11 +129,13 @@ static void launch_gemm(hipStream_t s, Profiler* prof, int kind, const DevList& 
   a.alpha = (T)alpha;
   a.beta = (T)beta;
   a.triple = kind == kKindTriple;
+  a.lower = lower ? 1 : 0;
   const std::string key = tile_key((int)sizeof(T), a.A.f32, a.B.f32, a.triple, tA, tB, m, n, k,
                                    tl.nout, (long long)tl.ntask);
   a.tile = tile_for(key);
   hipEvent_t ev = nullptr;
-  const double fl = 2.0 * m * n * (double)k * tl.ntask;
+  // a symmetric output computed on and below its diagonal: n (n + 1) / 2 entries
+  const double fl = 2.0 * (lower ? 0.5 * m * (n + 1.0) : (double)m * n) * k * tl.ntask;
   if (prof) prof->begin(kind, fl, &ev);
   if (tile_logging()) {
     hipEvent_t t0, t1;
@@ -204,12 +206,13 @@ void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int
     run(Ai, B, Ci, alpha * sa, 1.0);
     return;
   }
+  const bool lower = (conj & kLowerOnly) && m == n;
   if (g_bulk_f32 && kind != kKindGram)
     launch_gemm<float>(s, prof, kind, tl, m, n, k, A, tA, B, tB, C, cstride, ldc, csub_r, csub_c,
-                       alpha, beta);
+                       alpha, beta, lower);
   else
     launch_gemm<double>(s, prof, kind, tl, m, n, k, A, tA, B, tB, C, cstride, ldc, csub_r, csub_c,
-                        alpha, beta);
+                        alpha, beta, lower);
 }
 
 static void launch_segsum(hipStream_t s, const DevList& tl, int m, int n, const Op& A, void* C,

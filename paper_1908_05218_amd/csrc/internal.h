@@ -215,6 +215,9 @@ struct Profiler {
 // real products over the planes; conj bit 0 / bit 1 conjugates A / B (after
 // the transposition flags, so tA with bit 0 is A^H).
 constexpr int kConjA = 1, kConjB = 2;
+// flag: C is symmetric and only its part on and below the diagonal is read
+// (real data only; a complex product computes every tile)
+constexpr int kLowerOnly = 4;
 void gemm(hipStream_t s, Profiler* prof, int kind, const DevList& tl, int m, int n, int k,
           const Op& A, bool tA, const Op& B, bool tB, void* C, long long cstride, int ldc,
           long long csub_r, long long csub_c, double alpha, double beta, int conj = 0);

@@ -36,6 +36,9 @@ struct BgemmArgs {
   T alpha, beta;
   int triple;  // launch under the block-product symbol (k_bgemm_triple)
   int tile;    // workgroup tile (kTile* id), -1: chosen from the output shape
+  // symmetric outputs read only on and below the diagonal: compute only the
+  // tiles there (m == n and a square tile; otherwise ignored)
+  int lower;
 };
 
 // Workgroup tiles of the batched GEMM (rows x columns of C per workgroup)

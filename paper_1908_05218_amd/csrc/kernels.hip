@@ -73,11 +73,23 @@ __device__ __forceinline__ void bgemm_body(const BgemmArgs<T>& p) {
   constexpr int SN = TN / 32;
   constexpr int LA = (TM * KC) / 256;  // A elements per thread per step
   constexpr int LB = (TN * KC) / 256;
-  const int ntile = p.tiles_m * p.tiles_n;
+  const bool low = p.lower && TM == TN && p.tiles_m == p.tiles_n;
+  const int ntile = low ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
   const int o = blockIdx.x / ntile;
   const int tt = blockIdx.x - o * ntile;
-  const int tm = tt % p.tiles_m;
-  const int tn = tt / p.tiles_m;
+  int tm, tn;
+  if (low) {
+    // tt enumerates the tiles on and below the diagonal row by row:
+    // row r holds tiles r(r+1)/2 .. r(r+1)/2 + r
+    int r = (int)((sqrtf(8.0f * (float)tt + 1.0f) - 1.0f) * 0.5f);
+    while (r * (r + 1) / 2 > tt) --r;
+    while ((r + 1) * (r + 2) / 2 <= tt) ++r;
+    tm = r;
+    tn = tt - r * (r + 1) / 2;
+  } else {
+    tm = tt % p.tiles_m;
+    tn = tt / p.tiles_m;
+  }
   __shared__ T As[2][KC][TM + 1];
   __shared__ T Bs[2][KC][TN + 1];
   const int tid = threadIdx.x;
@@ -247,7 +259,10 @@ __global__ __launch_bounds__(256) void k_gram_norm(GramNormArgs p) {
   const double w2 = tr[2] > 0 ? 1.0 / tr[2] : 0.0;
   const long long base = (long long)c * p.stride;
   int bad = 0;
+  // the sums are symmetric and read on and below the diagonal only (the
+  // products may leave the part above it unwritten)
   for (int e = threadIdx.x; e < D * D; e += 256) {
+    if (e % D < e / D) continue;
     const double v = w0 * p.G[0][base + e] + w1 * p.G[1][base + e] + w2 * p.G[2][base + e];
     if (!(v == v) || v - v != 0.0) bad = 1;
     p.out[base + e] = v;
@@ -310,7 +325,10 @@ template <typename T, int TM, int TN>
 static hipError_t launch_tile(BgemmArgs<T> a, hipStream_t s) {
   a.tiles_m = cdiv(a.m, TM);
   a.tiles_n = cdiv(a.n, TN);
-  const long long grid = (long long)a.nout * a.tiles_m * a.tiles_n;
+  const bool low = a.lower && TM == TN && a.tiles_m == a.tiles_n;
+  const long long per = low ? (long long)a.tiles_m * (a.tiles_m + 1) / 2
+                            : (long long)a.tiles_m * a.tiles_n;
+  const long long grid = (long long)a.nout * per;
   const dim3 g((unsigned)grid), b(256);
 #define H2K_LAUNCH(K)                                                  \
   do {                                                                 \

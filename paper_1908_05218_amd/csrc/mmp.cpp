@@ -331,28 +331,28 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       gemm(st, pp, kKindGram, dl(LP.gB), np, np, np, FB, false, FB, true, b1.p(), nn2, np, 0, 0, 1, 0, kConjB);
       segsum(st, dl(LP.H), np, np, o1, b2.p(), nn2, np, 0, 0, 0.0);
       gemm(st, pp, kKindGram, dl(LP.X1), np, np, np, FA, false, o2, false, b3.p(), nn2, np, 0, 0, 1, 0);
-      gemm(st, pp, kKindGram, dl(LP.G1), np, np, np, o3, false, FA, true, G[0].p(), nn2, np, 0, 0, 1, 0, kConjB);
+      gemm(st, pp, kKindGram, dl(LP.G1), np, np, np, o3, false, FA, true, G[0].p(), nn2, np, 0, 0, 1, 0, kConjB | kLowerOnly);
       // column Gram, case 1 (equation case1-ch)
       gemm(st, pp, kKindGram, dl(LP.hA), np, np, np, FA, true, FA, false, b1.p(), nn2, np, 0, 0, 1, 0, kConjB);
       segsum(st, dl(LP.Hc), np, np, o1, b2.p(), nn2, np, 0, 0, 0.0);
       gemm(st, pp, kKindGram, dl(LP.X1c), np, np, np, FB, true, o2, false, b3.p(), nn2, np, 0, 0, 1, 0);
-      gemm(st, pp, kKindGram, dl(LP.G1c), np, np, np, o3, false, FB, false, Gc[0].p(), nn2, np, 0, 0, 1, 0, kConjB);
+      gemm(st, pp, kKindGram, dl(LP.G1c), np, np, np, o3, false, FB, false, Gc[0].p(), nn2, np, 0, 0, 1, 0, kConjB | kLowerOnly);
       // case 2: F^A_ij V^B_j (Gr2L) and (W^A_j^T F^B_jk)^T (case2-ch)
       Buf Z(ctx, (size_t)nnL * np * std::max(rrB[L], rcA[L]) * gb, false, cplx);
       const long long zs = (long long)np * rrB[L], zcs = (long long)np * rcA[L];
       gemm(st, pp, kKindGram, dl(LP.Z), np, rrB[L], np, FA, false,
            Op{Bd->V.p(), nullptr, B->V_stride, 0, np}, false, Z.p(), zs, np, 0, 0, 1, 0);
       gemm(st, pp, kKindGram, dl(LP.G2), np, np, rrB[L], Op{Z.p(), nullptr, zs, 0, np}, false,
-           Op{Z.p(), nullptr, zs, 0, np}, true, G[1].p(), nn2, np, 0, 0, 1, 0, kConjB);
+           Op{Z.p(), nullptr, zs, 0, np}, true, G[1].p(), nn2, np, 0, 0, 1, 0, kConjB | kLowerOnly);
       gemm(st, pp, kKindGram, dl(LP.Zc), np, rcA[L], np, FB, true,
            Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, false, Z.p(), zcs, np, 0, 0, 1, 0);
       gemm(st, pp, kKindGram, dl(LP.G2c), np, np, rcA[L], Op{Z.p(), nullptr, zcs, 0, np}, false,
-           Op{Z.p(), nullptr, zcs, 0, np}, true, Gc[1].p(), nn2, np, 0, 0, 1, 0, kConjB);
+           Op{Z.p(), nullptr, zcs, 0, np}, true, Gc[1].p(), nn2, np, 0, 0, 1, 0, kConjB | kLowerOnly);
       // case 3/4: the old bases V^A_i V^A_i^T (Gr3L) and W^B_k W^B_k^T (case3-ch)
       gemm(st, pp, kKindGram, dl(LP.G3), np, np, rrA[L], Op{Ad->V.p(), nullptr, A->V_stride, 0, np},
-           false, Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, true, G[2].p(), nn2, np, 0, 0, 1, 0, kConjB);
+           false, Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, true, G[2].p(), nn2, np, 0, 0, 1, 0, kConjB | kLowerOnly);
       gemm(st, pp, kKindGram, dl(LP.G3c), np, np, rcB[L], Op{Bd->W.p(), nullptr, B->W_stride, 0, np},
-           false, Op{Bd->W.p(), nullptr, B->W_stride, 0, np}, true, Gc[2].p(), nn2, np, 0, 0, 1, 0, kConjB);
+           false, Op{Bd->W.p(), nullptr, B->W_stride, 0, np}, true, Gc[2].p(), nn2, np, 0, 0, 1, 0, kConjB | kLowerOnly);
     }
     eig_level(L, np, G, Gc, Ur_L, Uc_L, rank_r[L], rank_c[L], leaf_sizes.as<int>(), nullptr,
               leaf_sizes.as<int>(), nullptr, 1, np);
@@ -464,8 +464,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       Gc[k] = Buf(ctx, (size_t)ncl * K2 * gb, false, cplx);
     }
     // case 1: merged children couplings M_IK (nonleafA; case1-ch-nl)
-    gemm(st, pp, kKindGram, dl(Q.G1), K, K, K, AccT, false, AccT, true, G[0].p(), K2, K, 0, 0, 1, 0, kConjB);
-    gemm(st, pp, kKindGram, dl(Q.G1c), K, K, K, AccT, true, AccT, false, Gc[0].p(), K2, K, 0, 0, 1, 0, kConjB);
+    gemm(st, pp, kKindGram, dl(Q.G1), K, K, K, AccT, false, AccT, true, G[0].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
+    gemm(st, pp, kKindGram, dl(Q.G1c), K, K, K, AccT, true, AccT, false, Gc[0].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
     // case 2: (NL^A)_coll T^B_J (case2-ch-nl) and its column mirror
     const long long ys = (long long)K * rrB[l], ycs = (long long)rcA[l] * K;
     Buf Y(ctx, (size_t)std::max(1, nn) * ys * gb, false, cplx);
@@ -474,13 +474,13 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
          Op{Ahat_ch.p(), nullptr, 4LL * cc * rrB[ch], 0, K}, false,
          Op{Bd->Tr[l].p(), nullptr, B->Tr_stride[l], 0, 2 * rrB[ch]}, false, Y.p(), ys, K, 0, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.G2), K, K, rrB[l], Op{Y.p(), nullptr, ys, 0, K}, false,
-         Op{Y.p(), nullptr, ys, 0, K}, true, G[1].p(), K2, K, 0, 0, 1, 0, kConjB);
+         Op{Y.p(), nullptr, ys, 0, K}, true, G[1].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
     gemm(st, pp, kKindGram, dl(Q.Yc), rcA[l], K, 2 * rcA[ch],
          Op{Ad->Tc[l].p(), nullptr, A->Tc_stride[l], 0, 2 * rcA[ch]}, true,
          Op{Bhat_ch.p(), nullptr, 4LL * rcA[ch] * cc, 0, 2 * rcA[ch]}, false, Yc.p(), ycs, rcA[l],
          0, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.G2c), K, K, rcA[l], Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, true,
-         Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, false, Gc[1].p(), K2, K, 0, 0, 1, 0, kConjB);
+         Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, false, Gc[1].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
     // cases 3/4: old bases projected on the children's new bases (case3-ch-nl)
     const long long ds = (long long)K * rrA[l], qs = (long long)K * rcB[l];
     Buf Dm(ctx, (size_t)ncl * ds * gb, false, cplx), Qm(ctx, (size_t)ncl * qs * gb, false, cplx);
@@ -489,13 +489,13 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
          Op{Ad->Tr[l].p(), nullptr, A->Tr_stride[l], 0, 2 * rrA[ch], rrA[ch], 0}, false, Dm.p(), ds,
          K, cc, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.G3), K, K, rrA[l], Op{Dm.p(), nullptr, ds, 0, K}, false,
-         Op{Dm.p(), nullptr, ds, 0, K}, true, G[2].p(), K2, K, 0, 0, 1, 0, kConjB);
+         Op{Dm.p(), nullptr, ds, 0, K}, true, G[2].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
     gemm(st, pp, kKindGram, dl(Q.Q), cc, rcB[l], rcB[ch],
          Op{PB_ch.p(), nullptr, (long long)rcB[ch] * cc, 0, rcB[ch]}, true,
          Op{Bd->Tc[l].p(), nullptr, B->Tc_stride[l], 0, 2 * rcB[ch], rcB[ch], 0}, false, Qm.p(), qs,
          K, cc, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.G3c), K, K, rcB[l], Op{Qm.p(), nullptr, qs, 0, K}, false,
-         Op{Qm.p(), nullptr, qs, 0, K}, true, Gc[2].p(), K2, K, 0, 0, 1, 0, kConjB);
+         Op{Qm.p(), nullptr, qs, 0, K}, true, Gc[2].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
     // new transfer matrices
     eig_level(l, K, G, Gc, Ur[l], Uc[l], rank_r[l], rank_c[l], rank_r[ch].as<int>(),
               rank_r[ch].as<int>() + 1, rank_c[ch].as<int>(), rank_c[ch].as<int>() + 1, 2, cc);
