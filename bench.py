@@ -34,7 +34,7 @@ def cpu_baseline():
     w = configs.plates_n(8192)
     A = w.build()
     t0 = time.perf_counter()
-    mmp.h2_mmp(A, A, 1e-4)
+    Co, _ = mmp.h2_mmp(A, A, 1e-4)
     t = time.perf_counter() - t0
     cores = len(os.sched_getaffinity(0))
     try:
@@ -43,9 +43,24 @@ def cpu_baseline():
         cores = max([i.get("num_threads", 1) for i in info] + [1])
     except Exception:
         pass
+    # the GPU products of the same matrix against the checker's C (FP64):
+    # ||(C_gpu - C_checker) x|| / ||C_checker x|| over random x
+    import paper_1908_05218_amd as h2
+    from oracle import h2ops
+    ctx = h2.Context(0)
+    dA = h2.load(ctx, A.to_flat())
+    X = np.random.default_rng(17).standard_normal((A.n, 4))
+    ref = h2ops.matvec(Co, X)
+    vs = {}
+    for prec in ("fp32_bulk", "fp64"):
+        C = h2.mmp(ctx, dA, dA, 1e-4, precision=prec)
+        vs[prec] = float(np.linalg.norm(h2.matvec(ctx, C, X) - ref) / np.linalg.norm(ref))
+        C.free()
+    ctx.close()
     return {"value": A.n / t, "unit": "unknowns/s", "cores": int(cores), "kind": "oracle",
             "sample": f"plates family N={A.n} (random points on both plates), eps=1e-4, "
-                      f"full checker product in {t:.1f} s"}
+                      f"full checker product in {t:.1f} s",
+            "gpu_vs_checker_rel": vs}
 
 
 PEAK = {"fp64": FP64_PEAK_TFLOPS, "fp32_bulk": FP32_PEAK_TFLOPS}

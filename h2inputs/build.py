@@ -6,8 +6,9 @@ The paper builds its inputs with a method it cites but does not describe
   * `chebyshev_h2`: kernel matrices with nested tensor Chebyshev
     interpolation bases.  Each cluster gets first-kind Chebyshev nodes of
     order p per axis on its tight bounding box (degenerate extents padded to
-    1e-9 times the root diameter); the leaf basis is the tensor Lagrange
-    basis evaluated at the cluster's points, the transfer matrix of a child is
+    1e-9 times the root diameter, or 1e-9 when all points coincide); the leaf
+    basis is the tensor Lagrange basis evaluated at the cluster's points, the
+    transfer matrix of a child is
     the parent's Lagrange basis evaluated at the child's nodes (exact, since
     the interpolant of a degree p-1 polynomial at p nodes is itself), a
     coupling matrix is the kernel at the two clusters' node sets, and a dense
@@ -103,7 +104,7 @@ def chebyshev_h2(tree, blocks, kernel, order):
     L = tree.L
     pts = tree.points
     root_diam = float(np.linalg.norm(tree.hi[0][0] - tree.lo[0][0]))
-    pad = 1e-9 * max(root_diam, 1e-300)
+    pad = 1e-9 * (root_diam if root_diam > 0.0 else 1.0)  # a single point: absolute pad
     nodes = [[_BoxNodes(tree.lo[lev][c], tree.hi[lev][c], order, pad)
               for c in range(1 << lev)] for lev in range(L + 1)]
     cdt = kernel.dtype

@@ -100,7 +100,7 @@ typedef struct {
 /* Upload an H^2 matrix to the device (padded per-level layout, FP64; with
  * is_complex != 0 the arrays V ... F hold interleaved complex pairs, counts
  * and offsets in complex elements).  Errors: H2_ERR_ARG (inconsistent
- * offsets, sizes or types), H2_ERR_NUMERIC (non-finite dense entry),
+ * offsets, sizes or types), H2_ERR_NUMERIC (a non-finite entry),
  * H2_ERR_OOM. */
 h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out);
 

@@ -686,9 +686,11 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
         need(off, c, (long long)nr * k, what);
         for (int j = 0; j < k; ++j)
           for (int i = 0; i < nr; ++i)
-            for (int part = 0; part < nc; ++part)
-              h[part * pl + (size_t)c * stride + i + (size_t)j * np] =
-                  src[(off[c] + i + (size_t)j * nr) * nc + part];
+            for (int part = 0; part < nc; ++part) {
+              const double v = src[(off[c] + i + (size_t)j * nr) * nc + part];
+              if (!std::isfinite(v)) throw Error(H2_ERR_NUMERIC, std::string("non-finite entry in ") + what);
+              h[part * pl + (size_t)c * stride + i + (size_t)j * np] = v;
+            }
       }
       dst = upload(h);
     };
@@ -714,9 +716,11 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
             if (kc_ * kp && !src) throw Error(H2_ERR_ARG, "null transfer array");
             for (int j = 0; j < kp; ++j)
               for (int i = 0; i < kc_; ++i)
-                for (int part = 0; part < nc; ++part)
-                  h[part * pl + (size_t)I * stride[l] + a * rp[l + 1] + i + (size_t)j * ld] =
-                      src[(off[fi] + i + (size_t)j * kc_) * nc + part];
+                for (int part = 0; part < nc; ++part) {
+                  const double v = src[(off[fi] + i + (size_t)j * kc_) * nc + part];
+                  if (!std::isfinite(v)) throw Error(H2_ERR_NUMERIC, std::string("non-finite entry in ") + what);
+                  h[part * pl + (size_t)I * stride[l] + a * rp[l + 1] + i + (size_t)j * ld] = v;
+                }
           }
         dst[l] = upload(h);
       }
@@ -744,9 +748,11 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
         need(m->S_off, g, (long long)kr * kc, "S");
         for (int j = 0; j < kc; ++j)
           for (int i = 0; i < kr; ++i)
-            for (int part = 0; part < nc; ++part)
-              h[part * pl + (size_t)q * bs + i + (size_t)j * M->rr[l]] =
-                  m->S[(m->S_off[g] + i + (size_t)j * kr) * nc + part];
+            for (int part = 0; part < nc; ++part) {
+              const double v = m->S[(m->S_off[g] + i + (size_t)j * kr) * nc + part];
+              if (!std::isfinite(v)) throw Error(H2_ERR_NUMERIC, "non-finite coupling entry");
+              h[part * pl + (size_t)q * bs + i + (size_t)j * M->rr[l]] = v;
+            }
       }
       M->S[l] = upload(h);
     }

@@ -13,7 +13,8 @@
 //     positive and max(diam t, diam s) <= eta * dist(t, s); other blocks are
 //     dense at the leaf level and split into four children above it;
 //   * bases: first-kind Chebyshev nodes of order p per axis on each cluster's
-//     tight box (degenerate extents padded to 1e-9 times the root diameter);
+//     tight box (degenerate extents padded to 1e-9 times the root diameter,
+//     or to 1e-9 when every point coincides);
 //     the leaf basis is the tensor Lagrange basis at the cluster's points, the
 //     transfer of a child the parent's Lagrange basis at the child's nodes,
 //     and column bases equal row bases (symmetric kernel);
@@ -200,7 +201,8 @@ h2_status build_impl(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* 
   const Tree t = make_tree(xyz, n, opts->leaf_size);
   const Blocks bl = make_blocks(t, opts->eta);
   const int L = t.L, nleaf = 1 << L;
-  const double pad = 1e-9 * std::max(diam(t.box[0][0]), 1e-300);
+  const double rd = diam(t.box[0][0]);
+  const double pad = 1e-9 * (rd > 0.0 ? rd : 1.0);  // coinciding points: absolute pad
   std::vector<std::vector<std::array<std::vector<double>, 3>>> ax(L + 1);
   for (int l = 0; l <= L; ++l)
     for (int c = 0; c < (1 << l); ++c) ax[l].push_back(cheb_axes(t.box[l][c], p, pad));
