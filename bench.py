@@ -270,7 +270,7 @@ def main():
                     help="concurrent requests of the serving loop")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the served-latency stream (0: skip)")
-    ap.add_argument("--sphere-n", type=int, default=16384,
+    ap.add_argument("--sphere-n", type=int, default=32768,
                     help="points of the complex Helmholtz sphere product (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device copies (scale of the HBM byte counters)")

@@ -209,9 +209,10 @@ h2_status h2_release(h2_ctx ctx, uint64_t ticket);
 /* C = A B (Sections III and IV).  A and B must have been loaded with the
  * same tree (leaf_off, perm) and block partition; C shares them (the
  * product keeps A's partition).  eps >= 0; eps == 0 selects EXACT.  A and
- * B both real or both complex (complex: FP64 only; Gram dimension <= 256,
- * half the real limit, since the Hermitian Grams are solved through their
- * real embedding).
+ * B both real or both complex (complex: FP64 only).  The Gram dimension of
+ * a cluster (twice the children's padded rank) is at most 1024 (512 for
+ * complex data, whose Hermitian Grams are solved through their real
+ * embedding).
  * Errors: H2_ERR_STRUCTURE, H2_ERR_ARG (eps < 0, bad mode/precision),
  * H2_ERR_UNSUPPORTED (a cluster whose Gram dimension exceeds the on-chip
  * eigensolver limit, reported in the message), H2_ERR_OOM, H2_ERR_NUMERIC. */

@@ -5,8 +5,8 @@
 // kept count follows from the truncation threshold tau * lambda_1.
 //
 // One workgroup per cluster (NT = 64..512 lanes chosen from the padded
-// dimension D <= 512; each lane holds up to SL = 4 or 8 rows of a column, so
-// one wave covers a whole column), FP64 throughout:
+// dimension D <= 1024; each lane holds up to SL = 4, 8 or 16 rows of a column,
+// so one wave covers a whole column), FP64 throughout:
 //   1. gather the live rows/columns (the children's actual ranks) into a
 //      packed lower triangle: in LDS for n <= kEigLdsN, else in the cluster's
 //      scratch;
@@ -478,11 +478,12 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
     }
     __syncthreads();
     // p = 2 A22 u: row r by T waves, each over a contiguous range of columns
+    // (more 64-row slots than waves: T = 1 and the waves loop over slots)
     const int nslot = (m + 63) >> 6;
-    const int T = NW / nslot;
-    {
-      const int slot = wave % nslot, t = wave / nslot;
-      if (t < T) {
+    const int T = nslot >= NW ? 1 : NW / nslot;
+    for (int unit = wave; unit < nslot * T; unit += NW) {
+      const int slot = unit % nslot, t = unit / nslot;
+      {
         const int r = i + 1 + slot * 64 + lane;
         const int c_lo = i + 1 + (m * t) / T, c_hi = i + 1 + (m * (t + 1)) / T;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -545,36 +546,41 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
     // the wave's column j; the loop takes them back by lane reads and keeps
     // four columns' loads in flight
     {
+      // columns per inner step (fewer with more row slots: registers)
+      constexpr int GC = SL > 8 ? 1 : 4;
       const int J = (m - wave + NW - 1) / NW;
-      double ucol = 0.0, wcol = 0.0;
-      if (lane < J) {
-        const int cc = i + 1 + wave + NW * lane;
-        double q = 0.0;
-        for (int t = 0; t < T; ++t) q += ybuf[t * ts + (cc - i - 1)];
-        ucol = vv[cc];
-        wcol = 2.0 * q - K * ucol;
-      }
-      // branch-free: lanes outside the triangle load and store a trash slot
-      for (int j = 0; j < J; j += 4) {
-        double pc[4][SL], uc[4], wc[4];
-        double* ptr[4][SL];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const int cg = j + g < J ? i + 1 + wave + NW * (j + g) : n;
-          uc[g] = read_lane(ucol, j + g);
-          wc[g] = read_lane(wcol, j + g);
-          const int base = cs(cg < n ? cg : 0, n) - cg;
-#pragma unroll
-          for (int s = 0; s < SL; ++s) {
-            const int r = i + 1 + lane + 64 * s;
-            ptr[g][s] = (r >= cg && r < n) ? P + (base + r) : trash;
-            pc[g][s] = *ptr[g][s];
-          }
+      for (int jb = 0; jb < J; jb += 64) {  // 64 of the wave's columns at a time
+        const int JB = J - jb < 64 ? J - jb : 64;
+        double ucol = 0.0, wcol = 0.0;
+        if (lane < JB) {
+          const int cc = i + 1 + wave + NW * (jb + lane);
+          double q = 0.0;
+          for (int t = 0; t < T; ++t) q += ybuf[t * ts + (cc - i - 1)];
+          ucol = vv[cc];
+          wcol = 2.0 * q - K * ucol;
         }
+        // branch-free: lanes outside the triangle load and store a trash slot
+        for (int j = 0; j < JB; j += GC) {
+          double pc[GC][SL], uc[GC], wc[GC];
+          double* ptr[GC][SL];
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
+          for (int g = 0; g < GC; ++g) {
+            const int cg = j + g < JB ? i + 1 + wave + NW * (jb + j + g) : n;
+            uc[g] = read_lane(ucol, j + g);
+            wc[g] = read_lane(wcol, j + g);
+            const int base = cs(cg < n ? cg : 0, n) - cg;
 #pragma unroll
-          for (int s = 0; s < SL; ++s) *ptr[g][s] = pc[g][s] - (ur[s] * wc[g] + wr[s] * uc[g]);
+            for (int s = 0; s < SL; ++s) {
+              const int r = i + 1 + lane + 64 * s;
+              ptr[g][s] = (r >= cg && r < n) ? P + (base + r) : trash;
+              pc[g][s] = *ptr[g][s];
+            }
+          }
+#pragma unroll
+          for (int g = 0; g < GC; ++g)
+#pragma unroll
+            for (int s = 0; s < SL; ++s) *ptr[g][s] = pc[g][s] - (ur[s] * wc[g] + wr[s] * uc[g]);
+        }
       }
     }
     __syncthreads();
@@ -611,10 +617,10 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
   double* F2 = S + 3 * DD;
   double* F3 = S + 4 * DD;
   const double tiny = 1e-16 * fmax(bnd, 1e-300);
-  if (tid < k) {
-    double* zm = Z + (long long)tid * ldz;
-    invit_solve(dd, ee, n, lam[tid], tiny, F0, F1, F2, F3, D, tid, zm, true, tid);
-    invit_solve(dd, ee, n, lam[tid], tiny, F0, F1, F2, F3, D, tid, zm, false, 0);
+  for (int m = tid; m < k; m += NT) {
+    double* zm = Z + (long long)m * ldz;
+    invit_solve(dd, ee, n, lam[m], tiny, F0, F1, F2, F3, D, m, zm, true, m);
+    invit_solve(dd, ee, n, lam[m], tiny, F0, F1, F2, F3, D, m, zm, false, 0);
   }
   __syncthreads();
 
@@ -646,10 +652,11 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
   bcgs2<NT, SL>(Z, ldz, n, k, pv, dv + NT);
 
   // 6. back-transformation: z <- H_0 ... H_{n-3} z, four vectors per wave
-  for (int b0 = wave * kVB; b0 < k; b0 += NW * kVB) {
-    double z[kVB][SL];
+  constexpr int VB = SL > 8 ? 2 : kVB;  // vectors per wave (registers)
+  for (int b0 = wave * VB; b0 < k; b0 += NW * VB) {
+    double z[VB][SL];
 #pragma unroll
-    for (int v = 0; v < kVB; ++v)
+    for (int v = 0; v < VB; ++v)
 #pragma unroll
       for (int s = 0; s < SL; ++s) {
         const int r = lane + 64 * s;
@@ -676,23 +683,23 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
           un[s] = (r > i - 1 && r < n) ? Pg[cn + r - (i - 1)] : 0.0;
         }
       }
-      double d[kVB];
+      double d[VB];
 #pragma unroll
-      for (int v = 0; v < kVB; ++v) {
+      for (int v = 0; v < VB; ++v) {
         double t = 0.0;
 #pragma unroll
         for (int s = 0; s < SL; ++s) t += u[s] * z[v][s];
         d[v] = t;
       }
 #pragma unroll
-      for (int v = 0; v < kVB; ++v) d[v] = 2.0 * wave_sum(d[v]);
+      for (int v = 0; v < VB; ++v) d[v] = 2.0 * wave_sum(d[v]);
 #pragma unroll
-      for (int v = 0; v < kVB; ++v)
+      for (int v = 0; v < VB; ++v)
 #pragma unroll
         for (int s = 0; s < SL; ++s) z[v][s] -= d[v] * u[s];
     }
 #pragma unroll
-    for (int v = 0; v < kVB; ++v) {
+    for (int v = 0; v < VB; ++v) {
       const int m = b0 + v;
       if (m < k) {
 #pragma unroll
@@ -735,8 +742,15 @@ __device__ __forceinline__ ClusterView cluster_view(const EigArgs& p) {
   return v;
 }
 
+// length of the symmetric product's partial sums: one per lane and 64-row
+// slot, at least NT
+__host__ __device__ __forceinline__ int partials_len(int dv, int nt) {
+  const int r = (dv + 63) & ~63;
+  return r > nt ? r : nt;
+}
+
 // Kernel 1: gather and tridiagonalise; zero the output columns.  LDS: packed
-// triangle [zr] | d[dv] | e[dv] | v[dv] | p-partials[NT] | red[8].
+// triangle [zr] | d[dv] | e[dv] | v[dv] | p-partials[partials_len] | red[8].
 template <int NT, int SL>
 __global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, int dv) {
   extern __shared__ double sm[];
@@ -758,11 +772,12 @@ __global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, 
   double* ee = dd + dv;
   double* vv = ee + dv;
   double* ybuf = vv + dv;
+  const int yb = partials_len(dv, NT);
   const double* Gc = p.G + (long long)v.c * p.gstride;
   // trash slot of the update: the unused reduction slots in LDS, or the unused
   // factor area of the scratch when the triangle is not in LDS
   if (n <= kEigLdsN && np <= zr)
-    gather_tridiag<NT, SL, true>(p, Gc, n, v.k1, v.half, v.D, sm, v.S, dd, ee, vv, ybuf, ybuf + NT);
+    gather_tridiag<NT, SL, true>(p, Gc, n, v.k1, v.half, v.D, sm, v.S, dd, ee, vv, ybuf, ybuf + yb);
   else
     gather_tridiag<NT, SL, false>(p, Gc, n, v.k1, v.half, v.D, v.S, v.S, dd, ee, vv, ybuf,
                               v.S + (long long)v.D * v.D);
@@ -855,8 +870,8 @@ __global__ __launch_bounds__(NT) void k_eig_val(EigArgs p0, EigArgs p1, int dv) 
     const double span = hi0 - lo0;
     int R = span > tol ? (int)ceil(log2(span / tol) / log2((double)(Q + 1))) : 0;
     R = R > 200 ? 200 : R;
-    const int g = tid / G, jl = tid % G;
-    if (g < k) {
+    const int jl = tid % G;
+    for (int g = tid / G; g < k; g += NT / G) {
       const int jt = n - 1 - g;
       double lo = lo0, hi = hi0;
       for (int it = 0; it < R; ++it) {
@@ -930,7 +945,7 @@ int eig_threads(int D) { return D <= 32 ? 64 : D <= 64 ? 128 : D <= 128 ? 256 : 
 // LDS regions (doubles) of the packed triangle (kernel 1) and of the
 // eigenvectors (kernel 3) for a launch of padded dimension D
 int tri_zr(int D, int nt) {
-  const int cap = kLdsBytes / 8 - 3 * D - nt - 8;
+  const int cap = kLdsBytes / 8 - 3 * D - partials_len(D, nt) - 8;
   if (D > kEigLdsN) return cap;
   const int zr = D * (D + 1) / 2;
   return zr < cap ? zr : cap;
@@ -955,8 +970,8 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
   }
   const dim3 grid(nclusters, 2);
   const int zt = tri_zr(D, NT), zv = vec_zr(D, NT);
-  hipLaunchKernelGGL((k_eig_tri<NT, SL>), grid, dim3(NT), sizeof(double) * ((size_t)zt + 3 * D + NT + 8),
-                     s, a, b, zt, D);
+  hipLaunchKernelGGL((k_eig_tri<NT, SL>), grid, dim3(NT),
+                     sizeof(double) * ((size_t)zt + 3 * D + partials_len(D, NT) + 8), s, a, b, zt, D);
   hipLaunchKernelGGL(k_eig_val<NT>, grid, dim3(NT), sizeof(double) * (4 * (size_t)D + 8), s, a, b,
                      D);
   const size_t lv = sizeof(double) * ((size_t)zv + 4 * D + NT + 8);
@@ -975,6 +990,7 @@ hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStre
   if (a.sstride < eig_scratch_doubles(a.D) || b.sstride < eig_scratch_doubles(b.D))
     return hipErrorInvalidValue;
   // SL row slots per lane: a wave holds a column of up to 64 SL rows
+  if (D > 512) return launch_nt<512, 16>(a, b, nclusters, D, s);
   if (D > 256) return launch_nt<512, 8>(a, b, nclusters, D, s);
   switch (eig_threads(D)) {
     case 64: return launch_nt<64, 4>(a, b, nclusters, D, s);
@@ -1035,7 +1051,7 @@ __global__ __launch_bounds__(256) void k_ceig_extract(CEigArgs p0, CEigArgs p1) 
   const CEigArgs& p = blockIdx.y == 0 ? p0 : p1;
   const int c = blockIdx.x, D = p.D, D2 = 2 * D, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  __shared__ double zr[256], zi[256], cr[256], ci[256], red[8];
+  __shared__ double zr[512], zi[512], cr[512], ci[512], red[8];
   const int k1 = p.k1[(long long)c * p.kstride];
   const int k2 = p.k2 ? p.k2[(long long)c * p.kstride] : 0;
   const int n = k1 + k2;
@@ -1115,7 +1131,7 @@ hipError_t launch_ceig_embed(const CEigArgs& a, const CEigArgs& b, int nclusters
 hipError_t launch_ceig_extract(const CEigArgs& a, const CEigArgs& b, int nclusters,
                                hipStream_t s) {
   if (nclusters <= 0) return hipSuccess;
-  if (a.D > 256 || b.D > 256) return hipErrorInvalidValue;
+  if (a.D > 512 || b.D > 512) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ceig_extract, dim3(nclusters, 2), dim3(256), 0, s, a, b);
   return hipGetLastError();
 }

@@ -126,7 +126,7 @@ struct CEigArgs {
 hipError_t launch_ceig_embed(const CEigArgs& a, const CEigArgs& b, int nclusters, hipStream_t s);
 hipError_t launch_ceig_extract(const CEigArgs& a, const CEigArgs& b, int nclusters, hipStream_t s);
 
-constexpr int kEigNmax = 512;  // largest Gram dimension
+constexpr int kEigNmax = 1024;  // largest Gram dimension
 constexpr int kEigLdsN = 195;  // largest dimension whose packed triangle stays in LDS
 // scratch per cluster (doubles) the eigensolver needs for padded dimension D
 inline long long eig_scratch_doubles(int D) { return 7LL * D * D + 4LL * D + 8; }
