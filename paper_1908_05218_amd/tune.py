@@ -22,7 +22,7 @@ TABLE = os.path.join(HERE, "tiles.txt")
 TILES = ["32x32", "96x32", "32x96", "96x96", "32x64", "64x32", "64x64"]
 
 # products timed per configuration: plates64k (C = A A, eps 1e-4) in both
-# precisions, and the complex Helmholtz sphere of 16,384 points (eps 1e-3)
+# precisions, and the complex Helmholtz sphere of 32,768 points (eps 1e-3)
 RUNNER = r"""
 import math, sys
 sys.path.insert(0, sys.argv[1])
@@ -34,7 +34,7 @@ A = h2.build(ctx, w.pts, w.leaf_size, w.eta, w.order, w.kernel.self_value)
 for prec in ("fp32_bulk", "fp64"):
     for _ in range(2):
         h2.mmp(ctx, A, A, 1e-4, precision=prec).free()
-n = 16384
+n = 32768
 kappa = 2 * math.pi / (10 * math.sqrt(4 * math.pi / n))
 rho = 2.0 / math.sqrt(n)
 pts = points.fibonacci_sphere(n)
@@ -84,7 +84,7 @@ def main():
     with open(TABLE, "w") as f:
         f.write("# workgroup tiles of the batched GEMM by launch key, written by\n"
                 "# python -m paper_1908_05218_amd.tune (plates64k FP32-bulk and FP64 products,\n"
-                "# complex Helmholtz sphere of 16,384 points); key: element bytes, A float,\n"
+                "# complex Helmholtz sphere of 32,768 points); key: element bytes, A float,\n"
                 "# B float, block-product symbol, transA, transB, m, n, k, log2 outputs,\n"
                 "# log2 tasks per output; value: tile id (0 32x32, 1 96x32, 2 32x96, 3 96x96,\n"
                 "# 4 32x64, 5 64x32, 6 64x64)\n"
