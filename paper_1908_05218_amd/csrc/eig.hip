@@ -40,6 +40,13 @@ namespace {
 
 constexpr int kLdsBytes = 163840;  // LDS per workgroup on gfx950
 constexpr int kVB = 4;             // vectors per wave in the back-transformation
+constexpr int kRed = 8;            // reduction slots in LDS: one per wave, up to 512 lanes
+
+// index of the calling wave in its workgroup, as a wave-uniform (scalar) value
+// so that per-wave index arithmetic runs on the scalar unit
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
 
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
@@ -231,7 +238,7 @@ __device__ void invit_solve(const double* dd, const double* ee, int n, double lm
 template <int NT>
 __device__ void cgs2(double* Z, int ldz, int n, int m, int q0, double* dots, double* red) {
   constexpr int NW = NT / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   double* zm = Z + (long long)m * ldz;
   for (int pass = 0; pass < 2 && m > q0; ++pass) {
     for (int q = q0 + wave; q < m; q += NW) {
@@ -273,7 +280,7 @@ __device__ void cgs2(double* Z, int ldz, int n, int m, int q0, double* dots, dou
 // projection coefficients.
 template <int NT, int SL>
 __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   for (int m0 = 0; m0 < k;) {
     int b = k - m0 < 8 ? k - m0 : 8;
     if (m0 > 0 && b * m0 > cap) b = cap / m0 > 0 ? cap / m0 : 1;
@@ -410,7 +417,7 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
                                                double* dd, double* ee, double* vv,
                                                double* ybuf, double* trash) {
   constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   // 1. gather the live block, packed lower triangle
   int bad = 0;
   for (int j = wave; j < n; j += NW) {
@@ -610,7 +617,7 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
                                         double bnd, double* pv, double* red, int dv, int k1,
                                         int half, double* Uc) {
   constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   // 4. inverse iteration, lane m owns vector m
   double* F0 = S + DD;
   double* F1 = S + 2 * DD;
@@ -808,7 +815,7 @@ __global__ __launch_bounds__(NT) void k_eig_val(EigArgs p0, EigArgs p1, int dv) 
   const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
   const ClusterView v = cluster_view(p);
   if (!v.ok || v.D > dv) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int n = v.n;
   double* dd = sm;
   double* ee = dd + dv;
@@ -945,13 +952,13 @@ int eig_threads(int D) { return D <= 32 ? 64 : D <= 64 ? 128 : D <= 128 ? 256 : 
 // LDS regions (doubles) of the packed triangle (kernel 1) and of the
 // eigenvectors (kernel 3) for a launch of padded dimension D
 int tri_zr(int D, int nt) {
-  const int cap = kLdsBytes / 8 - 3 * D - partials_len(D, nt) - 8;
+  const int cap = kLdsBytes / 8 - 3 * D - partials_len(D, nt) - kRed;
   if (D > kEigLdsN) return cap;
   const int zr = D * (D + 1) / 2;
   return zr < cap ? zr : cap;
 }
 int vec_zr(int D, int nt) {
-  const int cap = kLdsBytes / 8 - 4 * D - nt - 8;
+  const int cap = kLdsBytes / 8 - 4 * D - nt - kRed;
   const long long zfull = (long long)(D | 1) * D;
   return zfull < cap ? (int)zfull : cap;
 }
@@ -971,13 +978,14 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
   const dim3 grid(nclusters, 2);
   const int zt = tri_zr(D, NT), zv = vec_zr(D, NT);
   hipLaunchKernelGGL((k_eig_tri<NT, SL>), grid, dim3(NT),
-                     sizeof(double) * ((size_t)zt + 3 * D + partials_len(D, NT) + 8), s, a, b, zt, D);
-  hipLaunchKernelGGL(k_eig_val<NT>, grid, dim3(NT), sizeof(double) * (4 * (size_t)D + 8), s, a, b,
+                     sizeof(double) * ((size_t)zt + 3 * D + partials_len(D, NT) + kRed), s, a, b, zt,
                      D);
-  const size_t lv = sizeof(double) * ((size_t)zv + 4 * D + NT + 8);
+  hipLaunchKernelGGL(k_eig_val<NT>, grid, dim3(NT), sizeof(double) * (4 * (size_t)D + kRed), s, a,
+                     b, D);
+  const size_t lv = sizeof(double) * ((size_t)zv + 4 * D + NT + kRed);
   hipLaunchKernelGGL((k_eig_vec<NT, SL, true>), grid, dim3(NT), lv, s, a, b, zv, D);
-  hipLaunchKernelGGL((k_eig_vec<NT, SL, false>), grid, dim3(NT), sizeof(double) * (4 * D + NT + 8), s,
-                     a, b, zv, D);
+  hipLaunchKernelGGL((k_eig_vec<NT, SL, false>), grid, dim3(NT), sizeof(double) * (4 * D + NT + kRed),
+                     s, a, b, zv, D);
   return hipGetLastError();
 }
 
@@ -1050,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_ceig_extract(CEigArgs p0, CEigArgs p1) 
   constexpr int NT = 256, NW = NT / 64;
   const CEigArgs& p = blockIdx.y == 0 ? p0 : p1;
   const int c = blockIdx.x, D = p.D, D2 = 2 * D, tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = wave_id();
   __shared__ double zr[512], zi[512], cr[512], ci[512], red[8];
   const int k1 = p.k1[(long long)c * p.kstride];
   const int k2 = p.k2 ? p.k2[(long long)c * p.kstride] : 0;
