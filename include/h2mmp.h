@@ -256,6 +256,23 @@ typedef struct {
 } h2_export_buffers;
 h2_status h2_export(h2_mat M, const h2_export_buffers* out);
 
+/* File interchange in the flat layout above: a NumPy .npz archive (zip of
+ * stored, uncompressed .npy members; numpy.load reads it, numpy.savez writes
+ * what h2_load_file reads) with members n, L, is_complex (int64 scalars),
+ * leaf_off, perm, node_off, krow, kcol and the *_off arrays (int64),
+ * node_row, node_col, node_type (int32), and V, W, Er, Ec, S, F (float64, or
+ * complex128 when is_complex).  Archives and members are limited to 4 GiB
+ * (no zip64).
+ * h2_save: writes M (the h2_export data) to `path`, replacing the file.
+ *   Errors: H2_ERR_ARG (cannot write), H2_ERR_UNSUPPORTED (over 4 GiB).
+ * h2_load_file: reads `path` and uploads it as h2_load does; members other
+ *   than those listed are ignored.  Errors: H2_ERR_ARG (not an archive, a
+ *   missing member, a wrong element type, sizes that do not match n and L,
+ *   offsets that run past their arrays, a checksum mismatch), H2_ERR_UNSUPPORTED
+ *   (compressed or zip64 members), and those of h2_load. */
+h2_status h2_save(h2_mat M, const char* path);
+h2_status h2_load_file(h2_ctx ctx, const char* path, h2_mat* out);
+
 /* Statistics of the last h2_mmp that produced M (zeros for loaded
  * matrices).  rank_max/rank_mean per level for the row (r) and column (c)
  * bases; canonical flops of the block products (2 r1 r2 r3 per evaluated

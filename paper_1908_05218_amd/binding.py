@@ -113,11 +113,14 @@ def lib():
         L.h2_wait.argtypes = [vp, C.c_uint64, C.POINTER(_Result)]
         L.h2_release.argtypes = [vp, C.c_uint64]
         L.h2_serve_slots.argtypes = [vp, C.c_int]
+        L.h2_save.argtypes = [vp, C.c_char_p]
+        L.h2_load_file.argtypes = [vp, C.c_char_p, C.POINTER(vp)]
         L.h2_last_error.restype = C.c_char_p
         L.h2_version.restype = C.c_int
         for f in ("h2_ctx_create", "h2_load", "h2_build", "h2_submit", "h2_poll", "h2_wait",
                   "h2_release", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
-                  "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling", "h2_serve_slots"):
+                  "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling", "h2_serve_slots",
+                  "h2_save", "h2_load_file"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -230,6 +233,18 @@ def load(ctx, flat):
     hm = _host_matrix(flat, keep)
     h = C.c_void_p()
     _check(lib().h2_load(ctx.h, C.byref(hm), C.byref(h)))
+    return Matrix(ctx, h)
+
+
+def save(M, path):
+    """h2_save: write M to `path` as a NumPy .npz archive in the flat layout."""
+    _check(lib().h2_save(M.h, os.fsencode(path)))
+
+
+def load_file(ctx, path):
+    """h2_load_file: upload the .npz archive at `path` (flat layout)."""
+    h = C.c_void_p()
+    _check(lib().h2_load_file(ctx.h, os.fsencode(path), C.byref(h)))
     return Matrix(ctx, h)
 
 
