@@ -794,6 +794,309 @@ __global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, 
   }
 }
 
+// ---------------------------------------------------------------------
+// Kernel 1 for dimensions up to 32 NW (NW waves, NW in {1, 2, 4, 8}): the
+// matrix stays in registers for the whole reduction.  Wave w holds columns
+// c = w + NW j (j < 32); lane l holds rows l + 64 s of each column for the
+// 64-row blocks s from the column's own block c / 64 on (the symmetric block
+// lower triangle, diagonal blocks stored in full).  Per Householder step:
+//   * the pivot column (written to LDS by its owner during the previous
+//     update) gives the reflector u in every wave's registers;
+//   * p = 2 A u: every stored entry contributes lane-locally to its row
+//     (A[r,c] u[c]); the entries of the strictly lower blocks also stand for
+//     their transposes, whose contributions A[r,c] u[r] to row c are one dot
+//     product per column, summed across lanes for 16 columns at once by a
+//     halving butterfly (each exchange halves the values a lane carries);
+//     the waves' partial vectors meet in LDS;
+//   * A -= u w^T + w u^T in registers, w = p - (u.p) u, rows of the finished
+//     part left untouched (u = w = 0 there).
+// Three workgroup barriers per step; LDS holds only vectors.
+
+// columns per wave; 64-row block of local column j
+constexpr int kRegCols = 32;
+template <int NW>
+__device__ constexpr int diag_slot(int j) { return (NW * j) >> 6; }
+
+// exchange of 64-bit values between lane halves (xor 32) or between odd and
+// even rows of 16 lanes (xor 16): afterwards x holds the first operand's
+// lower part and the second operand's lower part, y the two upper parts
+__device__ __forceinline__ void swap_halves32(double& x, double& y) {
+  const unsigned long long xb = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long yb = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)xb, (unsigned)yb, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ void swap_rows16(double& x, double& y) {
+  const unsigned long long xb = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long yb = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)xb, (unsigned)yb, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
+// t[q] (q < 16) summed over all 64 lanes: lane l returns the sum for column
+// q = 8 b1 + 4 b0 + 2 b4 + b5 (b_k: bit k of l).  Each halving exchange
+// leaves a lane one of every two values, summed with its partner's: xor 32
+// and xor 16 by lane-half swaps, xor 1 and xor 2 by quad permutes; the four
+// lanes left with the same column (bits 2 and 3) are summed by row rotates.
+__device__ __forceinline__ double butterfly16(const double* t, int lane) {
+  double t1[8], t2[4], t3[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    double x = t[2 * k], y = t[2 * k + 1];
+    swap_halves32(x, y);
+    t1[k] = x + y;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double x = t1[2 * k], y = t1[2 * k + 1];
+    swap_rows16(x, y);
+    t2[k] = x + y;
+  }
+  const bool b0 = lane & 1, b1 = lane & 2;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double keep = b0 ? t2[2 * k + 1] : t2[2 * k], give = b0 ? t2[2 * k] : t2[2 * k + 1];
+    t3[k] = keep + dpp<0xB1>(give);  // quad_perm [1,0,3,2]
+  }
+  const double keep = b1 ? t3[1] : t3[0], give = b1 ? t3[0] : t3[1];
+  double v = keep + dpp<0x4E>(give);  // quad_perm [2,3,0,1]
+  v += dpp<0x128>(v);                 // row_ror:8
+  v += dpp<0x124>(v);                 // row_ror:4
+  return v;
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1, int dv) {
+  constexpr int NT = NW * 64, RS = NW >= 4 ? NW / 2 : 1, J = kRegCols, RM = 64 * RS;
+  // a group of 16 columns has cross-block (transposed) terms when its first
+  // column's block is not the last one
+  constexpr int NG = RS > 1 ? (diag_slot<NW>(16) < RS - 1 ? 2 : 1) : 0;
+  __shared__ double pc[2][RM];      // pivot column, by step parity
+  __shared__ double ypart[NW][RM];  // per-wave partials of the row-wise terms
+  __shared__ double tsum[RM];       // transposed terms, by column
+  __shared__ double yfull[RM];      // p = 2 A u
+  __shared__ double dd[RM], ee[RM], last[RM];
+  const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
+  const ClusterView v = cluster_view(p);
+  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
+  double* Uc = p.U + (long long)v.c * p.ustride;
+  for (long long e = tid; e < (long long)v.D * v.D; e += NT) Uc[e] = 0.0;
+  if (!v.ok || v.D > dv || v.n > NW * J) {
+    if (tid == 0) {
+      p.rank[v.c] = 0;
+      if (v.n != 0) p.status[1] = 1;
+    }
+    return;
+  }
+  const int n = v.n;
+  double* Pg = v.S;
+  const double* Gc = p.G + (long long)v.c * p.gstride;
+
+  // gather the live block (rows and columns [0,k1) and [half, half+k2));
+  // only the Gram's lower triangle is read (entries above the diagonal of
+  // the diagonal blocks from their mirror images)
+  double a[J][RS];
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int c = w + NW * j;
+    const int oc = c < v.k1 ? c : v.half + (c - v.k1);
+#pragma unroll
+    for (int s = diag_slot<NW>(j); s < RS; ++s) {
+      const int r = lane + 64 * s;
+      double x = 0.0;
+      if (c < n && r < n) {
+        const int orow = r < v.k1 ? r : v.half + (r - v.k1);
+        x = r >= c ? Gc[orow + (long long)oc * v.D] : Gc[oc + (long long)orow * v.D];
+        if (!(x == x) || x - x != 0.0) bad = 1;
+      }
+      a[j][s] = x;
+    }
+  }
+  if (bad) p.status[0] = 1;
+  if (w == 0) {
+#pragma unroll
+    for (int s = 0; s < RS; ++s) pc[0][lane + 64 * s] = a[0][s];
+  }
+  __syncthreads();
+
+  for (int i = 0; i + 2 < n; ++i) {
+    // this wave's active columns i < c < n are local j in [jlo, jhi).  Work
+    // is skipped by blocks of 8 columns: an inactive column has u[c] = w[c] = 0
+    // and contributes nothing, and whole blocks schedule better than single
+    // columns.  The opaque copy of the wave index keeps per-column quantities
+    // from being precomputed for all columns outside the loop
+    int wl = w;
+    asm volatile("" : "+s"(wl));
+    const int jlo = (i + 1 - wl + NW - 1) / NW, jhi = (n - wl + NW - 1) / NW;
+    const double* col = pc[i & 1];
+    double* next = pc[(i + 1) & 1];
+    double u[RS];
+    double part = 0.0;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int r = lane + 64 * s;
+      u[s] = (r > i && r < n) ? col[r] : 0.0;
+      part += u[s] * u[s];
+    }
+    const double xx = wave_sum(part);
+    const double x0 = col[i + 1];
+    const double diag = col[i];
+    const double nx = sqrt(xx);
+    const long long ci = (long long)i * n - ((long long)i * (i - 1)) / 2;
+    if (!(nx > 0.0)) {  // column already reduced: H_i = I, A unchanged
+      if (w == 0) {
+#pragma unroll
+        for (int s = 0; s < RS; ++s) {
+          const int r = lane + 64 * s;
+          if (r > i && r < n) Pg[ci + r - i] = 0.0;
+        }
+        if (lane == 0) {
+          dd[i] = diag;
+          ee[i] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        if (wl + NW * j == i + 1) {
+#pragma unroll
+          for (int s = diag_slot<NW>(j); s < RS; ++s) next[lane + 64 * s] = a[j][s];
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    const double alpha = -copysign(nx, x0);
+    const double v0 = x0 - alpha;
+    const double rvn = 1.0 / sqrt(xx - x0 * x0 + v0 * v0);
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int r = lane + 64 * s;
+      u[s] = (r == i + 1 ? v0 : u[s]) * rvn;
+    }
+    if (w == 0) {
+#pragma unroll
+      for (int s = 0; s < RS; ++s) {
+        const int r = lane + 64 * s;
+        if (r > i && r < n) Pg[ci + r - i] = u[s];
+      }
+      if (lane == 0) {
+        dd[i] = diag;
+        ee[i] = alpha;
+      }
+    }
+
+    // p = 2 A u
+    double y[RS];
+#pragma unroll
+    for (int s = 0; s < RS; ++s) y[s] = 0.0;
+#pragma unroll
+    for (int g = 0; g < J / 16; ++g) {
+      double t[16];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int jb = 16 * g + 8 * h;
+        if (jb + 8 > jlo && jb < jhi) {
+#pragma unroll
+          for (int q = 8 * h; q < 8 * h + 8; ++q) {
+            const int j = 16 * g + q;
+            const int sd = diag_slot<NW>(j);
+            const double uc = read_lane(u[sd], (wl + NW * j) & 63);
+#pragma unroll
+            for (int s = sd; s < RS; ++s) y[s] += a[j][s] * uc;
+            t[q] = 0.0;
+#pragma unroll
+            for (int s = sd + 1; s < RS; ++s) t[q] += a[j][s] * u[s];
+          }
+        } else {
+#pragma unroll
+          for (int q = 8 * h; q < 8 * h + 8; ++q) t[q] = 0.0;
+        }
+      }
+      // a group without active columns leaves its (stale) partials: they
+      // only reach rows outside (i, n), where w is cleared below
+      if (g < NG && jlo < 16 * g + 16 && jhi > 16 * g) {
+        const int q = ((lane >> 1) & 1) * 8 + (lane & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 5) & 1);
+        const double sum = butterfly16(t, lane);
+        if ((lane & 12) == 0) tsum[wl + NW * (16 * g + q)] = sum;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < RS; ++s) ypart[w][lane + 64 * s] = y[s];
+    __syncthreads();
+    if (lane < 32) {
+      const int r = 32 * w + lane;
+      double acc = 0.0;
+      // rows of the last block receive no transposed terms
+      if (NG > 0 && r < 64 * (RS - 1)) acc = tsum[r];
+#pragma unroll
+      for (int x = 0; x < NW; ++x) acc += ypart[x][r];
+      yfull[r] = 2.0 * acc;
+    }
+    __syncthreads();
+    double wv[RS];
+    part = 0.0;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int r = lane + 64 * s;
+      wv[s] = (r > i && r < n) ? yfull[r] : 0.0;
+      part += u[s] * wv[s];
+    }
+    const double K = wave_sum(part);
+#pragma unroll
+    for (int s = 0; s < RS; ++s) wv[s] -= K * u[s];
+
+    // A -= u w^T + w u^T on the stored blocks; the owner of column i+1 hands
+    // it on as the next pivot
+#pragma unroll
+    for (int jb = 0; jb < J; jb += 8) {
+      if (jb + 8 > jlo && jb < jhi) {
+#pragma unroll
+        for (int j = jb; j < jb + 8; ++j) {
+          const int sd = diag_slot<NW>(j);
+          const int lc = (wl + NW * j) & 63;
+          const double uc = read_lane(u[sd], lc), wc = read_lane(wv[sd], lc);
+#pragma unroll
+          for (int s = sd; s < RS; ++s) a[j][s] -= u[s] * wc + wv[s] * uc;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (wl + NW * j == i + 1) {
+#pragma unroll
+        for (int s = diag_slot<NW>(j); s < RS; ++s) next[lane + 64 * s] = a[j][s];
+      }
+    }
+    __syncthreads();
+  }
+  // the trailing 2x2 (or 1x1) block
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (w + NW * j == n - 1) {
+#pragma unroll
+      for (int s = diag_slot<NW>(j); s < RS; ++s) last[lane + 64 * s] = a[j][s];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (n >= 2) {
+      dd[n - 2] = pc[(n - 2) & 1][n - 2];
+      ee[n - 2] = pc[(n - 2) & 1][n - 1];
+    }
+    dd[n - 1] = last[n - 1];
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += NT) {
+    v.tri[j] = dd[j];
+    v.tri[v.D + j] = j < n - 1 ? ee[j] : 0.0;
+  }
+}
+
 // Gershgorin bound of the tridiagonal matrix (d, e)
 __device__ __forceinline__ void gershgorin(const double* dd, const double* ee, int n, double& gl,
                                            double& gu) {
@@ -967,9 +1270,13 @@ template <int NT, int SL>
 hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    for (const void* f : {(const void*)k_eig_tri<NT, SL>, (const void*)k_eig_val<NT>,
-                          (const void*)k_eig_vec<NT, SL, true>,
+    // kernels with dynamic LDS (the register-resident tridiagonalisation has
+    // only static LDS and keeps the default)
+    const void* tri = nullptr;
+    if constexpr (SL != 4) tri = (const void*)k_eig_tri<NT, SL>;
+    for (const void* f : {tri, (const void*)k_eig_val<NT>, (const void*)k_eig_vec<NT, SL, true>,
                           (const void*)k_eig_vec<NT, SL, false>}) {
+      if (!f) continue;
       hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
       if (e != hipSuccess) return e;
     }
@@ -977,9 +1284,12 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
   }
   const dim3 grid(nclusters, 2);
   const int zt = tri_zr(D, NT), zv = vec_zr(D, NT);
-  hipLaunchKernelGGL((k_eig_tri<NT, SL>), grid, dim3(NT),
-                     sizeof(double) * ((size_t)zt + 3 * D + partials_len(D, NT) + kRed), s, a, b, zt,
-                     D);
+  if constexpr (SL == 4)  // dimensions up to 4 x 64: the triangle in registers
+    hipLaunchKernelGGL((k_eig_tri_reg<NT / 64>), grid, dim3(NT), 0, s, a, b, D);
+  else
+    hipLaunchKernelGGL((k_eig_tri<NT, SL>), grid, dim3(NT),
+                       sizeof(double) * ((size_t)zt + 3 * D + partials_len(D, NT) + kRed), s, a, b,
+                       zt, D);
   hipLaunchKernelGGL(k_eig_val<NT>, grid, dim3(NT), sizeof(double) * (4 * (size_t)D + kRed), s, a,
                      b, D);
   const size_t lv = sizeof(double) * ((size_t)zv + 4 * D + NT + kRed);
