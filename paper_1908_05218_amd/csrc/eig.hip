@@ -27,8 +27,9 @@
 //   5. block classical Gram-Schmidt with one re-orthogonalisation over all
 //      kept vectors, in descending eigenvalue order (blocks of 8 projected
 //      by the workgroup, orthonormalised inside by one wave);
-//   6. back-transformation by the reflectors, one wave per four vectors held
-//      in registers, and scatter to the padded row layout.
+//   6. back-transformation by the reflectors, one wave per eight (four, two
+//      for the largest dimensions) vectors held in registers, and scatter to
+//      the padded row layout.
 // Wave reductions use DPP row operations and lane reads, not LDS permutes.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -77,6 +78,57 @@ __device__ __forceinline__ double group_red(double v, int G) {
   if (G >= 4) v = MAX ? fmax(v, dpp<0x4E>(v)) : fmin(v, dpp<0x4E>(v));
   if (G >= 8) v = MAX ? fmax(v, dpp<0x141>(v)) : fmin(v, dpp<0x141>(v));
   return v;
+}
+
+// exchange of 64-bit values between lane halves (xor 32) or between odd and
+// even rows of 16 lanes (xor 16): afterwards x holds the first operand's
+// lower part and the second operand's lower part, y the two upper parts
+__device__ __forceinline__ void swap_halves32(double& x, double& y) {
+  const unsigned long long xb = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long yb = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)xb, (unsigned)yb, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ void swap_rows16(double& x, double& y) {
+  const unsigned long long xb = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long yb = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)xb, (unsigned)yb, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
+// Sums over the 64 lanes of t[0..7]; every lane receives all eight in
+// out[] (wave-uniform).  Halving exchanges (lane-half swaps for xor 32 and
+// xor 16, a quad permute for xor 1) leave each lane one of the eight values,
+// the rest of its lanes are summed by quad permute and row rotates, and the
+// eight sums are read from one lane each.  Every lane of the wave must be
+// active.
+__device__ __forceinline__ void wave_sum8(const double* t, double* out) {
+  double t1[4], t2[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double x = t[2 * k], y = t[2 * k + 1];
+    swap_halves32(x, y);
+    t1[k] = x + y;
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    double x = t1[2 * k], y = t1[2 * k + 1];
+    swap_rows16(x, y);
+    t2[k] = x + y;
+  }
+  // lane l now holds partial sums of values 4k + 2 b4 + b5 (b_k: bit k of l)
+  const bool b0 = threadIdx.x & 1;
+  const double keep = b0 ? t2[1] : t2[0], give = b0 ? t2[0] : t2[1];
+  double v = keep + dpp<0xB1>(give);  // value 4 b0 + 2 b4 + b5
+  v += dpp<0x4E>(v);                  // quad_perm [2,3,0,1]
+  v += dpp<0x128>(v);                 // row_ror:8
+  v += dpp<0x124>(v);                 // row_ror:4
+#pragma unroll
+  for (int q = 0; q < 8; ++q) out[q] = read_lane(v, ((q >> 2) & 1) | (((q >> 1) & 1) << 4) | ((q & 1) << 5));
 }
 
 template <int NT>
@@ -331,7 +383,7 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
         for (int s = 0; s < SL; ++s) t0 += z[s] * z[s];
         const double nb2 = wave_sum(t0);
         for (int pass = 0; pass < 2 && j > 0; ++pass) {
-          double d[8];
+          double t8[8], d[8];
 #pragma unroll
           for (int jj = 0; jj < 8; ++jj) {
             double t = 0.0;
@@ -343,8 +395,9 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
                 if (r < n) t += zq[r] * z[s];
               }
             }
-            d[jj] = wave_sum(t);
+            t8[jj] = t;
           }
+          wave_sum8(t8, d);
 #pragma unroll
           for (int jj = 0; jj < 8; ++jj) {
             if (jj < j) {
@@ -658,8 +711,9 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
   // blocks (coefficients in the contiguous pv | ybuf region of LDS)
   bcgs2<NT, SL>(Z, ldz, n, k, pv, dv + NT);
 
-  // 6. back-transformation: z <- H_0 ... H_{n-3} z, four vectors per wave
-  constexpr int VB = SL > 8 ? 2 : kVB;  // vectors per wave (registers)
+  // 6. back-transformation: z <- H_0 ... H_{n-3} z, VB vectors per wave
+  // (eight with four row slots: their dot products share one batched wave sum)
+  constexpr int VB = SL > 8 ? 2 : SL > 4 ? kVB : 8;
   for (int b0 = wave * VB; b0 < k; b0 += NW * VB) {
     double z[VB][SL];
 #pragma unroll
@@ -698,8 +752,17 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
         for (int s = 0; s < SL; ++s) t += u[s] * z[v][s];
         d[v] = t;
       }
+      if constexpr (VB == 8) {
+        double t8[8];
 #pragma unroll
-      for (int v = 0; v < VB; ++v) d[v] = 2.0 * wave_sum(d[v]);
+        for (int v = 0; v < 8; ++v) t8[v] = d[v];
+        wave_sum8(t8, d);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) d[v] *= 2.0;
+      } else {
+#pragma unroll
+        for (int v = 0; v < VB; ++v) d[v] = 2.0 * wave_sum(d[v]);
+      }
 #pragma unroll
       for (int v = 0; v < VB; ++v)
 #pragma unroll
@@ -816,26 +879,6 @@ __global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, 
 constexpr int kRegCols = 32;
 template <int NW>
 __device__ constexpr int diag_slot(int j) { return (NW * j) >> 6; }
-
-// exchange of 64-bit values between lane halves (xor 32) or between odd and
-// even rows of 16 lanes (xor 16): afterwards x holds the first operand's
-// lower part and the second operand's lower part, y the two upper parts
-__device__ __forceinline__ void swap_halves32(double& x, double& y) {
-  const unsigned long long xb = (unsigned long long)__double_as_longlong(x);
-  const unsigned long long yb = (unsigned long long)__double_as_longlong(y);
-  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)xb, (unsigned)yb, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
-  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
-}
-__device__ __forceinline__ void swap_rows16(double& x, double& y) {
-  const unsigned long long xb = (unsigned long long)__double_as_longlong(x);
-  const unsigned long long yb = (unsigned long long)__double_as_longlong(y);
-  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)xb, (unsigned)yb, false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
-  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
-}
 
 // t[q] (q < 16) summed over all 64 lanes: lane l returns the sum for column
 // q = 8 b1 + 4 b0 + 2 b4 + b5 (b_k: bit k of l).  Each halving exchange
@@ -1261,6 +1304,10 @@ int tri_zr(int D, int nt) {
   return zr < cap ? zr : cap;
 }
 int vec_zr(int D, int nt) {
+  // dimensions in (64, 128] come in launches of many clusters: the
+  // eigenvectors go to scratch so that several workgroups share a CU (one
+  // would fill its LDS)
+  if (D > 64 && D <= 128) return 0;
   const int cap = kLdsBytes / 8 - 4 * D - nt - kRed;
   const long long zfull = (long long)(D | 1) * D;
   return zfull < cap ? (int)zfull : cap;
