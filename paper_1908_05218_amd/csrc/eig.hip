@@ -323,6 +323,93 @@ __device__ void cgs2(double* Z, int ldz, int n, int m, int q0, double* dots, dou
   __syncthreads();
 }
 
+// Orthonormalises vectors m0 .. m0+b-1 (b <= 8) of Z among themselves, in
+// order, by the calling wave (every lane active): each vector twice against
+// the block's earlier members; a vector that loses more than half its norm
+// there is re-orthogonalised twice against every earlier vector; then it is
+// normalised.
+template <int SL>
+__device__ void orth_block(double* Z, int ldz, int n, int m0, int b) {
+  const int lane = threadIdx.x & 63;
+  for (int j = 0; j < b; ++j) {
+    double* zj = Z + (long long)(m0 + j) * ldz;
+    double z[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int r = lane + 64 * s;
+      z[s] = r < n ? zj[r] : 0.0;
+    }
+    double t0 = 0.0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) t0 += z[s] * z[s];
+    const double nb2 = wave_sum(t0);
+    for (int pass = 0; pass < 2 && j > 0; ++pass) {
+      double t8[8], d[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        double t = 0.0;
+        if (jj < j) {
+          const double* zq = Z + (long long)(m0 + jj) * ldz;
+#pragma unroll
+          for (int s = 0; s < SL; ++s) {
+            const int r = lane + 64 * s;
+            if (r < n) t += zq[r] * z[s];
+          }
+        }
+        t8[jj] = t;
+      }
+      wave_sum8(t8, d);
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        if (jj < j) {
+          const double* zq = Z + (long long)(m0 + jj) * ldz;
+#pragma unroll
+          for (int s = 0; s < SL; ++s) {
+            const int r = lane + 64 * s;
+            if (r < n) z[s] -= d[jj] * zq[r];
+          }
+        }
+      }
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) t += z[s] * z[s];
+    double nrm2 = wave_sum(t);
+    if (nrm2 < 0.25 * nb2) {
+      // the vector was nearly dependent on the block's earlier members:
+      // what is left is rounding noise that still leans on the earlier
+      // blocks, so it is re-orthogonalised against every earlier vector,
+      // twice, before it is normalised
+      for (int pass = 0; pass < 2; ++pass)
+        for (int q = 0; q < m0 + j; ++q) {
+          const double* zq = Z + (long long)q * ldz;
+          double u = 0.0;
+#pragma unroll
+          for (int s = 0; s < SL; ++s) {
+            const int r = lane + 64 * s;
+            if (r < n) u += zq[r] * z[s];
+          }
+          const double dq = wave_sum(u);
+#pragma unroll
+          for (int s = 0; s < SL; ++s) {
+            const int r = lane + 64 * s;
+            if (r < n) z[s] -= dq * zq[r];
+          }
+        }
+      t = 0.0;
+#pragma unroll
+      for (int s = 0; s < SL; ++s) t += z[s] * z[s];
+      nrm2 = wave_sum(t);
+    }
+    const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int r = lane + 64 * s;
+      if (r < n) zj[r] = z[s] * inv;
+    }
+  }
+}
+
 // Block classical Gram-Schmidt with re-orthogonalisation over the k kept
 // vectors (columns of Z, leading dimension ldz), in blocks of at most 8:
 // two passes project a block on all earlier vectors (whole workgroup), then
@@ -369,58 +456,76 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
       }
       __syncthreads();
     }
-    if (wave == 0) {
-      for (int j = 0; j < b; ++j) {
-        double* zj = Z + (long long)(m0 + j) * ldz;
-        double z[SL];
+    if (wave == 0) orth_block<SL>(Z, ldz, n, m0, b);
+    __syncthreads();
+    m0 += b;
+  }
+}
+
+// Block Gram-Schmidt with re-orthogonalisation for dimensions up to 256
+// (four row slots), in blocks of NW vectors; wave j holds vector m0 + j in
+// registers throughout.  It first projects the vector out of all earlier
+// blocks, twice, eight vectors at a time (one batched wave sum per eight dot
+// products, the projection subtracted at once).  Inside the block the waves
+// then take turns: at step t wave t normalises its vector (after
+// re-orthogonalising it twice against every earlier vector if it kept less
+// than half its norm) and stores it, and each later wave projects it out,
+// twice.
+template <int NT>
+__device__ void bcgs2_waves(double* Z, int ldz, int n, int k) {
+  constexpr int NW = NT / 64, SL = 4;
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  for (int m0 = 0; m0 < k; m0 += NW) {
+    const int b = k - m0 < NW ? k - m0 : NW;
+    const bool mine = wave < b;
+    double* zj = Z + (long long)(m0 + (mine ? wave : 0)) * ldz;
+    double z[SL];
 #pragma unroll
-        for (int s = 0; s < SL; ++s) {
-          const int r = lane + 64 * s;
-          z[s] = r < n ? zj[r] : 0.0;
-        }
-        double t0 = 0.0;
+    for (int s = 0; s < SL; ++s) {
+      const int r = lane + 64 * s;
+      z[s] = (mine && r < n) ? zj[r] : 0.0;
+    }
+    if (mine && m0 > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int q0 = 0; q0 < m0; q0 += 8) {
+          double zq[8][SL], t[8], d[8];
 #pragma unroll
-        for (int s = 0; s < SL; ++s) t0 += z[s] * z[s];
-        const double nb2 = wave_sum(t0);
-        for (int pass = 0; pass < 2 && j > 0; ++pass) {
-          double t8[8], d[8];
+          for (int qq = 0; qq < 8; ++qq) {
+            const double* col = Z + (long long)(q0 + qq) * ldz;
+            t[qq] = 0.0;
 #pragma unroll
-          for (int jj = 0; jj < 8; ++jj) {
-            double t = 0.0;
-            if (jj < j) {
-              const double* zq = Z + (long long)(m0 + jj) * ldz;
-#pragma unroll
-              for (int s = 0; s < SL; ++s) {
-                const int r = lane + 64 * s;
-                if (r < n) t += zq[r] * z[s];
-              }
+            for (int s = 0; s < SL; ++s) {
+              const int r = lane + 64 * s;
+              zq[qq][s] = (q0 + qq < m0 && r < n) ? col[r] : 0.0;
+              t[qq] += zq[qq][s] * z[s];
             }
-            t8[jj] = t;
           }
-          wave_sum8(t8, d);
+          wave_sum8(t, d);
 #pragma unroll
-          for (int jj = 0; jj < 8; ++jj) {
-            if (jj < j) {
-              const double* zq = Z + (long long)(m0 + jj) * ldz;
+          for (int qq = 0; qq < 8; ++qq)
 #pragma unroll
-              for (int s = 0; s < SL; ++s) {
-                const int r = lane + 64 * s;
-                if (r < n) z[s] -= d[jj] * zq[r];
-              }
-            }
-          }
+            for (int s = 0; s < SL; ++s) z[s] -= d[qq] * zq[qq][s];
         }
-        double t = 0.0;
+      }
+    }
+    double nb2 = 0.0;
+    if (mine) {
+      double t0 = 0.0;
 #pragma unroll
-        for (int s = 0; s < SL; ++s) t += z[s] * z[s];
-        double nrm2 = wave_sum(t);
+      for (int s = 0; s < SL; ++s) t0 += z[s] * z[s];
+      nb2 = wave_sum(t0);
+    }
+    for (int t = 0; t < b; ++t) {
+      if (wave == t) {
+        double t1 = 0.0;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) t1 += z[s] * z[s];
+        double nrm2 = wave_sum(t1);
         if (nrm2 < 0.25 * nb2) {
-          // the vector was nearly dependent on the block's earlier members:
-          // what is left is rounding noise that still leans on the earlier
-          // blocks, so it is re-orthogonalised against every earlier vector,
-          // twice, before it is normalised
+          // nearly dependent on the block's earlier members: what is left is
+          // rounding noise that still leans on earlier vectors
           for (int pass = 0; pass < 2; ++pass)
-            for (int q = 0; q < m0 + j; ++q) {
+            for (int q = 0; q < m0 + t; ++q) {
               const double* zq = Z + (long long)q * ldz;
               double u = 0.0;
 #pragma unroll
@@ -435,22 +540,40 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
                 if (r < n) z[s] -= dq * zq[r];
               }
             }
-          t = 0.0;
+          t1 = 0.0;
 #pragma unroll
-          for (int s = 0; s < SL; ++s) t += z[s] * z[s];
-          nrm2 = wave_sum(t);
+          for (int s = 0; s < SL; ++s) t1 += z[s] * z[s];
+          nrm2 = wave_sum(t1);
         }
         const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
           const int r = lane + 64 * s;
-          if (r < n) zj[r] = z[s] * inv;
+          z[s] *= inv;
+          if (r < n) zj[r] = z[s];
+        }
+      }
+      __syncthreads();
+      if (mine && wave > t) {
+        const double* qt = Z + (long long)(m0 + t) * ldz;
+        double qv[SL];
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+          const int r = lane + 64 * s;
+          qv[s] = r < n ? qt[r] : 0.0;
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+          double u = 0.0;
+#pragma unroll
+          for (int s = 0; s < SL; ++s) u += qv[s] * z[s];
+          const double dq = wave_sum(u);
+#pragma unroll
+          for (int s = 0; s < SL; ++s) z[s] -= dq * qv[s];
         }
       }
     }
-    __syncthreads();
-    m0 += b;
   }
+  __syncthreads();
 }
 
 }  // namespace
@@ -709,7 +832,10 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
 
   // 5. Gram-Schmidt with re-orthogonalisation over all kept vectors, in
   // blocks (coefficients in the contiguous pv | ybuf region of LDS)
-  bcgs2<NT, SL>(Z, ldz, n, k, pv, dv + NT);
+  if constexpr (SL == 4 && NW >= 4)
+    bcgs2_waves<NT>(Z, ldz, n, k);
+  else
+    bcgs2<NT, SL>(Z, ldz, n, k, pv, dv + NT);
 
   // 6. back-transformation: z <- H_0 ... H_{n-3} z, VB vectors per wave
   // (eight with four row slots: their dot products share one batched wave sum)
