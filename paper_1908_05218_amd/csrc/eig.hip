@@ -7,30 +7,36 @@
 // One workgroup per cluster (NT = 64..512 lanes chosen from the padded
 // dimension D <= 1024; each lane holds up to SL = 4, 8 or 16 rows of a column,
 // so one wave covers a whole column), FP64 throughout:
-//   1. gather the live rows/columns (the children's actual ranks) into a
-//      packed lower triangle: in LDS for n <= kEigLdsN, else in the cluster's
-//      scratch;
-//   2. Householder reduction to tridiagonal form.  Per step the symmetric
-//      product p = 2 A u is split over waves (each row's column range in
-//      contiguous chunks, loads pipelined); the rank-2 update runs lanes over
-//      rows of one column at a time.  Finished reflectors go to the cluster's
-//      scratch, which frees the LDS for the eigenvectors;
-//   3. lambda_1 by block-wide multisection of Sturm counts, the kept count k
-//      by one Sturm count at the threshold, then the k leading eigenvalues
-//      by grouped multisection (G lanes and two interleaved Sturm sequences
-//      per eigenvalue);
+//   1. gather the live rows/columns (the children's actual ranks; only the
+//      Gram's lower triangle is read);
+//   2. Householder reduction to tridiagonal form.  Up to D = 256 the matrix
+//      stays in registers (kernel k_eig_tri_reg: block lower triangle spread
+//      over the waves by columns, transposed terms of the symmetric product
+//      summed by a lane-swap butterfly, three barriers per step).  Above, a
+//      packed lower triangle in LDS (n <= kEigLdsN) or in the cluster's
+//      scratch: the symmetric product split over waves, the rank-2 update
+//      by lanes over rows of one column at a time.  Finished reflectors go to
+//      the cluster's scratch;
+//   3. lambda_1 by multisection of Sturm counts, the kept count k by one
+//      Sturm count at the threshold, then the k leading eigenvalues by
+//      grouped multisection (G lanes and two interleaved Sturm sequences per
+//      eigenvalue, G chosen for the fewest waves per SIMD x iterations);
 //   4. eigenvectors of the tridiagonal matrix by two steps of inverse
 //      iteration per lane (Gaussian elimination with partial pivoting fused
 //      with the forward sweep of the right-hand side); eigenvalues closer than
 //      1e-12 ||T|| are handled as clusters (fresh start, orthogonalisation
 //      against the earlier members between solves);
-//   5. block classical Gram-Schmidt with one re-orthogonalisation over all
-//      kept vectors, in descending eigenvalue order (blocks of 8 projected
-//      by the workgroup, orthonormalised inside by one wave);
+//   5. block Gram-Schmidt with one re-orthogonalisation over all kept
+//      vectors, in descending eigenvalue order.  Up to D = 256 each wave
+//      holds one vector of a block in registers and projects it out of the
+//      earlier blocks eight vectors at a time, then the waves orthonormalise
+//      inside the block in turn; above, blocks of 8 projected by the
+//      workgroup and orthonormalised inside by one wave;
 //   6. back-transformation by the reflectors, one wave per eight (four, two
 //      for the largest dimensions) vectors held in registers, and scatter to
 //      the padded row layout.
-// Wave reductions use DPP row operations and lane reads, not LDS permutes.
+// Wave reductions use DPP row operations, lane-half swaps and lane reads,
+// not LDS permutes.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -411,7 +417,8 @@ __device__ void orth_block(double* Z, int ldz, int n, int m0, int b) {
 }
 
 // Block classical Gram-Schmidt with re-orthogonalisation over the k kept
-// vectors (columns of Z, leading dimension ldz), in blocks of at most 8:
+// vectors (columns of Z, leading dimension ldz), in blocks of at most 8 (the
+// path for dimensions above 256 and for workgroups of fewer than four waves):
 // two passes project a block on all earlier vectors (whole workgroup), then
 // wave 0 orthonormalises inside the block (each vector twice against the
 // block's earlier members; a vector that loses more than half its norm there
@@ -1312,12 +1319,18 @@ __global__ __launch_bounds__(NT) void k_eig_val(EigArgs p0, EigArgs p1, int dv) 
   if (p.exact) {
     k = n;
   } else {
-    // lambda_1 by multisection over the whole workgroup
+    // lambda_1 by multisection over the first NP lanes (at most two waves:
+    // the Sturm counts are issue-bound, so one wave per SIMD and a few more
+    // iterations beat more points per iteration)
+    constexpr int NP = NT < 128 ? NT : 128;
     double lo = gl, hi = gu;
     for (int it = 0; it < 64 && hi - lo > tol; ++it) {
       const double h = hi - lo;
-      const double x = lo + h * (double)(tid + 1) / (double)(NT + 1);
-      const int below = sturm1(dd, e2, n, x, pivmin) < n;
+      int below = 0;
+      if (tid < NP) {
+        const double x = lo + h * (double)(tid + 1) / (double)(NP + 1);
+        below = sturm1(dd, e2, n, x, pivmin) < n;
+      }
       const int wc = __popcll(__ballot(below));
       __syncthreads();
       if (lane == 0) red[wave] = (double)wc;
@@ -1325,8 +1338,8 @@ __global__ __launch_bounds__(NT) void k_eig_val(EigArgs p0, EigArgs p1, int dv) 
       int cnt = 0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) cnt += (int)red[w];
-      const double nlo = cnt > 0 ? lo + h * (double)cnt / (double)(NT + 1) : lo;
-      const double nhi = cnt < NT ? lo + h * (double)(cnt + 1) / (double)(NT + 1) : hi;
+      const double nlo = cnt > 0 ? lo + h * (double)cnt / (double)(NP + 1) : lo;
+      const double nhi = cnt < NP ? lo + h * (double)(cnt + 1) / (double)(NP + 1) : hi;
       lo = nlo;
       hi = nhi;
     }
@@ -1341,13 +1354,26 @@ __global__ __launch_bounds__(NT) void k_eig_val(EigArgs p0, EigArgs p1, int dv) 
       lo0 = fmin(thr, lo) - tol;
     }
   }
-  // the k leading eigenvalues by grouped multisection
+  // the k leading eigenvalues by grouped multisection: G lanes per
+  // eigenvalue, two points each.  The Sturm counts are issue-bound, so G
+  // minimises (waves per SIMD) x (iterations) rather than the iterations
   {
-    int G = 8;
-    while (G > 1 && G * k > NT) G >>= 1;
-    const int Q = 2 * G;
     const double span = hi0 - lo0;
-    int R = span > tol ? (int)ceil(log2(span / tol) / log2((double)(Q + 1))) : 0;
+    const double bits = span > tol ? log2(span / tol) : 0.0;
+    int G = 1;
+    double best = 1e300;
+    for (int g = 1; g <= 8; g *= 2) {
+      if (g > 1 && g * k > NT) break;
+      const int waves = (g * k + 63) / 64;
+      const int per_simd = (waves + 3) / 4;
+      const double cost = (double)per_simd * ceil(bits / log2((double)(2 * g + 1)));
+      if (cost < best) {
+        best = cost;
+        G = g;
+      }
+    }
+    const int Q = 2 * G;
+    int R = span > tol ? (int)ceil(bits / log2((double)(Q + 1))) : 0;
     R = R > 200 ? 200 : R;
     const int jl = tid % G;
     for (int g = tid / G; g < k; g += NT / G) {
