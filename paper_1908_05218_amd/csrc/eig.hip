@@ -202,7 +202,9 @@ __device__ __forceinline__ double start_vec(int r, int m) {
 // swept right-hand side are kept interleaved by m in F[0..3] (stride fs) for
 // the backward sweep.  b is the start vector of seed `seed` (fresh) or zm
 // itself; x overwrites zm and is normalised.  Near-singular pivots are
-// clamped to +-tiny; a growing solution is rescaled before it can overflow.
+// clamped to +-tiny (one hardware reciprocal refined by Newton steps serves
+// both the multiplier and the stored reciprocal pivot); a growing solution is
+// rescaled before it can overflow.
 __device__ void invit_solve(const double* dd, const double* ee, int n, double lm, double tiny,
                             double* F0, double* F1, double* F2, double* F3, int fs, int m,
                             double* zm, bool fresh, int seed) {
@@ -214,29 +216,30 @@ __device__ void invit_solve(const double* dd, const double* ee, int n, double lm
     const double dn = dd[i + 1] - lm;
     const double un = i < n - 2 ? ee[i + 1] : 0.0;
     const double bn = fresh ? start_vec(i + 1, seed) : zm[i + 1];
-    double piv, u1, u2, y;
+    double rp, u1, u2, y;  // rp: reciprocal of the pivot
     if (fabs(di) >= fabs(li)) {
       if (fabs(di) < tiny) di = di < 0.0 ? -tiny : tiny;
-      piv = di;
+      rp = recip(di);
       u1 = ui;
       u2 = 0.0;
       y = bi;
-      const double f = li / di;
+      const double f = li * rp;
       di = dn - f * ui;
       ui = un;
       bi = bn - f * bi;
     } else {
-      piv = li;
+      const double lp = fabs(li) < tiny ? (li < 0.0 ? -tiny : tiny) : li;
+      rp = recip(lp);
       u1 = dn;
       u2 = un;
       y = bn;
-      const double f = di / li;
+      const double f = di * rp;
       di = ui - f * dn;
       ui = -f * un;
       bi = bi - f * bn;
     }
     const long long o = (long long)i * fs + m;
-    F0[o] = 1.0 / piv;
+    F0[o] = rp;
     F1[o] = u1;
     F2[o] = u2;
     F3[o] = y;
@@ -806,7 +809,8 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
   double* F1 = S + 2 * DD;
   double* F2 = S + 3 * DD;
   double* F3 = S + 4 * DD;
-  const double tiny = 1e-16 * fmax(bnd, 1e-300);
+  // pivot floor, kept in the normal range so that reciprocals stay finite
+  const double tiny = 1e-16 * fmax(bnd, 1e-270);
   for (int m = tid; m < k; m += NT) {
     double* zm = Z + (long long)m * ldz;
     invit_solve(dd, ee, n, lam[m], tiny, F0, F1, F2, F3, D, m, zm, true, m);

@@ -272,8 +272,27 @@ __global__ __launch_bounds__(256) void k_gram_norm(GramNormArgs p) {
 
 template <typename Tin, typename Tout>
 __global__ void k_convert(const Tin* in, Tout* out, long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (Tout)in[i];
+  // four elements per thread (16-byte float and 2 x 16-byte double accesses;
+  // the pool's buffers are 256-byte aligned), a scalar tail for the rest
+  const long long i = 4 * ((long long)blockIdx.x * blockDim.x + threadIdx.x);
+  if (i + 3 < n) {
+    Tin v[4];
+    if constexpr (sizeof(Tin) == 4) {
+      const float4 f = *(const float4*)(in + i);
+      v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+    } else {
+      const double2 a = *(const double2*)(in + i), b = *(const double2*)(in + i + 2);
+      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+    if constexpr (sizeof(Tout) == 4) {
+      *(float4*)(out + i) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    } else {
+      *(double2*)(out + i) = make_double2((double)v[0], (double)v[1]);
+      *(double2*)(out + i + 2) = make_double2((double)v[2], (double)v[3]);
+    }
+  } else {
+    for (long long j = i; j < n; ++j) out[j] = (Tout)in[j];
+  }
 }
 
 __global__ void k_fill(double* p, double v, long long n) {
@@ -403,13 +422,13 @@ hipError_t launch_fill_f(float* p, float v, long long n, hipStream_t s) {
 
 hipError_t launch_d2f(const double* in, float* out, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_convert<double, float>), dim3(cdiv(n, 256)), dim3(256), 0, s, in, out, n);
+  hipLaunchKernelGGL((k_convert<double, float>), dim3(cdiv(n, 1024)), dim3(256), 0, s, in, out, n);
   return hipGetLastError();
 }
 
 hipError_t launch_f2d(const float* in, double* out, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_convert<float, double>), dim3(cdiv(n, 256)), dim3(256), 0, s, in, out, n);
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(cdiv(n, 1024)), dim3(256), 0, s, in, out, n);
   return hipGetLastError();
 }
 
