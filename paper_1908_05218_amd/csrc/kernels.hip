@@ -36,6 +36,18 @@ __device__ __forceinline__ long long opnd_off(const Opnd& o, int v, int& sel) {
          ((v & 2) ? o.sub_c : 0LL);
 }
 
+// 64-bit exchange between odd and even rows of 16 lanes: afterwards x holds
+// x's and y's values of the even rows (x's in the even rows, y's in the odd
+// ones), y those of the odd rows (x's in the even rows, y's in the odd ones)
+__device__ __forceinline__ void swap_rows16(double& x, double& y) {
+  const unsigned long long xb = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long yb = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)xb, (unsigned)yb, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
 template <typename T>
 struct Mfma;
 
@@ -180,13 +192,73 @@ __device__ __forceinline__ void bgemm_body(const BgemmArgs<T>& p) {
     __syncthreads();
   }
   const int ov = p.out_idx[o];
-  T* Cb = (T*)p.C + ((long long)(ov >> 3) * p.cstride + ((ov & 1) ? p.csub_r : 0LL) +
-                     ((ov & 2) ? p.csub_c : 0LL));
+  const long long coff = (long long)(ov >> 3) * p.cstride + ((ov & 1) ? p.csub_r : 0LL) +
+                         ((ov & 2) ? p.csub_c : 0LL);
+  T* Cb = (T*)p.C + coff;
+  // FP32: a lane holds four consecutive rows of one column, written as one
+  // 16-byte access where the output's rows and columns keep that alignment.
+  // FP64: a lane holds rows r, r+4, r+8, r+12 (r = lane / 16); two swaps with
+  // the neighbouring 16-lane group leave it two pairs of adjacent rows, each
+  // written as one 16-byte access
+  const bool vec4 = sizeof(T) == 4 && ((coff | p.ldc | row0) & 3) == 0 &&
+                    (((uintptr_t)p.C) & 15) == 0;
+  const bool vec2 = sizeof(T) == 8 && ((coff | p.ldc | row0) & 1) == 0 &&
+                    (((uintptr_t)p.C) & 15) == 0;
 #pragma unroll
   for (int a = 0; a < SM; ++a)
 #pragma unroll
     for (int b = 0; b < SN; ++b) {
       const int gj = col0 + wc + b * 16 + (lane & 15);
+      if constexpr (sizeof(T) == 8) {
+        if (vec2) {
+          double x0 = acc[a][b][0], x1 = acc[a][b][1], x2 = acc[a][b][2], x3 = acc[a][b][3];
+          swap_rows16(x0, x1);  // rows base, base + 1
+          swap_rows16(x2, x3);  // rows base + 8, base + 9
+          const int g = lane >> 4;
+          const int gi = row0 + wr + a * 16 + (g & 1) * 4 + (g >> 1) * 2;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int r = gi + 8 * h;
+            const double e0 = (double)p.alpha * (h ? x2 : x0), e1 = (double)p.alpha * (h ? x3 : x1);
+            if (gj < p.n && r + 1 < p.m) {
+              double2* c = (double2*)(Cb + r + (long long)gj * p.ldc);
+              double2 val = make_double2(e0, e1);
+              if (p.beta != (T)0) {
+                const double2 old = *c;
+                val.x += (double)p.beta * old.x;
+                val.y += (double)p.beta * old.y;
+              }
+              *c = val;
+            } else if (gj < p.n) {
+              for (int q = 0; q < 2; ++q) {
+                if (r + q < p.m) {
+                  T* c = Cb + r + q + (long long)gj * p.ldc;
+                  T val = q ? e1 : e0;
+                  if (p.beta != (T)0) val += p.beta * (*c);
+                  *c = val;
+                }
+              }
+            }
+          }
+          continue;
+        }
+      }
+      const int gi0 = row0 + wr + a * 16 + Mfma<T>::row(lane, 0);
+      if (vec4 && gi0 + 3 < p.m && gj < p.n) {
+        float4* c = (float4*)(Cb + gi0 + (long long)gj * p.ldc);
+        float4 val = make_float4((float)(p.alpha * acc[a][b][0]), (float)(p.alpha * acc[a][b][1]),
+                                 (float)(p.alpha * acc[a][b][2]), (float)(p.alpha * acc[a][b][3]));
+        if (p.beta != (T)0) {
+          const float4 old = *c;
+          const float bt = (float)p.beta;
+          val.x += bt * old.x;
+          val.y += bt * old.y;
+          val.z += bt * old.z;
+          val.w += bt * old.w;
+        }
+        *c = val;
+        continue;
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gi = row0 + wr + a * 16 + Mfma<T>::row(lane, v);
