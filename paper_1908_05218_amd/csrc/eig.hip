@@ -1049,9 +1049,11 @@ __device__ __forceinline__ double butterfly16(const double* t, int lane) {
   return v;
 }
 
-template <int NW>
+// RS: 64-row slots per lane (NW / 2 for four and eight waves, fewer when the
+// dimension allows: three for D <= 192 with eight waves)
+template <int NW, int RS>
 __global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1, int dv) {
-  constexpr int NT = NW * 64, RS = NW >= 4 ? NW / 2 : 1, J = kRegCols, RM = 64 * RS;
+  constexpr int NT = NW * 64, J = kRegCols, RM = 64 * RS;
   // a group of 16 columns has cross-block (transposed) terms when its first
   // column's block is not the last one
   constexpr int NG = RS > 1 ? (diag_slot<NW>(16) < RS - 1 ? 2 : 1) : 0;
@@ -1065,7 +1067,7 @@ __global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1,
   const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   double* Uc = p.U + (long long)v.c * p.ustride;
   for (long long e = tid; e < (long long)v.D * v.D; e += NT) Uc[e] = 0.0;
-  if (!v.ok || v.D > dv || v.n > NW * J) {
+  if (!v.ok || v.D > dv || v.n > NW * J || v.n > RM) {
     if (tid == 0) {
       p.rank[v.c] = 0;
       if (v.n != 0) p.status[1] = 1;
@@ -1185,10 +1187,11 @@ __global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1,
           for (int q = 8 * h; q < 8 * h + 8; ++q) {
             const int j = 16 * g + q;
             const int sd = diag_slot<NW>(j);
+            t[q] = 0.0;
+            if (sd >= RS) continue;  // a column past the last row slot (folded away)
             const double uc = read_lane(u[sd], (wl + NW * j) & 63);
 #pragma unroll
             for (int s = sd; s < RS; ++s) y[s] += a[j][s] * uc;
-            t[q] = 0.0;
 #pragma unroll
             for (int s = sd + 1; s < RS; ++s) t[q] += a[j][s] * u[s];
           }
@@ -1208,7 +1211,7 @@ __global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1,
 #pragma unroll
     for (int s = 0; s < RS; ++s) ypart[w][lane + 64 * s] = y[s];
     __syncthreads();
-    if (lane < 32) {
+    if (lane < 32 && 32 * w + lane < RM) {
       const int r = 32 * w + lane;
       double acc = 0.0;
       // rows of the last block receive no transposed terms
@@ -1238,6 +1241,7 @@ __global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1,
 #pragma unroll
         for (int j = jb; j < jb + 8; ++j) {
           const int sd = diag_slot<NW>(j);
+          if (sd >= RS) continue;  // a column past the last row slot (folded away)
           const int lc = (wl + NW * j) & 63;
           const double uc = read_lane(u[sd], lc), wc = read_lane(wv[sd], lc);
 #pragma unroll
@@ -1476,7 +1480,7 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
     // kernels with dynamic LDS (the register-resident tridiagonalisation has
     // only static LDS and keeps the default)
     const void* tri = nullptr;
-    if constexpr (SL != 4) tri = (const void*)k_eig_tri<NT, SL>;
+    if constexpr (SL != 4) tri = (const void*)k_eig_tri<NT, SL>;  // the others use static LDS only
     for (const void* f : {tri, (const void*)k_eig_val<NT>, (const void*)k_eig_vec<NT, SL, true>,
                           (const void*)k_eig_vec<NT, SL, false>}) {
       if (!f) continue;
@@ -1487,9 +1491,17 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
   }
   const dim3 grid(nclusters, 2);
   const int zt = tri_zr(D, NT), zv = vec_zr(D, NT);
-  if constexpr (SL == 4)  // dimensions up to 4 x 64: the triangle in registers
-    hipLaunchKernelGGL((k_eig_tri_reg<NT / 64>), grid, dim3(NT), 0, s, a, b, D);
-  else
+  if constexpr (SL == 4) {  // dimensions up to 4 x 64: the triangle in registers
+    constexpr int NW = NT / 64, RS = NW >= 4 ? NW / 2 : 1;
+    bool done = false;
+    if constexpr (NW == 8) {
+      if (D <= 192) {
+        hipLaunchKernelGGL((k_eig_tri_reg<8, 3>), grid, dim3(NT), 0, s, a, b, D);
+        done = true;
+      }
+    }
+    if (!done) hipLaunchKernelGGL((k_eig_tri_reg<NW, RS>), grid, dim3(NT), 0, s, a, b, D);
+  } else
     hipLaunchKernelGGL((k_eig_tri<NT, SL>), grid, dim3(NT),
                        sizeof(double) * ((size_t)zt + 3 * D + partials_len(D, NT) + kRed), s, a, b,
                        zt, D);
