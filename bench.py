@@ -288,8 +288,8 @@ def main():
                           "copies": 3}))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import paper_1908_05218_amd as h2
