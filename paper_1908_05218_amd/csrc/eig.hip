@@ -5,8 +5,8 @@
 // kept count follows from the truncation threshold tau * lambda_1.
 //
 // One workgroup per cluster (NT = 64..512 lanes chosen from the padded
-// dimension D <= 1024; each lane holds up to SL = 4, 8 or 16 rows of a column,
-// so one wave covers a whole column), FP64 throughout:
+// dimension D <= 1024; each lane holds SL = 1, 2, 4, 8 or 16 rows of a column,
+// as many as D needs, so one wave covers a whole column), FP64 throughout:
 //   1. gather the live rows/columns (the children's actual ranks; only the
 //      Gram's lower triangle is read);
 //   2. Householder reduction to tridiagonal form.  Up to D = 256 the matrix
@@ -481,9 +481,9 @@ __device__ void bcgs2(double* Z, int ldz, int n, int k, double* Dc, int cap) {
 // re-orthogonalising it twice against every earlier vector if it kept less
 // than half its norm) and stores it, and each later wave projects it out,
 // twice.
-template <int NT>
+template <int NT, int SL>
 __device__ void bcgs2_waves(double* Z, int ldz, int n, int k) {
-  constexpr int NW = NT / 64, SL = 4;
+  constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = wave_id();
   for (int m0 = 0; m0 < k; m0 += NW) {
     const int b = k - m0 < NW ? k - m0 : NW;
@@ -843,8 +843,8 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
 
   // 5. Gram-Schmidt with re-orthogonalisation over all kept vectors, in
   // blocks (coefficients in the contiguous pv | ybuf region of LDS)
-  if constexpr (SL == 4 && NW >= 4)
-    bcgs2_waves<NT>(Z, ldz, n, k);
+  if constexpr (SL <= 4 && NW >= 4)
+    bcgs2_waves<NT, SL>(Z, ldz, n, k);
   else
     bcgs2<NT, SL>(Z, ldz, n, k, pv, dv + NT);
 
@@ -1480,7 +1480,7 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
     // kernels with dynamic LDS (the register-resident tridiagonalisation has
     // only static LDS and keeps the default)
     const void* tri = nullptr;
-    if constexpr (SL != 4) tri = (const void*)k_eig_tri<NT, SL>;  // the others use static LDS only
+    if constexpr (SL > 4) tri = (const void*)k_eig_tri<NT, SL>;  // the others use static LDS only
     for (const void* f : {tri, (const void*)k_eig_val<NT>, (const void*)k_eig_vec<NT, SL, true>,
                           (const void*)k_eig_vec<NT, SL, false>}) {
       if (!f) continue;
@@ -1491,7 +1491,7 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
   }
   const dim3 grid(nclusters, 2);
   const int zt = tri_zr(D, NT), zv = vec_zr(D, NT);
-  if constexpr (SL == 4) {  // dimensions up to 4 x 64: the triangle in registers
+  if constexpr (SL <= 4) {  // dimensions up to 4 x 64: the triangle in registers
     constexpr int NW = NT / 64, RS = NW >= 4 ? NW / 2 : 1;
     bool done = false;
     if constexpr (NW == 8) {
@@ -1526,9 +1526,11 @@ hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStre
   if (D > 512) return launch_nt<512, 16>(a, b, nclusters, D, s);
   if (D > 256) return launch_nt<512, 8>(a, b, nclusters, D, s);
   switch (eig_threads(D)) {
-    case 64: return launch_nt<64, 4>(a, b, nclusters, D, s);
-    case 128: return launch_nt<128, 4>(a, b, nclusters, D, s);
-    case 256: return launch_nt<256, 4>(a, b, nclusters, D, s);
+    // row slots per lane: as many as the dimension needs (fewer registers
+    // and no padding work in the eigenvector phases)
+    case 64: return launch_nt<64, 1>(a, b, nclusters, D, s);
+    case 128: return launch_nt<128, 1>(a, b, nclusters, D, s);
+    case 256: return launch_nt<256, 2>(a, b, nclusters, D, s);
     default: return launch_nt<512, 4>(a, b, nclusters, D, s);
   }
 }
