@@ -1,7 +1,7 @@
 """Construction of the input H^2 matrices.
 
 The paper builds its inputs with a method it cites but does not describe
-(Section V); these inputs stand in for them.  Two families:
+(Section VI); these inputs stand in for them.  Two families:
 
   * `chebyshev_h2`: kernel matrices with nested tensor Chebyshev
     interpolation bases.  Each cluster gets first-kind Chebyshev nodes of

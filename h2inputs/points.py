@@ -1,7 +1,7 @@
 """Seeded synthetic point clouds shaped like the paper's workloads.
 
 The paper measures on capacitance-extraction and volume-integral-equation
-matrices (Section V) that are not available here; these generators give
+matrices (Section VI) that are not available here; these generators give
 point sets of the same families (a 3-D volume, two parallel plates, a
 closed surface) from which kernel matrices of the same character are built.
 Every generator takes an explicit seed and is deterministic.

@@ -1,6 +1,6 @@
 """Exact operations on an H^2 matrix: expansion to dense and the matrix-vector
 product (the exact H^2 mat-vec the accuracy criterion, equation `error` of
-Section V, relies on).  FP64 / complex128, plain NumPy.
+Section VI, relies on).  FP64 / complex128, plain NumPy.
 
 Part of the CPU checker: test infrastructure only.
 """

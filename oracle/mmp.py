@@ -29,14 +29,27 @@ Plain FP64 / complex128 NumPy, one block at a time, in the paper's order:
   8. a top-down split of the couplings attached to non-leaf blocks into the
      admissible and dense blocks below them (end of Section IV).
 
+FIXED mode is the fixed-basis ("formatted") product the paper compares
+against (Section I; Table IV, "existing" row): C keeps the row bases of A and
+the column bases of B, orthonormalised (each new basis is the numerical
+range of the third Gram component alone, eigenvalues above 1e-12 lambda_1),
+so no contribution changes the bases and the error of C is not controlled
+by eps (which FIXED mode ignores); every other step is the same.
+
 Readings of points the paper leaves open (each also listed in the design
 notes): "normalize" divides a Gram sum by its trace and skips empty sums;
 "normalized singular values greater than eps" keeps eigenvalues with
 lambda_m > tau * lambda_1 where tau = eps in PAPER mode (the Gram's own
 singular values, which reproduces the paper's error of about sqrt(eps)) and
-tau = (theta*eps)^2 with theta = 1 in ACCURACY mode (the default: singular
-values of the stacked normalised contributions above eps, aimed at
-||C - AB||_F <= eps ||AB||_F), at least one vector; EXACT mode keeps every eigenvector; the non-leaf column
+tau = (theta*eps/n_t)^2 in ACCURACY mode (the default, aimed at
+||C - AB||_F <= eps ||AB||_F): singular values of the stacked normalised
+contributions above theta*eps/n_t, where n_t = L - l_min + 1 is the number
+of levels whose bases are truncated.  Each level's truncation adds its own
+error to C and these errors add up over the levels (measured: the error at
+theta*eps per level grows about linearly with n_t), so the budget eps is
+split evenly over the levels; theta = 1 was fixed once by
+`calibrate_theta.py` on small members of each input family.  At least one
+vector is kept; EXACT mode keeps every eigenvector; the non-leaf column
 "original basis" term is Q Q^H with Q = diag(P^B_k'^T) T^B_K; blocks enter
 the case-1 Gram one product at a time at the leaf level and one merged
 target at a time above it; every dense (or non-leaf) block of A in a row
@@ -50,22 +63,32 @@ from h2inputs.h2data import H2Matrix
 from h2inputs.structure import R, F, NL
 
 BLUE = 3
-EXACT, ACCURACY, PAPER = "exact", "accuracy", "paper"
+EXACT, ACCURACY, PAPER, FIXED = "exact", "accuracy", "paper", "fixed"
 THETA = 1.0
+# FIXED mode: relative eigenvalue floor of the numerical rank of an old basis
+FIXED_TAU = 1e-12
 
 
 def _h(x):
     return x.conj().T
 
 
-def threshold(eps, mode, theta=THETA):
+def truncated_levels(L, lmin):
+    """Number of levels whose bases are truncated: the leaves and every
+    non-leaf level down to l_min."""
+    return max(1, L - lmin + 1)
+
+
+def threshold(eps, mode, theta=THETA, levels=1):
     """Relative eigenvalue threshold tau (lambda_m > tau * lambda_1 is kept)."""
     if mode == EXACT:
         return None
+    if mode == FIXED:
+        return FIXED_TAU
     if mode == PAPER:
         return float(eps)
     if mode == ACCURACY:
-        return float(theta * eps) ** 2
+        return float(theta * eps / levels) ** 2
     raise ValueError(mode)
 
 
@@ -173,13 +196,19 @@ def h2_mmp(A, B, eps, mode=ACCURACY, theta=THETA):
         raise ValueError("A and B must share the cluster tree and block partition")
     if eps < 0:
         raise ValueError("eps must be >= 0")
-    if eps == 0:
+    if eps == 0 and mode != FIXED:
         mode = EXACT
-    tau = threshold(eps, mode, theta)
+    fixed = mode == FIXED
+
+    def comps(c1, c2, c3):
+        """Gram components entering a new basis: all three, or in FIXED mode
+        only the old basis (whose span the new one then equals)."""
+        return [c3] if fixed else [c1, c2, c3]
     L = A.L
     T = A.tree
     sym = Symbolic(A.blocks)
     lmin = sym.lmin
+    tau = threshold(eps, mode, theta, truncated_levels(L, lmin))
     cdt = np.result_type(A.dtype, B.dtype)
 
     # ---- step 0: cluster-basis products Pi_j = (W^A_j)^T V^B_j
@@ -261,10 +290,10 @@ def h2_mmp(A, B, eps, mode=ACCURACY, theta=THETA):
     for c in range(nl):
         g3r = _Gram(T.size(L, c), cdt)
         g3r.add_row(A.V[c])
-        VC[c], _ = truncated_basis([g1r[c].comp(), g2r[c].comp(), g3r.comp()], tau)
+        VC[c], _ = truncated_basis(comps(g1r[c].comp(), g2r[c].comp(), g3r.comp()), tau)
         g3c = _Gram(T.size(L, c), cdt)
         g3c.add_row(B.W[c])          # enters as W^B_k (W^B_k)^H
-        WC[c], _ = truncated_basis([g1c[c].comp(), g2c[c].comp(), g3c.comp()], tau)
+        WC[c], _ = truncated_basis(comps(g1c[c].comp(), g2c[c].comp(), g3c.comp()), tau)
 
     # step 2: projections and collected blocks
     PA[L] = [_h(VC[i]) @ A.V[i] for i in range(nl)]
@@ -362,11 +391,11 @@ def h2_mmp(A, B, eps, mode=ACCURACY, theta=THETA):
         for c in range(ncl):
             g3r = _Gram(Kr[c], cdt)
             g3r.add_row(_blockdiag(PA[ch][2 * c], PA[ch][2 * c + 1]) @ stack2(A.Er, lev, c))
-            TCr[c], _ = truncated_basis([g1r[c].comp(), g2r[c].comp(), g3r.comp()], tau)
+            TCr[c], _ = truncated_basis(comps(g1r[c].comp(), g2r[c].comp(), g3r.comp()), tau)
             g3c = _Gram(Kc[c], cdt)
             Q = _blockdiag(PB[ch][2 * c].T, PB[ch][2 * c + 1].T) @ stack2(B.Ec, lev, c)
             g3c.add_row(Q)            # enters as Q Q^H
-            TCc[c], _ = truncated_basis([g1c[c].comp(), g2c[c].comp(), g3c.comp()], tau)
+            TCc[c], _ = truncated_basis(comps(g1c[c].comp(), g2c[c].comp(), g3c.comp()), tau)
             ErC[ch][2 * c] = TCr[c][:kr[2 * c]]
             ErC[ch][2 * c + 1] = TCr[c][kr[2 * c]:]
             EcC[ch][2 * c] = TCc[c][:kc[2 * c]]

@@ -12,7 +12,14 @@ independent of the checker's own formulas.
   * PAPER mode's error scales like sqrt(eps) (Tables I, II, IV);
   * C keeps the block partition of A and B (Section III);
   * the new bases are orthonormal; B = I gives C = A; A symmetric gives C
-    symmetric; smaller eps gives smaller error and larger ranks.
+    symmetric; smaller eps gives smaller error and larger ranks;
+  * scale invariance of the truncation (the normalisation of Section III-C
+    makes each Gram component independent of the scale of its blocks):
+    C(alpha A, B) = alpha C(A, B) with identical ranks;
+  * the column side mirrors the row side: C(B^T, A^T) = C(A, B)^T with the
+    row ranks of one equal to the column ranks of the other, for a real
+    non-symmetric product and a complex one (which decides the conjugations
+    of the column Grams, Section III-C and Section IV).
 """
 import numpy as np
 import pytest
@@ -232,3 +239,103 @@ def test_planted_swapped_children_is_caught(monkeypatch):
     orig = mmp._blockdiag
     monkeypatch.setattr(mmp, "_blockdiag", lambda a, b: orig(b, a))
     assert _exact_error(A, B) > 1e-6
+
+
+# ------------------------------------------------------------ scale and mirror
+def _flat(info, key):
+    return [r for lev, rr in enumerate(info[key]) if lev >= info["lmin"] for r in rr]
+
+
+@pytest.mark.parametrize("alpha", [2.0 ** 10, 2.0 ** -10])
+def test_scale_invariance(alpha):
+    """Powers of two scale every floating-point step exactly, so the kept
+    ranks must be identical and C must scale exactly."""
+    A = cases.plates(2048)
+    C, info = mmp.h2_mmp(A, A, 1e-4)
+    Cs, infos = mmp.h2_mmp(cases.scaled_h2(A, alpha), A, 1e-4)
+    assert infos["ranks_row"] == info["ranks_row"] and infos["ranks_col"] == info["ranks_col"]
+    assert rel(h2ops.to_dense(Cs), alpha * h2ops.to_dense(C)) < 1e-14
+
+
+def test_planted_missing_normalisation_is_caught(monkeypatch):
+    """Summing the Gram components without dividing by their traces must
+    break scale invariance."""
+    orig = mmp.truncated_basis
+    monkeypatch.setattr(mmp, "truncated_basis",
+                        lambda comps, tau: orig([(g, 1.0 if tr > 0 else 0.0) for g, tr in comps], tau))
+    A = cases.plates(2048)
+    _, info = mmp.h2_mmp(A, A, 1e-4)
+    _, infos = mmp.h2_mmp(cases.scaled_h2(A, 2.0 ** 10), A, 1e-4)
+    assert infos["ranks_row"] != info["ranks_row"]
+
+
+def _mirror(A, B, eps):
+    C, info = mmp.h2_mmp(A, B, eps)
+    Ct, infot = mmp.h2_mmp(cases.transpose_h2(B), cases.transpose_h2(A), eps)
+    D, Dt = h2ops.to_dense(C), h2ops.to_dense(Ct)
+    return rel(Dt, D.T), info, infot, D
+
+
+def test_transpose_mirror_real_nonsymmetric():
+    A, B = cases.plates_two_orders(2048)
+    err, info, infot, D = _mirror(A, B, 1e-4)
+    assert err < 1e-12
+    assert _flat(infot, "ranks_row") == _flat(info, "ranks_col")
+    assert _flat(infot, "ranks_col") == _flat(info, "ranks_row")
+    # the product really is non-symmetric, so the check is not vacuous
+    assert np.linalg.norm(D - D.T) > 1e3 * err * np.linalg.norm(D)
+    assert _flat(info, "ranks_row") != _flat(info, "ranks_col")
+
+
+def test_transpose_mirror_complex():
+    A, B = cases.helmholtz_sphere(1024, 32, 2, 20.0)
+    err, info, infot, D = _mirror(A, B, 1e-3)
+    assert err < 1e-12
+    assert _flat(infot, "ranks_row") == _flat(info, "ranks_col")
+    assert _flat(infot, "ranks_col") == _flat(info, "ranks_row")
+    assert np.linalg.norm(D - D.T) > 1e3 * err * np.linalg.norm(D)
+
+
+def test_planted_unconjugated_column_gram_is_caught(monkeypatch):
+    """A column Gram formed as Z^T Z (no conjugate) must break the complex
+    mirror."""
+    monkeypatch.setattr(mmp._Gram, "add_col",
+                        lambda self, Z: (self.G.__iadd__(Z.T @ Z),
+                                         setattr(self, "tr", self.tr + float(np.vdot(Z, Z).real))))
+    A, B = cases.helmholtz_sphere(1024, 32, 2, 20.0)
+    err, _, _, _ = _mirror(A, B, 1e-3)
+    assert err > 1e-8
+
+
+# ------------------------------------------------------------ fixed-basis mode
+def test_fixed_basis_times_identity_is_a():
+    """A I in fixed-basis mode: every contribution already lies in A's bases,
+    so the projections are exact."""
+    A = cases.plates(2048)
+    C, _ = mmp.h2_mmp(A, identity_h2(A), 0.0, mode=mmp.FIXED)
+    DA = h2ops.to_dense(A)
+    assert rel(h2ops.to_dense(C), DA) < 1e-11
+
+
+def test_fixed_basis_keeps_the_input_spans():
+    """The new row bases of C span A's row bases and the column bases span
+    B's, on every level from the leaves to l_min (nested bases expanded)."""
+    A, B = cases.plates_two_orders(2048)
+    C, info = mmp.h2_mmp(A, B, 0.0, mode=mmp.FIXED)
+    for lev in range(info["lmin"], A.L + 1):
+        for c in range(0, 1 << lev, max(1, (1 << lev) // 8)):
+            for exp, M, N in ((h2ops.expanded_row_basis, C, A), (h2ops.expanded_col_basis, C, B)):
+                Q, X = exp(M, lev, c), exp(N, lev, c)
+                assert Q.shape[1] == X.shape[1]
+                assert np.linalg.norm(X - Q @ (Q.conj().T @ X)) <= 1e-11 * np.linalg.norm(X)
+
+
+def test_fixed_basis_error_well_above_proposed():
+    """Table IV's claim on synthetic data: the fixed-basis product's error
+    is far above the proposed product's at eps = 1e-4."""
+    for A in (cases.plates(2048), cases.cube(2048)):
+        ref = h2ops.to_dense(A) @ h2ops.to_dense(A)
+        Cf, _ = mmp.h2_mmp(A, A, 0.0, mode=mmp.FIXED)
+        Ca, _ = mmp.h2_mmp(A, A, 1e-4)
+        ef, ea = rel(h2ops.to_dense(Cf), ref), rel(h2ops.to_dense(Ca), ref)
+        assert ef > 10 * ea and ea <= 1e-4, (ef, ea)
