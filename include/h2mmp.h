@@ -20,12 +20,18 @@
  *    the boundary: interleaved (real, imaginary) pairs in h2_load, h2_export
  *    and h2_to_dense; planar vectors (all real parts, then all imaginary
  *    parts) in h2_matvec.
- *  - All work runs on the context's own HIP stream (default priority); every
- *    entry point returns after that stream has finished its work.
+ *  - Device work runs on the context's own HIP stream (default priority).
+ *    h2_mmp and h2_matvec also take a caller stream: with a non-null stream
+ *    the call's work is ordered after the work queued on that stream before
+ *    the call, work queued on it after the call is ordered after the call's
+ *    work, and the call may return before its last kernels finish (h2_sync
+ *    waits for them).  With a null stream, and for every other entry point,
+ *    the call returns after its work has finished.
  */
 #ifndef H2MMP_H
 #define H2MMP_H
 
+#include <hip/hip_runtime_api.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -51,21 +57,52 @@ typedef struct h2_mat_s* h2_mat;
 /* Truncation rule for the eigenvalues lambda_1 >= lambda_2 ... of a cluster's
  * summed normalised Gram matrix (Section III-C "singular vectors whose
  * normalized singular values are greater than eps_trunc"):
- *  ACCURACY: keep lambda_m > eps^2 lambda_1 (normalised singular values of
- *            the stacked contributions above eps; aims at ||C-AB||_F <= eps ||AB||_F)
+ *  ACCURACY: keep lambda_m > (eps / n_t)^2 lambda_1, n_t = L - l_min + 1 the
+ *            number of levels whose bases are truncated (normalised singular
+ *            values of the stacked contributions above eps / n_t: the
+ *            budget eps split evenly over the levels, whose truncation
+ *            errors add up in C; aims at ||C-AB||_F <= eps ||AB||_F)
  *  PAPER:    keep lambda_m > eps lambda_1 (the Gram's own singular values)
- *  EXACT:    keep every eigenvector (no truncation; eps ignored) */
-typedef enum { H2_TRUNC_ACCURACY = 0, H2_TRUNC_PAPER = 1, H2_TRUNC_EXACT = 2 } h2_trunc_mode;
+ *  EXACT:    keep every eigenvector (no truncation; eps ignored)
+ *  FIXED:    the fixed-basis ("formatted") product the paper compares
+ *            against (Section I; Table IV): C keeps A's row bases and B's
+ *            column bases, orthonormalised (eigenvalues of the old basis'
+ *            Gram component alone above 1e-12 lambda_1); no contribution
+ *            changes a basis, so the error of C is not controlled (eps
+ *            ignored). */
+typedef enum {
+  H2_TRUNC_ACCURACY = 0,
+  H2_TRUNC_PAPER = 1,
+  H2_TRUNC_EXACT = 2,
+  H2_TRUNC_FIXED = 3
+} h2_trunc_mode;
 
 /* Arithmetic of the bulk products.  FP64: everything in double.
  * FP32_BULK: block products in float on the matrix cores, Gram sums,
  * eigen-decompositions and bases in double. */
 typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32_BULK = 1 } h2_precision;
 
+/* Device memory supplier of a context (e.g. a framework's caching
+ * allocator).  alloc returns `bytes` of device memory on `device` for work on
+ * `stream` (the context's stream), or NULL when it has none; free returns a
+ * block from alloc.  free may be called while work already queued on
+ * `stream` still reads the block: the allocator must not hand the block to
+ * work on another stream before that work has finished (a stream-ordered
+ * caching allocator does this).  Both may be called from the library's
+ * serving threads.  `user` is passed back unchanged. */
+typedef struct {
+  void* (*alloc)(void* user, size_t bytes, int device, hipStream_t stream);
+  void (*free)(void* user, void* ptr, size_t bytes, int device, hipStream_t stream);
+  void* user;
+} h2_allocator;
+
 /* Create a context on HIP device `device`.  hbm_budget (bytes) bounds the
- * device memory the context may hold; 0 means no bound.  Errors:
- * H2_ERR_DEVICE (no such device), H2_ERR_ARG (out == NULL). */
-h2_status h2_ctx_create(int device, size_t hbm_budget, h2_ctx* out);
+ * device memory the context may hold; 0 means no bound.  alloc (nullable,
+ * copied): the supplier of every device allocation of the context and of its
+ * serving slots; without one the context takes memory with hipMalloc and
+ * keeps freed blocks in a pool of its own.  Errors: H2_ERR_DEVICE (no such
+ * device), H2_ERR_ARG (out == NULL, or an allocator without alloc or free). */
+h2_status h2_ctx_create(int device, size_t hbm_budget, const h2_allocator* alloc, h2_ctx* out);
 void h2_ctx_destroy(h2_ctx ctx);
 
 /* Host description of an H^2 matrix in the flat interchange layout
@@ -107,7 +144,7 @@ h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out);
 /* Kernel of h2_build: H2_KERNEL_LAPLACE is 1/(4 pi r) (real), with
  * self_value where r = 0 (coincident points; e.g. the mean of 1/(4 pi r) over
  * a panel).  H2_KERNEL_HELMHOLTZ is exp(-j kappa r)/(4 pi r) with kappa =
- * wavenumber (complex128 matrix; the scattering kernel of Section V), with
+ * wavenumber (complex128 matrix; the scattering kernel of Section VI), with
  * self_value + j self_value_imag where r = 0. */
 typedef enum { H2_KERNEL_LAPLACE = 0, H2_KERNEL_HELMHOLTZ = 1 } h2_kernel_kind;
 typedef struct {
@@ -213,11 +250,20 @@ h2_status h2_release(h2_ctx ctx, uint64_t ticket);
  * a cluster (twice the children's padded rank) is at most 1024 (512 for
  * complex data, whose Hermitian Grams are solved through their real
  * embedding).
+ * stream: see the conventions above.  The call blocks the host once per
+ * level to read back the kept ranks (they size the next level's launches);
+ * the launches after the last level (the top-down split, the conversion of
+ * FP32-bulk results) may still run when it returns.
  * Errors: H2_ERR_STRUCTURE, H2_ERR_ARG (eps < 0, bad mode/precision),
  * H2_ERR_UNSUPPORTED (a cluster whose Gram dimension exceeds the on-chip
  * eigensolver limit, reported in the message), H2_ERR_OOM, H2_ERR_NUMERIC. */
 h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int precision,
-                 h2_mat* C_out);
+                 hipStream_t stream, h2_mat* C_out);
+
+/* Wait until every launch of the call that produced M (h2_mmp or
+ * h2_matvec into M's context) has finished.  Errors: H2_ERR_ARG (null),
+ * H2_ERR_DEVICE (a failed launch). */
+h2_status h2_sync(h2_mat M);
 
 /* y = M x for nrhs right-hand sides, x and y n x nrhs column-major in the
  * original point order, host memory (x_on_device = 0) or device memory
@@ -225,9 +271,11 @@ h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int
  * n x nrhs real parts followed by the n x nrhs imaginary parts (2 n nrhs
  * doubles).  Exact H^2 mat-vec: forward
  * transform up the column tree, couplings, backward transform down the row
- * tree, dense near field (the reference solution of equation `error`). */
+ * tree, dense near field (the reference solution of equation `error`).
+ * stream: see the conventions above (host vectors: the call always returns
+ * with y filled). */
 h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nrhs,
-                    int x_on_device);
+                    int x_on_device, hipStream_t stream);
 
 /* Dense M (original order) into host memory `out` (column-major, ld >= n;
  * complex M: interleaved pairs, ld in complex elements).  Only for
@@ -275,11 +323,17 @@ h2_status h2_load_file(h2_ctx ctx, const char* path, h2_mat* out);
 
 /* Statistics of the last h2_mmp that produced M (zeros for loaded
  * matrices).  rank_max/rank_mean per level for the row (r) and column (c)
- * bases; canonical flops of the block products (2 r1 r2 r3 per evaluated
- * block product at the actual ranks, Sections III-IV; Gram and eigensolver
- * work is not included), counted on the first h2_stats call for M by a host
- * pass over every evaluated block product; device time of the numeric phase in ms; the
- * triple-contraction kernels' summed device time and launch count. */
+ * bases; algorithmic work at the actual ranks (Sections III-IV), counted on
+ * the first h2_stats call for M by a host pass over every evaluated block
+ * product: flops_triple = one contraction per evaluated block product
+ * (2 n^3 for a dense target, 2 r1 r2 r3 in rank form otherwise),
+ * flops_target = the per-target products that apply the projections,
+ * flops_gram = 2 d^2 per column contributed to a Gram sum of dimension d,
+ * eig_flops = 9 d^3 per Gram matrix, flops = their sum (complex: four real
+ * products per complex one, eight for the eigen-decompositions of the real
+ * embedding); device time of the numeric phase in ms (waits for the product
+ * to finish); per kernel class (with h2_set_profiling on) summed device ms,
+ * launches and executed (padded) flops. */
 #define H2_MAX_LEVELS 40
 typedef struct {
   int64_t L, lmin;
@@ -290,6 +344,7 @@ typedef struct {
   double symbolic_ms;
   int64_t n_triples;
   int64_t sparsity_constant;
+  /* the per-triple contraction kernels (k_bgemm_triple) */
   double contraction_ms;
   int64_t contraction_launches;
   double contraction_flops;
@@ -298,14 +353,13 @@ typedef struct {
    * product (operands, the product and its temporaries; blocks cached by
    * the context's pool are not counted) */
   int64_t bytes_device;
-  /* per kernel class (with h2_set_profiling on): summed device ms and
-   * launches of the Gram-sum products and of all remaining batched products */
+  /* Gram-sum products, and all remaining batched products (projections,
+   * collects, per-target products, split) */
   double gram_ms, other_ms;
   int64_t eig_launches, gram_launches, other_launches;
-  double gram_flops, other_flops; /* executed (padded) flops of those launches */
-  /* algorithmic work of the eigen-decompositions: 9 d^3 per Gram matrix of
-   * dimension d (the children's actual ranks; leaf size at the leaves) */
+  double gram_flops, other_flops;
   double eig_flops;
+  double flops_triple, flops_target, flops_gram;
 } h2_stats_t;
 h2_status h2_stats(h2_mat M, h2_stats_t* out);
 

@@ -18,7 +18,7 @@ H2_ERR_BUSY = 8
 STATUS_NAMES = {0: "H2_OK", 1: "H2_ERR_ARG", 2: "H2_ERR_DEVICE", 3: "H2_ERR_OOM",
                 4: "H2_ERR_STRUCTURE", 5: "H2_ERR_NUMERIC", 6: "H2_ERR_UNSUPPORTED",
                 7: "H2_ERR_INTERNAL"}
-TRUNC = {"accuracy": 0, "paper": 1, "exact": 2}
+TRUNC = {"accuracy": 0, "paper": 1, "exact": 2, "fixed": 3}
 PREC = {"fp64": 0, "fp32_bulk": 1}
 MAX_LEVELS = 40
 
@@ -59,7 +59,9 @@ class _Stats(C.Structure):
                 ("bytes_device", C.c_int64), ("gram_ms", C.c_double), ("other_ms", C.c_double),
                 ("eig_launches", C.c_int64), ("gram_launches", C.c_int64),
                 ("other_launches", C.c_int64), ("gram_flops", C.c_double),
-                ("other_flops", C.c_double), ("eig_flops", C.c_double)]
+                ("other_flops", C.c_double), ("eig_flops", C.c_double),
+                ("flops_triple", C.c_double), ("flops_target", C.c_double),
+                ("flops_gram", C.c_double)]
 
 
 class _Kernel(C.Structure):
@@ -92,13 +94,22 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run paper_1908_05218_amd/build.py")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7,
+        # and whichever copy is loaded first serves both (same soname).  Load
+        # PyTorch's first, so that its streams and its caching allocator and
+        # the library's launches share one runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
-        L.h2_ctx_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(vp)]
+        L.h2_ctx_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(_Allocator), C.POINTER(vp)]
         L.h2_ctx_destroy.argtypes = [vp]
         L.h2_load.argtypes = [vp, C.POINTER(_HostMatrix), C.POINTER(vp)]
-        L.h2_mmp.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.c_int, C.POINTER(vp)]
-        L.h2_matvec.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int]
+        L.h2_mmp.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.c_int, vp, C.POINTER(vp)]
+        L.h2_matvec.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int, vp]
+        L.h2_sync.argtypes = [vp]
         L.h2_to_dense.argtypes = [vp, vp, vp, C.c_int64]
         L.h2_export_size.argtypes = [vp, C.POINTER(_ExportSizes)]
         L.h2_export.argtypes = [vp, C.POINTER(_ExportBuffers)]
@@ -120,7 +131,7 @@ def lib():
         for f in ("h2_ctx_create", "h2_load", "h2_build", "h2_submit", "h2_poll", "h2_wait",
                   "h2_release", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
                   "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling", "h2_serve_slots",
-                  "h2_save", "h2_load_file"):
+                  "h2_save", "h2_load_file", "h2_sync"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -141,10 +152,50 @@ def _ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+def _torch_alloc(user, nbytes, device, stream):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), int(device), int(stream or 0))
+    except RuntimeError:
+        return None
+
+
+def _torch_free(user, ptr, nbytes, device, stream):
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# kept alive for the lifetime of the module (the library holds the pointers)
+_TORCH_ALLOCATOR = _Allocator(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free), None)
+
+
+def _stream_handle(stream):
+    """hipStream_t of a torch stream, an integer handle, or None."""
+    if stream is None:
+        return None
+    h = getattr(stream, "cuda_stream", stream)
+    return C.c_void_p(int(h)) if int(h) else None
+
+
 class Context:
-    def __init__(self, device=0, hbm_budget=0):
+    """A library context on one device.  allocator="torch": every device
+    allocation of the context comes from PyTorch's caching allocator (on the
+    context's stream), so the memory shows in torch.cuda.memory_allocated()."""
+
+    def __init__(self, device=0, hbm_budget=0, allocator=None):
         h = C.c_void_p()
-        _check(lib().h2_ctx_create(device, hbm_budget, C.byref(h)))
+        if allocator not in (None, "torch"):
+            raise ValueError("allocator must be None or 'torch'")
+        hook = C.byref(_TORCH_ALLOCATOR) if allocator == "torch" else None
+        _check(lib().h2_ctx_create(device, hbm_budget, hook, C.byref(h)))
         self.h = h
         self._mats = weakref.WeakSet()
 
@@ -321,10 +372,19 @@ def release(ctx, ticket):
     _check(lib().h2_release(ctx.h, ticket))
 
 
-def mmp(ctx, A, B, eps, mode="accuracy", precision="fp64"):
+def mmp(ctx, A, B, eps, mode="accuracy", precision="fp64", stream=None):
+    """C = A B.  stream: a torch stream or hipStream_t handle; the product is
+    ordered on it and the call may return before its last kernels finish
+    (sync(C) waits).  Without a stream the call returns when C is complete."""
     h = C.c_void_p()
-    _check(lib().h2_mmp(ctx.h, A.h, B.h, float(eps), TRUNC[mode], PREC[precision], C.byref(h)))
+    _check(lib().h2_mmp(ctx.h, A.h, B.h, float(eps), TRUNC[mode], PREC[precision],
+                        _stream_handle(stream), C.byref(h)))
     return Matrix(ctx, h)
+
+
+def sync(M):
+    """Wait for the launches of the call that produced M."""
+    _check(lib().h2_sync(M.h))
 
 
 def is_complex(M):
@@ -333,9 +393,11 @@ def is_complex(M):
     return bool(sz.is_complex)
 
 
-def matvec(ctx, M, x):
+def matvec(ctx, M, x, stream=None):
     """y = M x.  x: numpy array (host) or a torch tensor on the GPU
-    (float64, n or n x nrhs, column-major for nrhs > 1 means x.T contiguous).
+    (float64, n or n x nrhs, column-major for nrhs > 1 means x.T contiguous;
+    the product is ordered on `stream`, a torch stream or handle, when given,
+    else on the current torch stream).
     Complex matrices: numpy x (complex), passed planar (real parts, then
     imaginary parts)."""
     if is_complex(M):
@@ -347,7 +409,7 @@ def matvec(ctx, M, x):
                             np.asfortranarray(X.imag).ravel(order="F")])
         Q = np.empty_like(P)
         _check(lib().h2_matvec(ctx.h, M.h, P.ctypes.data_as(C.c_void_p),
-                               Q.ctypes.data_as(C.c_void_p), nrhs, 0))
+                               Q.ctypes.data_as(C.c_void_p), nrhs, 0, None))
         m = X.shape[0] * nrhs
         Y = (Q[:m] + 1j * Q[m:]).reshape(X.shape, order="F")
         return Y[:, 0] if vec else Y
@@ -362,8 +424,9 @@ def matvec(ctx, M, x):
         nrhs = xx.shape[1]
         xc = xx.t().contiguous()  # column-major
         yc = torch.empty_like(xc)
+        st = stream if stream is not None else torch.cuda.current_stream(xc.device)
         _check(lib().h2_matvec(ctx.h, M.h, C.c_void_p(xc.data_ptr()), C.c_void_p(yc.data_ptr()),
-                               nrhs, 1))
+                               nrhs, 1, _stream_handle(st)))
         y = yc.t()
         return y[:, 0] if vec else y
     x = np.asarray(x, dtype=np.float64)
@@ -371,7 +434,7 @@ def matvec(ctx, M, x):
     X = np.asfortranarray(x.reshape(x.shape[0], -1))
     Y = np.empty_like(X, order="F")
     _check(lib().h2_matvec(ctx.h, M.h, X.ctypes.data_as(C.c_void_p), Y.ctypes.data_as(C.c_void_p),
-                           X.shape[1], 0))
+                           X.shape[1], 0, None))
     return Y[:, 0] if vec else Y
 
 
@@ -422,4 +485,6 @@ def stats(M):
                 bytes_device=s.bytes_device, gram_ms=s.gram_ms, other_ms=s.other_ms,
                 eig_launches=s.eig_launches, gram_launches=s.gram_launches,
                 other_launches=s.other_launches, gram_flops=s.gram_flops,
-                other_flops=s.other_flops, eig_flops=s.eig_flops)
+                other_flops=s.other_flops, eig_flops=s.eig_flops,
+                flops_triple=s.flops_triple, flops_target=s.flops_target,
+                flops_gram=s.flops_gram)

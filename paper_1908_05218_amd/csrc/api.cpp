@@ -475,7 +475,6 @@ void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64
   }
   H2_HIP(h2k::launch_scatter_rows(yt.d(), y_dev, sh.d_perm.as<long long>(),
                                   sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R * nc, st));
-  H2_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace h2
@@ -527,7 +526,12 @@ void* h2_ctx_s::alloc_raw(size_t bytes, bool is_f32) {
                                       " > " + std::to_string(budget) + " bytes)");
   }
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  if (has_hook) {
+    // the supplier pools on its own: hand out its block directly
+    p = hook.alloc(hook.user, bytes, device, stream);
+    if (!p) throw h2::Error(H2_ERR_OOM, "the context's allocator has no " + std::to_string(bytes) +
+                                            " bytes");
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
     // the failed call leaves its error as the thread's last error, which the
     // next launch check would report: clear it before the retry
     (void)hipGetLastError();
@@ -570,8 +574,15 @@ void h2_ctx_s::end_call(size_t start) {
 void h2_ctx_s::release(void* p) {
   auto it = live.find(p);
   if (it == live.end()) return;
-  pool.emplace(it->second, p);
-  pooled += it->second;
+  if (has_hook) {
+    // stream-ordered supplier: it may reuse the block for later work on this
+    // context's stream only
+    hook.free(hook.user, p, it->second, device, stream);
+    used -= it->second;
+  } else {
+    pool.emplace(it->second, p);
+    pooled += it->second;
+  }
   live_bytes -= it->second;
   live.erase(it);
   f32.erase(p);
@@ -581,8 +592,33 @@ void h2_ctx_s::release(void* p) {
 h2_ctx_s::~h2_ctx_s() {
   if (stream) hipStreamSynchronize(stream);
   for (auto& kv : pool) hipFree(kv.second);
-  for (auto& kv : live) hipFree(kv.first);
+  for (auto& kv : live) {
+    if (has_hook)
+      hook.free(hook.user, kv.first, kv.second, device, stream);
+    else
+      hipFree(kv.first);
+  }
   if (stream) hipStreamDestroy(stream);
+}
+
+void h2_mat_s::finish() {
+  if (ev_end) {
+    if (hipEventSynchronize(ev_end) != hipSuccess)
+      throw h2::Error(H2_ERR_DEVICE, "a launch of the product failed");
+  }
+  if (timing_pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev_begin, ev_end) == hipSuccess) stats.mmp_ms = ms;
+    (void)hipGetLastError();
+    timing_pending = false;
+  }
+}
+
+h2_mat_s::~h2_mat_s() {
+  // the context's stream may still run the launches that write M: the pool
+  // (or supplier) reuses its blocks only for later work on that stream
+  if (ev_begin) hipEventDestroy(ev_begin);
+  if (ev_end) hipEventDestroy(ev_end);
 }
 
 extern "C" {
@@ -590,8 +626,10 @@ extern "C" {
 const char* h2_last_error(void) { return h2::g_last_error.c_str(); }
 int h2_version(void) { return 1; }
 
-h2_status h2_ctx_create(int device, size_t hbm_budget, h2_ctx* out) {
+h2_status h2_ctx_create(int device, size_t hbm_budget, const h2_allocator* alloc, h2_ctx* out) {
   if (!out) return h2::set_error(H2_ERR_ARG, "out is null");
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return h2::set_error(H2_ERR_ARG, "an allocator needs both alloc and free");
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
     (void)hipGetLastError();
@@ -601,6 +639,10 @@ h2_status h2_ctx_create(int device, size_t hbm_budget, h2_ctx* out) {
   auto* c = new h2_ctx_s();
   c->device = device;
   c->budget = hbm_budget;
+  if (alloc) {
+    c->hook = *alloc;
+    c->has_hook = true;
+  }
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return h2::set_error(H2_ERR_DEVICE, "hipStreamCreate failed");
@@ -810,12 +852,40 @@ h2_status h2_load(h2_ctx ctx, const h2_host_matrix* m, h2_mat* out) {
   return h2::load_impl(ctx, m, false, out);
 }
 
+// Orders the context's stream after the work queued on the caller's stream
+// so far (no-op for a null stream or the context's own).
+static void fence_in(h2_ctx ctx, hipStream_t caller) {
+  if (!caller || caller == ctx->stream) return;
+  hipEvent_t ev;
+  H2_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  H2_HIP(hipEventRecord(ev, caller));
+  const hipError_t e = hipStreamWaitEvent(ctx->stream, ev, 0);
+  hipEventDestroy(ev);
+  H2_HIP(e);
+}
+
+// Orders later work on the caller's stream after the context's stream, or,
+// for a null caller stream, waits for the context's stream.
+static void fence_out(h2_ctx ctx, hipStream_t caller) {
+  if (!caller) {
+    H2_HIP(hipStreamSynchronize(ctx->stream));
+    return;
+  }
+  if (caller == ctx->stream) return;
+  hipEvent_t ev;
+  H2_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  H2_HIP(hipEventRecord(ev, ctx->stream));
+  const hipError_t e = hipStreamWaitEvent(caller, ev, 0);
+  hipEventDestroy(ev);
+  H2_HIP(e);
+}
+
 h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int precision,
-                 h2_mat* C_out) {
+                 hipStream_t stream, h2_mat* C_out) {
   using namespace h2;
   if (!ctx || !A || !B || !C_out) return set_error(H2_ERR_ARG, "null argument");
   if (!(eps >= 0.0) || !std::isfinite(eps)) return set_error(H2_ERR_ARG, "eps must be finite and >= 0");
-  if (trunc_mode < 0 || trunc_mode > 2) return set_error(H2_ERR_ARG, "bad truncation mode");
+  if (trunc_mode < 0 || trunc_mode > 3) return set_error(H2_ERR_ARG, "bad truncation mode");
   if (precision < 0 || precision > 1) return set_error(H2_ERR_ARG, "bad precision");
   if (A->shape != B->shape && !A->st().same_as(B->st()))
     return set_error(H2_ERR_STRUCTURE, "A and B differ in tree or block partition");
@@ -832,7 +902,18 @@ h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int
   h2_status r;
   try {
     hipSetDevice(ctx->device);
+    fence_in(ctx, stream);
     r = mmp_impl(ctx, A, B, eps, trunc_mode, precision, C_out);
+    if (r == H2_OK) {
+      try {
+        fence_out(ctx, stream);
+        if (!stream) (*C_out)->finish();
+      } catch (...) {
+        h2_free(*C_out);
+        *C_out = nullptr;
+        throw;
+      }
+    }
   } catch (const Error& e) {
     (void)hipGetLastError();
     r = set_error(e.code, e.msg);
@@ -843,8 +924,24 @@ h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int
   return r;
 }
 
+h2_status h2_sync(h2_mat M) {
+  using namespace h2;
+  if (!M) return set_error(H2_ERR_ARG, "null matrix");
+  std::unique_lock<std::recursive_mutex> lk;
+  if (M->ctx) lk = std::unique_lock<std::recursive_mutex>(M->ctx->mu);
+  try {
+    if (M->ctx) hipSetDevice(M->ctx->device);
+    M->finish();
+    if (M->ctx) H2_HIP(hipStreamSynchronize(M->ctx->stream));
+    return H2_OK;
+  } catch (const Error& e) {
+    (void)hipGetLastError();
+    return set_error(e.code, e.msg);
+  }
+}
+
 h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nrhs,
-                    int x_on_device) {
+                    int x_on_device, hipStream_t stream) {
   using namespace h2;
   if (!ctx || !M || !x || !y || nrhs < 1) return set_error(H2_ERR_ARG, "bad argument");
   ctx = home_of(ctx, M);
@@ -856,12 +953,16 @@ h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nr
     const long long n = M->st().n;
     const long long len = n * nrhs * (M->cplx ? 2 : 1);
     if (x_on_device) {
+      fence_in(ctx, stream);
       matvec_impl(ctx, M, x, y, nrhs);
+      fence_out(ctx, stream);
     } else {
       Buf xd(ctx, len * sizeof(double)), yd(ctx, len * sizeof(double));
-      H2_HIP(hipMemcpy(xd.d(), x, len * sizeof(double), hipMemcpyHostToDevice));
+      fence_in(ctx, stream);
+      H2_HIP(hipMemcpyAsync(xd.d(), x, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
       matvec_impl(ctx, M, xd.d(), yd.d(), nrhs);
-      H2_HIP(hipMemcpy(y, yd.d(), len * sizeof(double), hipMemcpyDeviceToHost));
+      H2_HIP(hipMemcpyAsync(y, yd.d(), len * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      H2_HIP(hipStreamSynchronize(ctx->stream));
     }
     return H2_OK;
   } catch (const Error& e) {
@@ -887,9 +988,12 @@ h2_status h2_to_dense(h2_ctx ctx, h2_mat M, double* out, int64_t ld) {
     std::vector<double> eye(nn * nc, 0.0);
     for (long long i = 0; i < n; ++i) eye[(size_t)i * n + i] = 1.0;
     Buf xd(ctx, nn * nc * sizeof(double)), yd(ctx, nn * nc * sizeof(double));
-    H2_HIP(hipMemcpy(xd.d(), eye.data(), nn * nc * sizeof(double), hipMemcpyHostToDevice));
+    H2_HIP(hipMemcpyAsync(xd.d(), eye.data(), nn * nc * sizeof(double), hipMemcpyHostToDevice,
+                          ctx->stream));
     matvec_impl(ctx, M, xd.d(), yd.d(), n);
-    H2_HIP(hipMemcpy(eye.data(), yd.d(), nn * nc * sizeof(double), hipMemcpyDeviceToHost));
+    H2_HIP(hipMemcpyAsync(eye.data(), yd.d(), nn * nc * sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    H2_HIP(hipStreamSynchronize(ctx->stream));
     for (long long j = 0; j < n; ++j)
       for (long long i = 0; i < n; ++i)
         for (int part = 0; part < nc; ++part)
@@ -1052,12 +1156,25 @@ h2_status h2_stats(h2_mat M, h2_stats_t* out) {
   if (!M || !out) return h2::set_error(H2_ERR_ARG, "null argument");
   std::unique_lock<std::recursive_mutex> lk;
   if (M->ctx) lk = std::unique_lock<std::recursive_mutex>(M->ctx->mu);
-  if (M->flops_pending) {
+  try {
+    if (M->ctx) hipSetDevice(M->ctx->device);
+    M->finish();
+  } catch (const h2::Error& e) {
+    (void)hipGetLastError();
+    return h2::set_error(e.code, e.msg);
+  }
+  if (M->flops_pending && M->flop_ranks) {
     // a complex block product is four real ones
-    M->stats.flops = h2::canonical_flops(M->st(), M->flop_akcol, M->flop_bkrow, *M) * (M->cplx ? 4.0 : 1.0);
+    const double m4 = M->cplx ? 4.0 : 1.0;
+    const h2::FlopCounts fc = h2::flop_counts(M->st(), *M->flop_ranks);
+    M->stats.flops_triple = fc.triple * m4;
+    M->stats.flops_target = fc.target * m4;
+    M->stats.flops_gram = fc.gram * m4;
+    M->stats.eig_flops = fc.eig * (M->cplx ? 8.0 : 1.0);  // real embedding of twice the size
+    M->stats.flops = M->stats.flops_triple + M->stats.flops_target + M->stats.flops_gram +
+                     M->stats.eig_flops;
     M->flops_pending = false;
-    std::vector<int64_t>().swap(M->flop_akcol);
-    std::vector<int64_t>().swap(M->flop_bkrow);
+    M->flop_ranks.reset();
   }
   *out = M->stats;
   return H2_OK;

@@ -31,12 +31,27 @@ struct Error {
   Error(h2_status c, std::string m) : code(c), msg(std::move(m)) {}
 };
 
+// ACCURACY-mode truncation factor: eigenvalues of a normalised Gram sum above
+// (kTheta eps / n_t)^2 lambda_1 are kept, n_t = levels whose bases are
+// truncated; fixed once on small members of each input family (the largest
+// value of {1, 1/2, 1/4} whose error stays at or below eps/2 there)
+constexpr double kTheta = 1.0;
+// fixed-basis mode: relative eigenvalue floor of an old basis' numerical rank
+constexpr double kFixedTau = 1e-12;
+
 inline int pad16(long long x) { return (int)(x <= 16 ? 16 : ((x + 15) / 16) * 16); }
 
 }  // namespace h2
 
 namespace h2 {
 struct Server;
+// actual ranks (flat cluster index 2^l - 1 + c) of A, B and C
+struct FlopRanks {
+  std::vector<int64_t> ar, ac, br, bc, cr, cc;
+};
+struct FlopCounts {
+  double triple = 0, target = 0, gram = 0, eig = 0;
+};
 }
 
 struct h2_ctx_s {
@@ -55,6 +70,10 @@ struct h2_ctx_s {
   h2_ctx_s* parent = nullptr;
   hipStream_t stream = nullptr;
   bool profiling = false;
+  // external supplier of device memory (h2_ctx_create); without one the
+  // context calls hipMalloc and pools freed blocks
+  h2_allocator hook{};
+  bool has_hook = false;
   std::multimap<size_t, void*> pool;
   std::unordered_map<void*, size_t> live;
   std::unordered_set<void*> f32;  // live allocations that hold float elements
@@ -168,20 +187,26 @@ struct h2_mat_s {
   h2::Buf F;                       // leaf level, flat by node, npad x npad
   h2_stats_t stats{};
   bool cplx = false;  // complex128 data (every block buffer holds two planes)
-  // ranks of the operands a product's canonical flop count needs (counted
-  // on the first h2_stats call)
-  std::vector<int64_t> flop_akcol, flop_bkrow;
+  // ranks a product's algorithmic flop count needs (counted on the first
+  // h2_stats call)
+  std::unique_ptr<h2::FlopRanks> flop_ranks;
   bool flops_pending = false;
   // float copy of V, W, Tr, Tc, S and F for FP32-bulk products (made on the
   // first such product, kept with the matrix)
   std::unique_ptr<h2_mat_s> f32;
+  // events around the numeric phase of the product that made M (on the
+  // context's stream); mmp_ms is read from them once they have completed
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+  bool timing_pending = false;
   const h2::Structure& st() const { return shape->s; }
+  // wait for the launches of the call that produced M; fills mmp_ms
+  void finish();
+  ~h2_mat_s();
 };
 
 namespace h2 {
 
-double canonical_flops(const Structure& s, const std::vector<int64_t>& a_kcol,
-                       const std::vector<int64_t>& b_krow, const h2_mat_s& C);
+FlopCounts flop_counts(const Structure& s, const FlopRanks& r);
 
 // Operand description for the batched GEMM helpers.
 struct Op {

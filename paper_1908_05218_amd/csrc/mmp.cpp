@@ -25,6 +25,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <unordered_map>
+#include <unordered_set>
 
 #include "internal.h"
 
@@ -41,35 +43,111 @@ struct Dims {
 
 }  // namespace
 
-// 2 r1 r2 r3 per evaluated block product with the actual dimensions; run on
-// the first h2_stats call for a product, not inside it
-double canonical_flops(const Structure& s, const std::vector<int64_t>& a_kcol,
-                       const std::vector<int64_t>& b_krow, const h2_mat_s& Cm) {
-  const h2_mat_s* C = &Cm;
-  double f = 0;
-  const int L = s.L;
-  for (int l = s.lmin; l <= L; ++l) {
+// Algorithmic work of a product at the actual ranks (unpadded), in four parts
+// (Sections III-IV; run on the first h2_stats call for a product, not inside
+// it):
+//  triple: one contraction per evaluated block product (A node (I,J), B node
+//    (J,K) of one level): 2 n_i n_j n_k for a dense target; at the leaves
+//    2 kC_i n_j kC_k for dense x dense, 2 kC_i kB_j kB_k (Ahat S^B),
+//    2 kA_i kA_j kC_k (S^A Bhat) and 2 kA_i kB_j kB_k ((S^A Pi) S^B) for the
+//    other pairs (equation leafcoup_simple); above the leaves the
+//    re-associated single contraction 2 kC_I kB_J kB_K for NL x R and
+//    2 kA_I kA_J kC_K otherwise (equation nonleafcoup_simple);
+//  target: per target the products that apply the projections once
+//    (X2 P^B, P^A X3, P^A X4 P^B at the leaves; W P^B, P^A W and
+//    T^C_I^H M_IK T^C_K above them);
+//  gram: 2 d^2 per contributed column of each row and column Gram sum
+//    (equations Gr1L-case3-ch and case1-ch-nl-case3-ch-nl);
+//  eig: 9 d^3 per Gram matrix.
+FlopCounts flop_counts(const Structure& s, const FlopRanks& r) {
+  FlopCounts f;
+  const int L = s.L, lmin = s.lmin;
+  auto n_ = [&](int c) { return (double)s.leaf_size[c]; };
+  auto at = [](const std::vector<int64_t>& v, int l, int c) { return (double)v[cidx(l, c)]; };
+  auto key = [](int i, int k) { return ((uint64_t)(uint32_t)i << 32) | (uint32_t)k; };
+  std::unordered_set<uint64_t> acc;  // blue accumulators of the level below
+  for (int l = L; l >= lmin; --l) {
     const LevelNodes& ln = s.lev[l];
-    std::vector<std::vector<int>> byrow(1 << l);
+    const int ncl = 1 << l;
+    std::vector<std::vector<int>> byrow(ncl);
     for (int q = 0; q < ln.size(); ++q) byrow[ln.row[q]].push_back(q);
+    std::vector<double> rcols(ncl, 0.0), ccols(ncl, 0.0), dr(ncl), dc(ncl);
+    for (int c = 0; c < ncl; ++c) {
+      dr[c] = l == L ? n_(c) : at(r.cr, l + 1, 2 * c) + at(r.cr, l + 1, 2 * c + 1);
+      dc[c] = l == L ? n_(c) : at(r.cc, l + 1, 2 * c) + at(r.cc, l + 1, 2 * c + 1);
+      rcols[c] = at(r.ar, l, c);  // the old bases (Gr3L / case3-ch-nl)
+      ccols[c] = at(r.bc, l, c);
+    }
+    // merged targets of this level: parents of the blue accumulators below
+    std::unordered_set<uint64_t> case1;
+    if (l < L)
+      for (uint64_t v : acc) case1.insert(key((int)(v >> 32) >> 1, (int)(uint32_t)v >> 1));
+    std::unordered_set<uint64_t> next;
+    // per target: bit 0 NL x R (or dense x admissible at the leaves),
+    // bit 1 admissible x dense, bit 2 admissible x admissible
+    std::unordered_map<uint64_t, int> tgt;
     for (int qa = 0; qa < ln.size(); ++qa) {
       const int i = ln.row[qa], j = ln.col[qa], ta = ln.type[qa];
+      if (ta == kF) rcols[i] += at(r.br, l, j);  // F^A_ij V^B_j (Gr2L)
+      if (ta == kNL) rcols[i] += at(r.br, l, j);  // Acoll_IJ T^B_J (case2-ch-nl)
+      if (ta == kF || ta == kNL) ccols[j] += at(r.ac, l, i);  // mirror on B's node (i, j)
       for (int qb : byrow[j]) {
         const int tb = ln.type[qb];
         if (ta == kNL && tb == kNL) continue;
         const int k = ln.col[qb];
-        const int qc = s.lev[l].find(i, k);
-        if (l == L) {
-          if (qc >= 0 && ln.type[qc] == kF)
-            f += 2.0 * s.leaf_size[i] * s.leaf_size[j] * s.leaf_size[k];
-          else
-            f += 2.0 * C->krow[cidx(l, i)] * s.leaf_size[j] * C->kcol[cidx(l, k)];
-        } else {
-          const double inner = ta == kNL ? b_krow[cidx(l, j)] : a_kcol[cidx(l, j)];
-          f += 2.0 * C->krow[cidx(l, i)] * inner * C->kcol[cidx(l, k)];
+        const int qc = ln.find(i, k);
+        const int tg = qc < 0 ? kBlue : ln.type[qc];
+        if (tg == kF) {
+          f.triple += 2.0 * n_(i) * n_(j) * n_(k);
+          continue;
         }
+        if (tg == kBlue) next.insert(key(i, k));
+        int bit = 0;
+        if (l == L) {
+          if (ta == kF && tb == kF) {
+            f.triple += 2.0 * at(r.cr, l, i) * n_(j) * at(r.cc, l, k);
+            rcols[i] += n_(k);  // F^A_ij F^B_jk (Gr1L)
+            ccols[k] += n_(i);
+          } else if (ta == kF) {
+            f.triple += 2.0 * at(r.cr, l, i) * at(r.br, l, j) * at(r.bc, l, k);
+            bit = 1;
+          } else if (tb == kF) {
+            f.triple += 2.0 * at(r.ar, l, i) * at(r.ac, l, j) * at(r.cc, l, k);
+            bit = 2;
+          } else {
+            f.triple += 2.0 * at(r.ar, l, i) * at(r.br, l, j) * at(r.bc, l, k);
+            bit = 4;
+          }
+        } else if (ta == kNL) {
+          f.triple += 2.0 * at(r.cr, l, i) * at(r.br, l, j) * at(r.bc, l, k);
+          bit = 1;
+        } else {
+          f.triple += 2.0 * at(r.ar, l, i) * at(r.ac, l, j) * at(r.cc, l, k);
+          bit = 2;
+        }
+        if (bit) tgt[key(i, k)] |= bit;
       }
     }
+    for (const auto& kv : tgt) {
+      const int i = (int)(kv.first >> 32), k = (int)(uint32_t)kv.first;
+      const double ci = at(r.cr, l, i), ck = at(r.cc, l, k), ai = at(r.ar, l, i),
+                   bk = at(r.bc, l, k);
+      if (kv.second & 1) f.target += 2.0 * ci * bk * ck;           // X2 P^B / W_nl P^B
+      if (kv.second & 4) f.target += 2.0 * ai * bk * ck;           // X4 P^B
+      if (kv.second & 6) f.target += 2.0 * ci * ai * ck;           // P^A (X3 + X4 P^B) / P^A W_r
+    }
+    for (uint64_t v : case1) {
+      const int i = (int)(v >> 32), k = (int)(uint32_t)v;
+      f.target += 2.0 * at(r.cr, l, i) * dr[i] * dc[k] + 2.0 * at(r.cr, l, i) * dc[k] * at(r.cc, l, k);
+      rcols[i] += dc[k];  // M_IK (case1-ch-nl)
+      ccols[k] += dr[i];
+      if (ln.find(i, k) < 0) next.insert(v);  // a blue merged target moves up
+    }
+    for (int c = 0; c < ncl; ++c) {
+      f.gram += 2.0 * dr[c] * dr[c] * rcols[c] + 2.0 * dc[c] * dc[c] * ccols[c];
+      f.eig += 9.0 * (dr[c] * dr[c] * dr[c] + dc[c] * dc[c] * dc[c]);
+    }
+    acc.swap(next);
   }
   return f;
 }
@@ -111,17 +189,36 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   const h2_mat_s* Ad = bulk ? &f32_shadow(ctx, A, st) : A;
   const h2_mat_s* Bd = bulk ? (B == A ? Ad : &f32_shadow(ctx, B, st)) : B;
   const int L = s.L, lmin = s.lmin, np = s.npad, nleaf = 1 << L;
-  const bool exact = (mode == H2_TRUNC_EXACT) || eps == 0.0;
-  const double tau = exact ? 0.0 : (mode == H2_TRUNC_PAPER ? eps : eps * eps);
+  const bool exact = mode == H2_TRUNC_EXACT || (eps == 0.0 && mode != H2_TRUNC_FIXED);
+  // ACCURACY: singular values of the stacked normalised contributions above
+  // theta eps / n_t, n_t = number of truncated levels (each level's
+  // truncation adds its own error to C, so the budget eps is split evenly);
+  // PAPER: the Gram's own values above eps (Section III-C)
+  const int n_trunc = std::max(1, L - lmin + 1);
+  const double sv = kTheta * eps / n_trunc;
+  // FIXED: the fixed-basis ("formatted") product of Section I and Table IV:
+  // each new basis is the numerical range of the old basis alone (the third
+  // Gram component), so C keeps A's row and B's column bases, orthonormalised
+  const bool fixed = mode == H2_TRUNC_FIXED;
+  const double tau = fixed ? kFixedTau
+                           : exact ? 0.0 : (mode == H2_TRUNC_PAPER ? eps : sv * sv);
   Profiler prof;
   prof.on = ctx->profiling;
   prof.stream = st;
   Profiler* pp = &prof;
 
-  hipEvent_t ev0, ev1;
-  H2_HIP(hipEventCreate(&ev0));
-  H2_HIP(hipEventCreate(&ev1));
-  H2_HIP(hipEventRecord(ev0, st));
+  // events around the numeric phase; handed to C at the end (destroyed here
+  // when the product fails)
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) hipEventDestroy(a);
+      if (b) hipEventDestroy(b);
+    }
+  } ev;
+  H2_HIP(hipEventCreate(&ev.a));
+  H2_HIP(hipEventCreate(&ev.b));
+  H2_HIP(hipEventRecord(ev.a, st));
 
   const std::vector<int>&rrA = A->rr, &rcA = A->rc, &rrB = B->rr, &rcB = B->rc;
   Buf status(ctx, 4 * sizeof(int));
@@ -142,7 +239,6 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   C->Tc_stride.assign(L, 0);
   C->S.resize(L + 1);
   std::vector<int> cpad(L + 1, 16);
-  double eig_flops = 0.0;
   std::vector<Buf> rank_r(L + 1), rank_c(L + 1);
 
   // ---------------------------------------------------------- step 0: Pi
@@ -320,7 +416,9 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       G[k] = Buf(ctx, (size_t)nleaf * nn2 * gb, false, cplx);
       Gc[k] = Buf(ctx, (size_t)nleaf * nn2 * gb, false, cplx);
     }
-    {
+    if (fixed) {
+      for (Buf* g : {&G[0], &G[1], &Gc[0], &Gc[1]}) zero(st, g->p(), (long long)nleaf * nn2);
+    } else {
       Buf b1(ctx, nnL * nn2 * gb, false, cplx), b2(ctx, nnL * nn2 * gb, false, cplx),
           b3(ctx, nnL * nn2 * gb, false, cplx);
       const Op FA{Ad->F.p(), nullptr, nn2, 0, np}, FB{Bd->F.p(), nullptr, nn2, 0, np};
@@ -348,6 +446,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
            Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, false, Z.p(), zcs, np, 0, 0, 1, 0);
       gemm(st, pp, kKindGram, dl(LP.G2c), np, np, rcA[L], Op{Z.p(), nullptr, zcs, 0, np}, false,
            Op{Z.p(), nullptr, zcs, 0, np}, true, Gc[1].p(), nn2, np, 0, 0, 1, 0, kConjB | kLowerOnly);
+    }
+    {
       // case 3/4: the old bases V^A_i V^A_i^T (Gr3L) and W^B_k W^B_k^T (case3-ch)
       gemm(st, pp, kKindGram, dl(LP.G3), np, np, rrA[L], Op{Ad->V.p(), nullptr, A->V_stride, 0, np},
            false, Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, true, G[2].p(), nn2, np, 0, 0, 1, 0, kConjB | kLowerOnly);
@@ -358,7 +458,6 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
               leaf_sizes.as<int>(), nullptr, 1, np);
   }
   c = read_ranks(L, rank_r[L], rank_c[L]);
-  for (int c2 = 0; c2 < nleaf; ++c2) eig_flops += 2.0 * 9.0 * std::pow((double)s.leaf_size[c2], 3);
   cpad[L] = c;
   {
     const Op VC{Ur_L.p(), nullptr, nn2, 0, np}, WC{Uc_L.p(), nullptr, nn2, 0, np};
@@ -464,8 +563,12 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       Gc[k] = Buf(ctx, (size_t)ncl * K2 * gb, false, cplx);
     }
     // case 1: merged children couplings M_IK (nonleafA; case1-ch-nl)
-    gemm(st, pp, kKindGram, dl(Q.G1), K, K, K, AccT, false, AccT, true, G[0].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
-    gemm(st, pp, kKindGram, dl(Q.G1c), K, K, K, AccT, true, AccT, false, Gc[0].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
+    if (fixed) {
+      for (Buf* g : {&G[0], &G[1], &Gc[0], &Gc[1]}) zero(st, g->p(), (long long)ncl * K2);
+    } else {
+      gemm(st, pp, kKindGram, dl(Q.G1), K, K, K, AccT, false, AccT, true, G[0].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
+      gemm(st, pp, kKindGram, dl(Q.G1c), K, K, K, AccT, true, AccT, false, Gc[0].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
+    }
     // case 2: (NL^A)_coll T^B_J (case2-ch-nl) and its column mirror
     const long long ys = (long long)K * rrB[l], ycs = (long long)rcA[l] * K;
     Buf Y(ctx, (size_t)std::max(1, nn) * ys * gb, false, cplx);
@@ -473,14 +576,16 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     gemm(st, pp, kKindGram, dl(Q.Y), K, rrB[l], 2 * rrB[ch],
          Op{Ahat_ch.p(), nullptr, 4LL * cc * rrB[ch], 0, K}, false,
          Op{Bd->Tr[l].p(), nullptr, B->Tr_stride[l], 0, 2 * rrB[ch]}, false, Y.p(), ys, K, 0, 0, 1, 0);
-    gemm(st, pp, kKindGram, dl(Q.G2), K, K, rrB[l], Op{Y.p(), nullptr, ys, 0, K}, false,
-         Op{Y.p(), nullptr, ys, 0, K}, true, G[1].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
+    if (!fixed)
+      gemm(st, pp, kKindGram, dl(Q.G2), K, K, rrB[l], Op{Y.p(), nullptr, ys, 0, K}, false,
+           Op{Y.p(), nullptr, ys, 0, K}, true, G[1].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
     gemm(st, pp, kKindGram, dl(Q.Yc), rcA[l], K, 2 * rcA[ch],
          Op{Ad->Tc[l].p(), nullptr, A->Tc_stride[l], 0, 2 * rcA[ch]}, true,
          Op{Bhat_ch.p(), nullptr, 4LL * rcA[ch] * cc, 0, 2 * rcA[ch]}, false, Yc.p(), ycs, rcA[l],
          0, 0, 1, 0);
-    gemm(st, pp, kKindGram, dl(Q.G2c), K, K, rcA[l], Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, true,
-         Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, false, Gc[1].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
+    if (!fixed)
+      gemm(st, pp, kKindGram, dl(Q.G2c), K, K, rcA[l], Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, true,
+           Op{Yc.p(), nullptr, ycs, 0, rcA[l]}, false, Gc[1].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
     // cases 3/4: old bases projected on the children's new bases (case3-ch-nl)
     const long long ds = (long long)K * rrA[l], qs = (long long)K * rcB[l];
     Buf Dm(ctx, (size_t)ncl * ds * gb, false, cplx), Qm(ctx, (size_t)ncl * qs * gb, false, cplx);
@@ -504,11 +609,6 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       Gc[k].reset();
     }
     const int cl = read_ranks(l, rank_r[l], rank_c[l]);
-    for (int c2 = 0; c2 < ncl; ++c2) {
-      const double dr = (double)(C->krow[cidx(ch, 2 * c2)] + C->krow[cidx(ch, 2 * c2 + 1)]);
-      const double dc = (double)(C->kcol[cidx(ch, 2 * c2)] + C->kcol[cidx(ch, 2 * c2 + 1)]);
-      eig_flops += 9.0 * (dr * dr * dr + dc * dc * dc);
-    }
     cpad[l] = cl;
     const Op TCr{Ur[l].p(), nullptr, K2, 0, K}, TCc{Uc[l].p(), nullptr, K2, 0, K};
     // projections (nonleafproj)
@@ -560,9 +660,9 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       gemm(st, pp, kKindOther, dl(Q.c1X), cl, K, K, TCr, true, AccT, false, X1.p(),
            (long long)cl * K, cl, 0, 0, 1, 0, kConjA);
       const Op X1o{X1.p(), nullptr, (long long)cl * K, 0, cl};
-      gemm(st, pp, kKindTriple, dl(Q.c1_R), cl, cl, K, X1o, false, TCc, false, C->S[l].p(), cs, cl,
+      gemm(st, pp, kKindOther, dl(Q.c1_R), cl, cl, K, X1o, false, TCc, false, C->S[l].p(), cs, cl,
            0, 0, 1, 1, kConjB);
-      gemm(st, pp, kKindTriple, dl(Q.c1_B), cl, cl, K, X1o, false, TCc, false, Acc_l.p(), acs,
+      gemm(st, pp, kKindOther, dl(Q.c1_B), cl, cl, K, X1o, false, TCc, false, Acc_l.p(), acs,
            2 * cl, cl, (long long)cl * 2 * cl, 1, 1, kConjB);
     }
     // cases 2-4 (nonleafcoup_simple), re-associated: for an admissible B
@@ -602,17 +702,17 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
                       const Buf& Wn, const Buf& Wr, const Tgt& t) {
       if (rcB[l] == rrA[l] && Wn.bytes() && Wr.bytes()) {
         // one pass over the targets: [W_nl | P^A_I] x [P^B_K ; W_r]
-        gemm(st, pp, kKindTriple, dl(fboth), cl, cl, rcB[l],
+        gemm(st, pp, kKindOther, dl(fboth), cl, cl, rcB[l],
              Op{Wn.p(), PA_l.p(), wns, (long long)cl * rrA[l], cl}, false,
              Op{PB_l.p(), Wr.p(), (long long)rcB[l] * cl, wrs, rcB[l]}, false, t.p, t.stride, t.ld,
              t.sr, t.sc, 1, 1);
         return;
       }
       if (Wn.bytes())
-        gemm(st, pp, kKindTriple, dl(fnl), cl, cl, rcB[l], Op{Wn.p(), nullptr, wns, 0, cl}, false,
+        gemm(st, pp, kKindOther, dl(fnl), cl, cl, rcB[l], Op{Wn.p(), nullptr, wns, 0, cl}, false,
              PBo, false, t.p, t.stride, t.ld, t.sr, t.sc, 1, 1);
       if (Wr.bytes())
-        gemm(st, pp, kKindTriple, dl(fr), cl, cl, rrA[l], PAo, false,
+        gemm(st, pp, kKindOther, dl(fr), cl, cl, rrA[l], PAo, false,
              Op{Wr.p(), nullptr, wrs, 0, rrA[l]}, false, t.p, t.stride, t.ld, t.sr, t.sc, 1, 1);
     };
     {
@@ -681,17 +781,14 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     for (int l = lmin; l <= L; ++l) widen(C->S[l]);
     widen(FC);
   }
-  H2_HIP(hipEventRecord(ev1, st));
-  H2_HIP(hipStreamSynchronize(st));
-  float ms = 0;
-  H2_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-  hipEventDestroy(ev0);
-  hipEventDestroy(ev1);
-  {
-    std::vector<int> stv(4);
-    H2_HIP(hipMemcpy(stv.data(), status.as<int>(), 4 * sizeof(int), hipMemcpyDeviceToHost));
-    if (stv[0]) throw Error(H2_ERR_NUMERIC, "non-finite value in a Gram matrix");
-  }
+  // the status flags were last read with the ranks of level l_min; nothing
+  // after that level writes them
+  H2_HIP(hipEventRecord(ev.b, st));
+  if (prof.on) H2_HIP(hipStreamSynchronize(st));
+  C->ev_begin = ev.a;
+  C->ev_end = ev.b;
+  C->timing_pending = true;
+  ev.a = ev.b = nullptr;
 
   // ---------------------------------------------------------- assemble C
   for (int l = lmin; l <= L; ++l) {
@@ -728,15 +825,14 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     S.rank_mean_r[l] = sr / (1 << l);
     S.rank_mean_c[l] = sc / (1 << l);
   }
-  S.mmp_ms = ms;
+  S.mmp_ms = 0.0;  // filled from the events by finish()
   S.symbolic_ms = sym_ms;
   S.n_triples = P.n_triples;
   S.sparsity_constant = s.sparsity_constant();
-  C->flop_akcol = A->kcol;
-  C->flop_bkrow = B->krow;
+  C->flop_ranks = std::make_unique<FlopRanks>(
+      FlopRanks{A->krow, A->kcol, B->krow, B->kcol, C->krow, C->kcol});
   C->flops_pending = true;
   S.bytes_device = (int64_t)ctx->peak_live;
-  S.eig_flops = eig_flops;
   if (prof.on) {
     double pms[kKindCount], pfl[kKindCount];
     long long pl[kKindCount];

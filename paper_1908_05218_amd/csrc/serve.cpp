@@ -126,7 +126,7 @@ struct Server {
         build_peak = sc->peak_live;
       }
       if (r.status == H2_OK) {
-        r.status = h2_mmp(sc, A, A, j->req.eps, j->req.trunc_mode, j->req.precision, &C);
+        r.status = h2_mmp(sc, A, A, j->req.eps, j->req.trunc_mode, j->req.precision, nullptr, &C);
         if (r.status != H2_OK) {
           h2_free(A);
           A = nullptr;
@@ -218,7 +218,7 @@ h2_status h2_submit(h2_ctx ctx, const h2_request* req, uint64_t* ticket) {
   if (req->n < 1 || req->opts.leaf_size < 1 || !(req->opts.eta > 0.0) ||
       req->opts.cheb_order < 1 || req->opts.cheb_order > 6)
     return set_error(H2_ERR_ARG, "invalid request sizes or options");
-  if (!(req->eps >= 0.0) || req->trunc_mode < 0 || req->trunc_mode > 2 || req->precision < 0 ||
+  if (!(req->eps >= 0.0) || req->trunc_mode < 0 || req->trunc_mode > 3 || req->precision < 0 ||
       req->precision > 1)
     return set_error(H2_ERR_ARG, "invalid eps, mode or precision");
   if (req->kernel.kind != H2_KERNEL_LAPLACE)
@@ -235,7 +235,7 @@ h2_status h2_submit(h2_ctx ctx, const h2_request* req, uint64_t* ticket) {
       s->ctx = ctx;
       for (int w = 0; w < ctx->serve_slots; ++w) {
         h2_ctx sc = nullptr;
-        if (h2_ctx_create(ctx->device, ctx->budget, &sc) != H2_OK) {
+        if (h2_ctx_create(ctx->device, ctx->budget, ctx->has_hook ? &ctx->hook : nullptr, &sc) != H2_OK) {
           for (h2_ctx c : s->slots) h2_ctx_destroy(c);
           delete s;
           return H2_ERR_DEVICE;  // message set by h2_ctx_create

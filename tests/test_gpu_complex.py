@@ -1,5 +1,5 @@
 """GPU parity for complex128 H^2 matrices (the Helmholtz-type inputs of
-Section V's scattering examples): the HIP library through the C-ABI against
+Section VI's scattering examples): the HIP library through the C-ABI against
 the CPU checker on the same seeded inputs.  Tolerances as for real data:
 mat-vec and dense expansion 1e-13 relative, EXACT products 1e-12 relative to
 the dense product, ACCURACY products within eps of AB and of the checker's

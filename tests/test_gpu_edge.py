@@ -70,19 +70,21 @@ def test_zero_matrix(ctx):
 
 
 def test_eps_large_keeps_one_vector(ctx):
-    """eps = 1: the threshold lambda_1 keeps exactly one vector per cluster,
-    as the checker does."""
+    """PAPER mode at eps = 1: the threshold lambda_1 keeps exactly one vector
+    per cluster; ACCURACY mode at eps = 1 keeps the checker's ranks."""
     print("case eps = 1", flush=True)
     A = cases.plates(2048)
     dA = h2.load(ctx, A.to_flat())
-    C = h2.mmp(ctx, dA, dA, 1.0)
-    exp = h2.export(C)
-    _, info = omp.h2_mmp(A, A, 1.0)
-    lmin = info["lmin"]
-    for key, r in (("krow", "ranks_row"), ("kcol", "ranks_col")):
-        got = np.asarray(exp[key])
-        for lev in range(lmin, A.L + 1):
-            ref = np.asarray(info[r][lev])
-            g = got[(1 << lev) - 1:(2 << lev) - 1]
-            assert np.array_equal(g, ref), (key, lev)
-            assert g.max() == 1
+    for mode, om in (("paper", omp.PAPER), ("accuracy", omp.ACCURACY)):
+        C = h2.mmp(ctx, dA, dA, 1.0, mode=mode)
+        exp = h2.export(C)
+        _, info = omp.h2_mmp(A, A, 1.0, mode=om)
+        lmin = info["lmin"]
+        for key, r in (("krow", "ranks_row"), ("kcol", "ranks_col")):
+            got = np.asarray(exp[key])
+            for lev in range(lmin, A.L + 1):
+                ref = np.asarray(info[r][lev])
+                g = got[(1 << lev) - 1:(2 << lev) - 1]
+                assert np.array_equal(g, ref), (mode, key, lev)
+                if mode == "paper":
+                    assert g.max() == 1
