@@ -46,6 +46,15 @@ def plates64k():
                     LaplaceKernel(panel_self_term(1 / 128, 1 / 256)), 1e-4)
 
 
+def plates64k_patch(nx, ny):
+    """A patch of the plates64k workload: nx x ny cells of its 128 x 256 grid
+    per plate (same spacing, gap, jitter, self-term, leaf size, order, eps;
+    2 nx ny points), a bounded sample of the same problem."""
+    return Workload(f"plates64k_patch{nx}x{ny}",
+                    points.plates_grid(nx, ny, 0.1, 1e-3, 1, cells=(128, 256)), 32, 1.0, 3,
+                    LaplaceKernel(panel_self_term(1 / 128, 1 / 256)), 1e-4)
+
+
 def cube_n(n, seed=0, leaf=32, order=3, eps=1e-4):
     return Workload(f"cube{n}", points.cube(n, seed), leaf, 1.0, order,
                     LaplaceKernel(1.0), eps)

@@ -17,14 +17,16 @@ def cube(n, seed):
     return rng.uniform(0.0, 1.0, size=(n, 3))
 
 
-def plates_grid(nx, ny, gap, jitter, seed):
-    """Two parallel unit plates at z=0 and z=gap, an nx-by-ny cell-centre grid
-    on each (x=(i+1/2)/nx, y=(j+1/2)/ny), every coordinate perturbed by
-    U[-jitter, jitter]. Returns 2*nx*ny points, lower plate first."""
+def plates_grid(nx, ny, gap, jitter, seed, cells=None):
+    """Two parallel plates at z=0 and z=gap, an nx-by-ny cell-centre grid on
+    each (x=(i+1/2)/cx, y=(j+1/2)/cy with (cx, cy) = cells, default (nx, ny):
+    unit plates), every coordinate perturbed by U[-jitter, jitter].  Returns
+    2*nx*ny points, lower plate first."""
     rng = np.random.default_rng(seed)
+    cx, cy = cells if cells is not None else (nx, ny)
     ix, iy = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
-    x = ((ix + 0.5) / nx).ravel()
-    y = ((iy + 0.5) / ny).ravel()
+    x = ((ix + 0.5) / cx).ravel()
+    y = ((iy + 0.5) / cy).ravel()
     pts = []
     for z in (0.0, gap):
         pts.append(np.stack([x, y, np.full_like(x, z)], axis=1))

@@ -71,8 +71,11 @@ static void check_extent(const void* base, long long stride, int maxtile, long l
   if (ld < rows) throw Error(H2_ERR_INTERNAL, std::string(what) + ": leading dimension too small");
   if (!g_active_ctx) return;
   auto it = g_active_ctx->live.find(const_cast<void*>(base));
-  if (it == g_active_ctx->live.end())
-    throw Error(H2_ERR_INTERNAL, std::string(what) + ": operand is not a live allocation");
+  if (it == g_active_ctx->live.end()) {
+    it = g_active_ctx->ext.find(const_cast<void*>(base));
+    if (it == g_active_ctx->ext.end())
+      throw Error(H2_ERR_INTERNAL, std::string(what) + ": operand is not a live allocation");
+  }
   const long long need = (long long)maxtile * stride + sub_r + sub_c + (rows - 1) + (cols - 1) * ld + 1;
   // a complex allocation is checked against its real plane (the imaginary
   // plane has the same layout one plane further)
@@ -334,86 +337,34 @@ std::unique_ptr<DevPlan> upload_plan(h2_ctx ctx, const Plan& p) {
 static inline long long cidx(int l, int c) { return (1LL << l) - 1 + c; }
 
 // ------------------------------------------------------------------ mat-vec
-// Exact H^2 mat-vec (the reference solution of equation `error`): forward
-// transform up the column tree, couplings, backward transform down the row
-// tree, dense near field.
-void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64_t nrhs) {
-  ActiveCtx active(ctx);
+// Task lists of the exact H^2 mat-vec of M, built once per matrix: forward
+// transform up the column tree, couplings per level, backward transform down
+// the row tree, dense near field.  The host copy stays with the plan so that
+// the upload needs no host wait.
+void build_matvec_plan(h2_ctx ctx, h2_mat M) {
   const Structure& s = M->st();
-  Shape& sh = *M->shape;
-  hipStream_t st = ctx->stream;
-  const int L = s.L, np = s.npad, nleaf = 1 << L;
-  const int lo = M->product ? s.lmin : s.lmin;  // no admissible block above lmin
-  const long long nt = (long long)nleaf * np;
-  const int R = (int)nrhs;
-  // complex: x and y planar (n x nrhs real parts, then the imaginary parts),
-  // gathered and scattered as 2 nrhs real columns
-  const int nc = M->cplx ? 2 : 1;
-  const bool cx = M->cplx;
-  Buf xt(ctx, nt * R * nc * sizeof(double), false, cx), yt(ctx, nt * R * nc * sizeof(double), false, cx);
-  H2_HIP(h2k::launch_gather_rows(x_dev, xt.d(), sh.d_perm.as<long long>(),
-                                 sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R * nc, st));
-  // identity task lists built on the fly (small)
-  std::vector<Buf> xh(L + 1), yh(L + 1);
-  for (int l = lo; l <= L; ++l) {
-    xh[l] = Buf(ctx, (size_t)(1 << l) * M->rc[l] * R * nc * sizeof(double), false, cx);
-    yh[l] = Buf(ctx, (size_t)(1 << l) * M->rr[l] * R * nc * sizeof(double), false, cx);
-    zero(st, yh[l].d(), (long long)(1 << l) * M->rr[l] * R);
-  }
-  // temporary device task lists
-  struct TmpList {
-    Buf mem;
-    DevList d;
-  };
-  auto mk = [&](const TaskList& t) {
-    TmpList r;
-    std::vector<int> h;
-    h.insert(h.end(), t.out.begin(), t.out.end());
-    h.insert(h.end(), t.seg.begin(), t.seg.end());
-    h.insert(h.end(), t.a.begin(), t.a.end());
-    h.insert(h.end(), t.b.begin(), t.b.end());
-    r.mem = Buf(ctx, (h.size() + 1) * sizeof(int));
-    H2_HIP(hipMemcpyAsync(r.mem.as<int>(), h.data(), h.size() * sizeof(int),
-                          hipMemcpyHostToDevice, st));
-    int* b = r.mem.as<int>();
-    r.d.nout = t.nout();
-    r.d.ntask = t.ntask();
-    r.d.out = b;
-    r.d.seg = b + t.out.size();
-    r.d.a = r.d.seg + t.seg.size();
-    r.d.b = r.d.a + t.a.size();
-    scan_limits(t, r.d);
-    H2_HIP(hipStreamSynchronize(st));
-    return r;
-  };
-  const LevelNodes& lf = s.lev[L];
-  const long long ldx = nt;
-  // forward
+  const int L = s.L, nleaf = 1 << L, lo = s.lmin;
+  auto mp = std::make_unique<MatvecPlan>();
+  std::vector<TaskList> lists;
+  // forward, leaves: xh_L(c) = W_c^T x_c
   {
     TaskList t;
     for (int c = 0; c < nleaf; ++c) {
       t.add_task(enc(c), enc(c));
       t.close(enc(c));
     }
-    TmpList d = mk(t);
-    Op A{M->W.d(), nullptr, M->W_stride, 0, np, 0, 0};
-    Op B{xt.d(), nullptr, np, 0, (int)ldx, 0, 0};
-    gemm(st, nullptr, 0, d.d, M->rc[L], R, np, A, true, B, false, xh[L].d(),
-         (long long)M->rc[L] * R, M->rc[L], 0, 0, 1.0, 0.0);
+    lists.push_back(std::move(t));
   }
+  // forward, level l < L: xh_l(J) = sum over the two children E_j^T xh_{l+1}(j)
   for (int l = L - 1; l >= lo; --l) {
     TaskList t;
     for (int J = 0; J < (1 << l); ++J) {
       for (int a = 0; a < 2; ++a) t.add_task(enc(J, a), enc(2 * J + a));
       t.close(enc(J));
     }
-    TmpList d = mk(t);
-    Op A{M->Tc[l].d(), nullptr, M->Tc_stride[l], 0, 2 * M->rc[l + 1], M->rc[l + 1], 0};
-    Op B{xh[l + 1].d(), nullptr, (long long)M->rc[l + 1] * R, 0, M->rc[l + 1], 0, 0};
-    gemm(st, nullptr, 0, d.d, M->rc[l], R, M->rc[l + 1], A, true, B, false, xh[l].d(),
-         (long long)M->rc[l] * R, M->rc[l], 0, 0, 1.0, 0.0);
+    lists.push_back(std::move(t));
   }
-  // couplings
+  // couplings, level l: yh_l(I) = sum over admissible (I, J) of S_IJ xh_l(J)
   for (int l = lo; l <= L; ++l) {
     const LevelNodes& ln = s.lev[l];
     TaskList t;
@@ -425,39 +376,29 @@ void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64
       for (int q : byrow[I]) t.add_task(enc(q), enc(ln.col[q]));
       t.close(enc(I));
     }
-    if (t.nout() == 0) continue;
-    TmpList d = mk(t);
-    Op A{M->S[l].d(), nullptr, (long long)M->rr[l] * M->rc[l], 0, M->rr[l], 0, 0};
-    Op B{xh[l].d(), nullptr, (long long)M->rc[l] * R, 0, M->rc[l], 0, 0};
-    gemm(st, nullptr, 0, d.d, M->rr[l], R, M->rc[l], A, false, B, false, yh[l].d(),
-         (long long)M->rr[l] * R, M->rr[l], 0, 0, 1.0, 1.0);
+    lists.push_back(std::move(t));
   }
-  // backward
+  // backward, level l < L: yh_{l+1}(c) += E_c yh_l(parent)
   for (int l = lo; l < L; ++l) {
     TaskList t;
     for (int c = 0; c < (2 << l); ++c) {
       t.add_task(enc(c >> 1, c & 1), enc(c >> 1));
       t.close(enc(c));
     }
-    TmpList d = mk(t);
-    Op A{M->Tr[l].d(), nullptr, M->Tr_stride[l], 0, 2 * M->rr[l + 1], M->rr[l + 1], 0};
-    Op B{yh[l].d(), nullptr, (long long)M->rr[l] * R, 0, M->rr[l], 0, 0};
-    gemm(st, nullptr, 0, d.d, M->rr[l + 1], R, M->rr[l], A, false, B, false, yh[l + 1].d(),
-         (long long)M->rr[l + 1] * R, M->rr[l + 1], 0, 0, 1.0, 1.0);
+    lists.push_back(std::move(t));
   }
+  // leaves: y_c = V_c yh_L(c)
   {
     TaskList t;
     for (int c = 0; c < nleaf; ++c) {
       t.add_task(enc(c), enc(c));
       t.close(enc(c));
     }
-    TmpList d = mk(t);
-    Op A{M->V.d(), nullptr, M->V_stride, 0, np, 0, 0};
-    Op B{yh[L].d(), nullptr, (long long)M->rr[L] * R, 0, M->rr[L], 0, 0};
-    gemm(st, nullptr, 0, d.d, np, R, M->rr[L], A, false, B, false, yt.d(), np, (int)ldx, 0, 0,
-         1.0, 0.0);
+    lists.push_back(std::move(t));
   }
+  // dense near field: y_I += sum over dense (I, J) of F_IJ x_J
   {
+    const LevelNodes& lf = s.lev[L];
     TaskList t;
     std::vector<std::vector<int>> byrow(nleaf);
     for (int q = 0; q < lf.size(); ++q)
@@ -467,13 +408,146 @@ void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64
       for (int q : byrow[I]) t.add_task(enc(q), enc(lf.col[q]));
       t.close(enc(I));
     }
-    TmpList d = mk(t);
+    lists.push_back(std::move(t));
+  }
+  size_t total = 0;
+  for (const TaskList& t : lists) total += t.out.size() + t.seg.size() + t.a.size() + t.b.size();
+  mp->host.resize(total + 1);
+  mp->mem = Buf(ctx, (total + 1) * sizeof(int));
+  int* base = mp->mem.as<int>();
+  size_t off = 0;
+  for (const TaskList& t : lists) {
+    DevList d;
+    d.nout = t.nout();
+    d.ntask = t.ntask();
+    auto put = [&](const std::vector<int>& v) -> const int* {
+      std::copy(v.begin(), v.end(), mp->host.begin() + off);
+      const int* r = base + off;
+      off += v.size();
+      return r;
+    };
+    d.out = put(t.out);
+    d.seg = put(t.seg);
+    d.a = put(t.a);
+    d.b = put(t.b);
+    scan_limits(t, d);
+    mp->lists.push_back(d);
+  }
+  H2_HIP(hipMemcpyAsync(base, mp->host.data(), total * sizeof(int), hipMemcpyHostToDevice,
+                        ctx->stream));
+  M->mv = std::move(mp);
+}
+
+// Device bytes of the mat-vec temporaries of M for nrhs right-hand sides
+// (each part rounded to 256 bytes).
+size_t matvec_scratch_bytes(const h2_mat_s* M, int64_t nrhs) {
+  const Structure& s = M->st();
+  const int L = s.L;
+  const size_t nc = M->cplx ? 2 : 1;
+  auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t b = 2 * r256((size_t)(1 << L) * s.npad * nrhs * nc * sizeof(double));
+  for (int l = s.lmin; l <= L; ++l)
+    b += r256((size_t)(1 << l) * M->rc[l] * nrhs * nc * sizeof(double)) +
+         r256((size_t)(1 << l) * M->rr[l] * nrhs * nc * sizeof(double));
+  return b;
+}
+
+// Exact H^2 mat-vec (the reference solution of equation `error`) on stream
+// st.  scratch (nullable): a device region of scratch_bytes for the
+// temporaries, checked against their size before any launch; without one
+// they come from the context's pool.
+void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64_t nrhs,
+                 hipStream_t st, void* scratch, size_t scratch_bytes) {
+  ActiveCtx active(ctx);
+  const Structure& s = M->st();
+  Shape& sh = *M->shape;
+  if (!M->mv) build_matvec_plan(ctx, M);
+  const std::vector<DevList>& ml = M->mv->lists;
+  const int L = s.L, np = s.npad, nleaf = 1 << L;
+  const int lo = s.lmin;  // no admissible block above lmin
+  const long long nt = (long long)nleaf * np;
+  const int R = (int)nrhs;
+  // complex: x and y planar (n x nrhs real parts, then the imaginary parts),
+  // gathered and scattered as 2 nrhs real columns
+  const int nc = M->cplx ? 2 : 1;
+  const bool cx = M->cplx;
+  // temporaries: pool buffers, or consecutive parts of the caller's region
+  // registered with the context for the launches' extent checks
+  std::vector<Buf> owned;
+  std::vector<ExtRegion> regions;
+  char* cursor = (char*)scratch;
+  if (scratch && matvec_scratch_bytes(M, nrhs) > scratch_bytes)
+    throw Error(H2_ERR_UNSUPPORTED,
+                "the mat-vec temporaries (" + std::to_string(matvec_scratch_bytes(M, nrhs)) +
+                    " bytes) exceed the scratch region of " + std::to_string(scratch_bytes) +
+                    " bytes");
+  regions.reserve(2 * (L + 2));
+  auto take = [&](size_t bytes) -> double* {
+    if (!scratch) {
+      owned.emplace_back(ctx, bytes, false, cx);
+      return owned.back().d();
+    }
+    double* p = (double*)cursor;
+    cursor += (bytes + 255) & ~(size_t)255;
+    regions.emplace_back(ctx, p, bytes, cx);
+    return p;
+  };
+  owned.reserve(2 * (L + 2));
+  double* xt = take(nt * R * nc * sizeof(double));
+  double* yt = take(nt * R * nc * sizeof(double));
+  H2_HIP(h2k::launch_gather_rows(x_dev, xt, sh.d_perm.as<long long>(),
+                                 sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R * nc, st));
+  std::vector<double*> xh(L + 1, nullptr), yh(L + 1, nullptr);
+  for (int l = lo; l <= L; ++l) {
+    xh[l] = take((size_t)(1 << l) * M->rc[l] * R * nc * sizeof(double));
+    yh[l] = take((size_t)(1 << l) * M->rr[l] * R * nc * sizeof(double));
+    // a fill kernel, not a memset (the call may be captured in a graph)
+    H2_HIP(h2k::launch_fill(yh[l], 0.0, (long long)(1 << l) * M->rr[l] * R * nc, st));
+  }
+  const long long ldx = nt;
+  size_t li = 0;
+  // forward
+  {
+    Op A{M->W.d(), nullptr, M->W_stride, 0, np, 0, 0};
+    Op B{xt, nullptr, np, 0, (int)ldx, 0, 0};
+    gemm(st, nullptr, 0, ml[li++], M->rc[L], R, np, A, true, B, false, xh[L],
+         (long long)M->rc[L] * R, M->rc[L], 0, 0, 1.0, 0.0);
+  }
+  for (int l = L - 1; l >= lo; --l) {
+    Op A{M->Tc[l].d(), nullptr, M->Tc_stride[l], 0, 2 * M->rc[l + 1], M->rc[l + 1], 0};
+    Op B{xh[l + 1], nullptr, (long long)M->rc[l + 1] * R, 0, M->rc[l + 1], 0, 0};
+    gemm(st, nullptr, 0, ml[li++], M->rc[l], R, M->rc[l + 1], A, true, B, false, xh[l],
+         (long long)M->rc[l] * R, M->rc[l], 0, 0, 1.0, 0.0);
+  }
+  // couplings
+  for (int l = lo; l <= L; ++l) {
+    const DevList& d = ml[li++];
+    if (d.nout == 0) continue;
+    Op A{M->S[l].d(), nullptr, (long long)M->rr[l] * M->rc[l], 0, M->rr[l], 0, 0};
+    Op B{xh[l], nullptr, (long long)M->rc[l] * R, 0, M->rc[l], 0, 0};
+    gemm(st, nullptr, 0, d, M->rr[l], R, M->rc[l], A, false, B, false, yh[l],
+         (long long)M->rr[l] * R, M->rr[l], 0, 0, 1.0, 1.0);
+  }
+  // backward
+  for (int l = lo; l < L; ++l) {
+    Op A{M->Tr[l].d(), nullptr, M->Tr_stride[l], 0, 2 * M->rr[l + 1], M->rr[l + 1], 0};
+    Op B{yh[l], nullptr, (long long)M->rr[l] * R, 0, M->rr[l], 0, 0};
+    gemm(st, nullptr, 0, ml[li++], M->rr[l + 1], R, M->rr[l], A, false, B, false, yh[l + 1],
+         (long long)M->rr[l + 1] * R, M->rr[l + 1], 0, 0, 1.0, 1.0);
+  }
+  {
+    Op A{M->V.d(), nullptr, M->V_stride, 0, np, 0, 0};
+    Op B{yh[L], nullptr, (long long)M->rr[L] * R, 0, M->rr[L], 0, 0};
+    gemm(st, nullptr, 0, ml[li++], np, R, M->rr[L], A, false, B, false, yt, np, (int)ldx, 0, 0,
+         1.0, 0.0);
+  }
+  {
     Op A{M->F.d(), nullptr, (long long)np * np, 0, np, 0, 0};
-    Op B{xt.d(), nullptr, np, 0, (int)ldx, 0, 0};
-    gemm(st, nullptr, 0, d.d, np, R, np, A, false, B, false, yt.d(), np, (int)ldx, 0, 0, 1.0,
+    Op B{xt, nullptr, np, 0, (int)ldx, 0, 0};
+    gemm(st, nullptr, 0, ml[li++], np, R, np, A, false, B, false, yt, np, (int)ldx, 0, 0, 1.0,
          1.0);
   }
-  H2_HIP(h2k::launch_scatter_rows(yt.d(), y_dev, sh.d_perm.as<long long>(),
+  H2_HIP(h2k::launch_scatter_rows(yt, y_dev, sh.d_perm.as<long long>(),
                                   sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R * nc, st));
 }
 
@@ -835,6 +909,7 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
     M->stats.L = L;
     M->stats.lmin = s.lmin;
     M->stats.sparsity_constant = s.sparsity_constant();
+    build_matvec_plan(ctx, M.get());
     *out = M.release();
     return H2_OK;
   } catch (const Error& e) {
@@ -954,13 +1029,13 @@ h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nr
     const long long len = n * nrhs * (M->cplx ? 2 : 1);
     if (x_on_device) {
       fence_in(ctx, stream);
-      matvec_impl(ctx, M, x, y, nrhs);
+      matvec_impl(ctx, M, x, y, nrhs, ctx->stream);
       fence_out(ctx, stream);
     } else {
       Buf xd(ctx, len * sizeof(double)), yd(ctx, len * sizeof(double));
       fence_in(ctx, stream);
       H2_HIP(hipMemcpyAsync(xd.d(), x, len * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-      matvec_impl(ctx, M, xd.d(), yd.d(), nrhs);
+      matvec_impl(ctx, M, xd.d(), yd.d(), nrhs, ctx->stream);
       H2_HIP(hipMemcpyAsync(y, yd.d(), len * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
       H2_HIP(hipStreamSynchronize(ctx->stream));
     }
@@ -990,7 +1065,7 @@ h2_status h2_to_dense(h2_ctx ctx, h2_mat M, double* out, int64_t ld) {
     Buf xd(ctx, nn * nc * sizeof(double)), yd(ctx, nn * nc * sizeof(double));
     H2_HIP(hipMemcpyAsync(xd.d(), eye.data(), nn * nc * sizeof(double), hipMemcpyHostToDevice,
                           ctx->stream));
-    matvec_impl(ctx, M, xd.d(), yd.d(), n);
+    matvec_impl(ctx, M, xd.d(), yd.d(), n, ctx->stream);
     H2_HIP(hipMemcpyAsync(eye.data(), yd.d(), nn * nc * sizeof(double), hipMemcpyDeviceToHost,
                           ctx->stream));
     H2_HIP(hipStreamSynchronize(ctx->stream));

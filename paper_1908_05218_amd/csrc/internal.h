@@ -76,6 +76,9 @@ struct h2_ctx_s {
   bool has_hook = false;
   std::multimap<size_t, void*> pool;
   std::unordered_map<void*, size_t> live;
+  // device regions a call uses that the context did not allocate (the
+  // allocation-free mat-vec's scratch parts), for the launches' extent checks
+  std::unordered_map<void*, size_t> ext;
   std::unordered_set<void*> f32;  // live allocations that hold float elements
   // live complex allocations: [real plane | imaginary plane] of doubles, the
   // value is the plane's length in elements
@@ -164,6 +167,35 @@ struct DevPlan {
   const DevList& get(const TaskList& t) const { return lists.at(&t); }
 };
 
+// Registers a caller-owned device region with a context for the duration of
+// a call (extent checks; complex regions also as two planes).
+struct ExtRegion {
+  h2_ctx c = nullptr;
+  void* p = nullptr;
+  ExtRegion(h2_ctx ctx, void* ptr, size_t bytes, bool cplx) : c(ctx), p(ptr) {
+    c->ext[p] = bytes;
+    if (cplx) c->planes[p] = (long long)(bytes / 16);
+  }
+  ExtRegion(ExtRegion&& o) noexcept : c(o.c), p(o.p) { o.c = nullptr; }
+  ExtRegion(const ExtRegion&) = delete;
+  ExtRegion& operator=(const ExtRegion&) = delete;
+  ExtRegion& operator=(ExtRegion&&) = delete;
+  ~ExtRegion() {
+    if (c) {
+      c->ext.erase(p);
+      c->planes.erase(p);
+    }
+  }
+};
+
+// Task lists of M's exact mat-vec (uploaded once; the host copy is kept so
+// the upload needs no wait).
+struct MatvecPlan {
+  Buf mem;
+  std::vector<int> host;
+  std::vector<DevList> lists;
+};
+
 struct Shape {
   Structure s;
   std::unique_ptr<Plan> plan;
@@ -198,6 +230,8 @@ struct h2_mat_s {
   // context's stream); mmp_ms is read from them once they have completed
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
   bool timing_pending = false;
+  // task lists of the exact mat-vec (built when M is made)
+  std::unique_ptr<h2::MatvecPlan> mv;
   const h2::Structure& st() const { return shape->s; }
   // wait for the launches of the call that produced M; fills mmp_ms
   void finish();
@@ -291,6 +325,12 @@ inline h2_ctx home_of(h2_ctx ctx, const h2_mat_s* M) {
 // stop a context's serving worker (after its current request) and drop the
 // requests still queued; no-op without one
 void stop_server(h2_ctx ctx);
-void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64_t nrhs);
+void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64_t nrhs,
+                 hipStream_t st, void* scratch = nullptr, size_t scratch_bytes = 0);
+void build_matvec_plan(h2_ctx ctx, h2_mat M);
+// locates the allocation-free mat-vec's scratch array on `device` (current)
+// once per device; sets the error message on failure
+h2_status noalloc_setup(int device);
+size_t matvec_scratch_bytes(const h2_mat_s* M, int64_t nrhs);
 
 }  // namespace h2

@@ -849,6 +849,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     S.other_launches = pl[kKindOther];
     S.other_flops = pfl[kKindOther];
   }
+  build_matvec_plan(ctx, C.get());
   *C_out = C.release();
   return H2_OK;
 }
