@@ -277,6 +277,28 @@ h2_status h2_sync(h2_mat M);
 h2_status h2_matvec(h2_ctx ctx, h2_mat M, const double* x, double* y, int64_t nrhs,
                     int x_on_device, hipStream_t stream);
 
+/* Allocation-free variant of h2_matvec with device vectors, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation).  y = M x as h2_matvec computes it (the
+ * same kernels in the same order: identical results).  x_dev, y_dev: device
+ * memory, n x nrhs column-major (complex M: planar, as in h2_matvec).  The
+ * temporaries live in a library-wide device array of H2_MATVEC_SCRATCH_BYTES
+ * per device, located when the first context on that device is created and
+ * held until the process ends; they take 2 npad 2^L + sum over the levels
+ * l_min..L of 2^l (rr_l + rc_l) doubles per right-hand side (twice for
+ * complex M; npad, rr, rc the padded leaf size and ranks), each part rounded
+ * to 256 bytes.  The work is launched on `stream` (null: the context's
+ * stream) with no host wait, no event and no memset; M must be complete
+ * (h2_sync after an h2_mmp on a caller stream).  Every call on one device
+ * shares the array and it keeps the last call's contents: calls that overlap
+ * on one GPU (other contexts or streams) race and must be serialised by the
+ * caller.  Errors: H2_ERR_ARG (null pointers, nrhs < 1, M of another
+ * context), H2_ERR_UNSUPPORTED (temporaries beyond the array; nothing is
+ * launched). */
+#define H2_MATVEC_SCRATCH_BYTES ((size_t)64 << 20)
+h2_status h2_matvec_noalloc(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev,
+                            int64_t nrhs, hipStream_t stream);
+
 /* Dense M (original order) into host memory `out` (column-major, ld >= n;
  * complex M: interleaved pairs, ld in complex elements).  Only for
  * n <= 16384 (H2_ERR_UNSUPPORTED above). */

@@ -110,6 +110,7 @@ def lib():
         L.h2_mmp.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.c_int, vp, C.POINTER(vp)]
         L.h2_matvec.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int, vp]
         L.h2_sync.argtypes = [vp]
+        L.h2_matvec_noalloc.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
         L.h2_to_dense.argtypes = [vp, vp, vp, C.c_int64]
         L.h2_export_size.argtypes = [vp, C.POINTER(_ExportSizes)]
         L.h2_export.argtypes = [vp, C.POINTER(_ExportBuffers)]
@@ -131,7 +132,7 @@ def lib():
         for f in ("h2_ctx_create", "h2_load", "h2_build", "h2_submit", "h2_poll", "h2_wait",
                   "h2_release", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
                   "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling", "h2_serve_slots",
-                  "h2_save", "h2_load_file", "h2_sync"):
+                  "h2_save", "h2_load_file", "h2_sync", "h2_matvec_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -436,6 +437,24 @@ def matvec(ctx, M, x, stream=None):
     _check(lib().h2_matvec(ctx.h, M.h, X.ctypes.data_as(C.c_void_p), Y.ctypes.data_as(C.c_void_p),
                            X.shape[1], 0, None))
     return Y[:, 0] if vec else Y
+
+
+def matvec_noalloc(ctx, M, x, y, stream=None):
+    """y = M x through h2_matvec_noalloc: x, y torch tensors on the GPU
+    (float64, n x nrhs, column-major: x.t() contiguous), nothing allocated
+    by the call; launched on `stream` (a torch stream or handle), else on the
+    context's stream.  Complex M: x, y planar (real parts, then imaginary
+    parts) in tensors of 2 n nrhs doubles."""
+    nrhs = x.numel() // ((2 if is_complex(M) else 1) * _npoints(M))
+    _check(lib().h2_matvec_noalloc(ctx.h, M.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                   nrhs, _stream_handle(stream)))
+
+
+def _npoints(M):
+    """Number of points of M."""
+    sz = _ExportSizes()
+    _check(lib().h2_export_size(M.h, C.byref(sz)))
+    return int(sz.n)
 
 
 def to_dense(ctx, M, n):

@@ -721,6 +721,11 @@ h2_status h2_ctx_create(int device, size_t hbm_budget, const h2_allocator* alloc
     delete c;
     return h2::set_error(H2_ERR_DEVICE, "hipStreamCreate failed");
   }
+  // the allocation-free mat-vec's scratch array of this device
+  if (h2::noalloc_setup(device) != H2_OK) {
+    delete c;
+    return H2_ERR_DEVICE;  // message set by noalloc_setup
+  }
   *out = c;
   return H2_OK;
 }
