@@ -601,7 +601,7 @@ template <int NT, int SL, bool PL>
 __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* Gc, int n, int k1,
                                                int half, int D, double* P, double* Pg,
                                                double* dd, double* ee, double* vv,
-                                               double* ybuf, double* trash) {
+                                               double* ybuf, double* trash, int stop) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   // 1. gather the live block, packed lower triangle
@@ -620,8 +620,9 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
   __syncthreads();
 
   // 2. Householder tridiagonalisation (lower); reflector u_i (unit norm,
-  // H_i = I - 2 u_i u_i^T) kept in column i of Pg
-  for (int i = 0; i + 2 < n; ++i) {
+  // H_i = I - 2 u_i u_i^T) kept in column i of Pg.  With stop < n - 2 only
+  // the first `stop` steps run and the trailing block stays in P
+  for (int i = 0; i + 2 < n && i < stop; ++i) {
     const int m = n - i - 1;
     const int ci = cs(i, n);
     double xr[SL], ur[SL];
@@ -778,7 +779,7 @@ __device__ __forceinline__ void gather_tridiag(const EigArgs& p, const double* G
     }
     __syncthreads();
   }
-  if (tid == 0) {
+  if (tid == 0 && stop >= n - 2) {
     if (n >= 2) {
       dd[n - 2] = P[cs(n - 2, n)];
       dd[n - 1] = P[cs(n - 1, n)];
@@ -843,14 +844,14 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
 
   // 5. Gram-Schmidt with re-orthogonalisation over all kept vectors, in
   // blocks (coefficients in the contiguous pv | ybuf region of LDS)
-  if constexpr (SL <= 4 && NW >= 4)
+  if constexpr (SL <= 5 && NW >= 4)
     bcgs2_waves<NT, SL>(Z, ldz, n, k);
   else
     bcgs2<NT, SL>(Z, ldz, n, k, pv, dv + NT);
 
   // 6. back-transformation: z <- H_0 ... H_{n-3} z, VB vectors per wave
   // (eight with four row slots: their dot products share one batched wave sum)
-  constexpr int VB = SL > 8 ? 2 : SL > 4 ? kVB : 8;
+  constexpr int VB = SL > 8 ? 2 : SL > 5 ? kVB : 8;
   for (int b0 = wave * VB; b0 < k; b0 += NW * VB) {
     double z[VB][SL];
 #pragma unroll
@@ -958,8 +959,11 @@ __host__ __device__ __forceinline__ int partials_len(int dv, int nt) {
 
 // Kernel 1: gather and tridiagonalise; zero the output columns.  LDS: packed
 // triangle [zr] | d[dv] | e[dv] | v[dv] | p-partials[partials_len] | red[8].
+// split: reduce only the leading n - kEigRegN columns (none when n <= kEigRegN)
+// and leave the trailing block, packed in the cluster's scratch, to
+// k_eig_tri_reg
 template <int NT, int SL>
-__global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, int dv) {
+__global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, int dv, int split) {
   extern __shared__ double sm[];
   const EigArgs& p = blockIdx.y == 0 ? p0 : p1;
   const ClusterView v = cluster_view(p);
@@ -975,6 +979,8 @@ __global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, 
   }
   const int n = v.n;
   const int np = n * (n + 1) / 2;
+  const int stop = split ? (n > kEigRegN ? n - kEigRegN : 0) : n;
+  if (stop == 0) return;
   double* dd = sm + zr;
   double* ee = dd + dv;
   double* vv = ee + dv;
@@ -983,12 +989,15 @@ __global__ __launch_bounds__(NT) void k_eig_tri(EigArgs p0, EigArgs p1, int zr, 
   const double* Gc = p.G + (long long)v.c * p.gstride;
   // trash slot of the update: the unused reduction slots in LDS, or the unused
   // factor area of the scratch when the triangle is not in LDS
-  if (n <= kEigLdsN && np <= zr)
-    gather_tridiag<NT, SL, true>(p, Gc, n, v.k1, v.half, v.D, sm, v.S, dd, ee, vv, ybuf, ybuf + yb);
+  if (!split && n <= kEigLdsN && np <= zr)
+    gather_tridiag<NT, SL, true>(p, Gc, n, v.k1, v.half, v.D, sm, v.S, dd, ee, vv, ybuf, ybuf + yb,
+                                 stop);
   else
     gather_tridiag<NT, SL, false>(p, Gc, n, v.k1, v.half, v.D, v.S, v.S, dd, ee, vv, ybuf,
-                              v.S + (long long)v.D * v.D);
-  for (int j = tid; j < n; j += NT) {
+                              v.S + (long long)v.D * v.D, stop);
+  // with a split, d and e of the finished columns only
+  const int ndone = stop < n ? stop : n;
+  for (int j = tid; j < ndone; j += NT) {
     v.tri[j] = dd[j];
     v.tri[v.D + j] = j < n - 1 ? ee[j] : 0.0;
   }
@@ -1050,9 +1059,12 @@ __device__ __forceinline__ double butterfly16(const double* t, int lane) {
 }
 
 // RS: 64-row slots per lane (NW / 2 for four and eight waves, fewer when the
-// dimension allows: three for D <= 192 with eight waves)
+// dimension allows: three for D <= 192 with eight waves).  split: a cluster
+// with n > kEigRegN had its leading n - kEigRegN columns reduced by k_eig_tri;
+// this kernel loads the trailing block from the packed matrix in the
+// cluster's scratch and finishes the reduction (global step i0 + i)
 template <int NW, int RS>
-__global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1, int dv) {
+__global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1, int dv, int split) {
   constexpr int NT = NW * 64, J = kRegCols, RM = 64 * RS;
   // a group of 16 columns has cross-block (transposed) terms when its first
   // column's block is not the last one
@@ -1067,20 +1079,23 @@ __global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1,
   const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   double* Uc = p.U + (long long)v.c * p.ustride;
   for (long long e = tid; e < (long long)v.D * v.D; e += NT) Uc[e] = 0.0;
-  if (!v.ok || v.D > dv || v.n > NW * J || v.n > RM) {
+  const int ng = v.n;  // the cluster's dimension; this kernel reduces [i0, ng)
+  const int i0 = (split && ng > kEigRegN) ? ng - kEigRegN : 0;
+  if (!v.ok || v.D > dv || ng - i0 > NW * J || ng - i0 > RM) {
     if (tid == 0) {
       p.rank[v.c] = 0;
       if (v.n != 0) p.status[1] = 1;
     }
     return;
   }
-  const int n = v.n;
+  const int n = ng - i0;
   double* Pg = v.S;
   const double* Gc = p.G + (long long)v.c * p.gstride;
 
   // gather the live block (rows and columns [0,k1) and [half, half+k2));
   // only the Gram's lower triangle is read (entries above the diagonal of
-  // the diagonal blocks from their mirror images)
+  // the diagonal blocks from their mirror images).  After a split: the
+  // trailing block from the packed lower triangle (column c at cs(c, ng))
   double a[J][RS];
   int bad = 0;
 #pragma unroll
@@ -1092,9 +1107,14 @@ __global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1,
       const int r = lane + 64 * s;
       double x = 0.0;
       if (c < n && r < n) {
-        const int orow = r < v.k1 ? r : v.half + (r - v.k1);
-        x = r >= c ? Gc[orow + (long long)oc * v.D] : Gc[oc + (long long)orow * v.D];
-        if (!(x == x) || x - x != 0.0) bad = 1;
+        if (i0 > 0) {
+          const int gr = i0 + r, gc = i0 + c;
+          x = gr >= gc ? Pg[cs(gc, ng) + gr - gc] : Pg[cs(gr, ng) + gc - gr];
+        } else {
+          const int orow = r < v.k1 ? r : v.half + (r - v.k1);
+          x = r >= c ? Gc[orow + (long long)oc * v.D] : Gc[oc + (long long)orow * v.D];
+          if (!(x == x) || x - x != 0.0) bad = 1;
+        }
       }
       a[j][s] = x;
     }
@@ -1129,7 +1149,8 @@ __global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1,
     const double x0 = col[i + 1];
     const double diag = col[i];
     const double nx = sqrt(xx);
-    const long long ci = (long long)i * n - ((long long)i * (i - 1)) / 2;
+    // packed column of the global step i0 + i (rows r > i lie at ci + r - i)
+    const long long ci = cs(i0 + i, ng);
     if (!(nx > 0.0)) {  // column already reduced: H_i = I, A unchanged
       if (w == 0) {
 #pragma unroll
@@ -1276,8 +1297,8 @@ __global__ __launch_bounds__(NW * 64) void k_eig_tri_reg(EigArgs p0, EigArgs p1,
   }
   __syncthreads();
   for (int j = tid; j < n; j += NT) {
-    v.tri[j] = dd[j];
-    v.tri[v.D + j] = j < n - 1 ? ee[j] : 0.0;
+    v.tri[i0 + j] = dd[j];
+    v.tri[v.D + i0 + j] = j < n - 1 ? ee[j] : 0.0;
   }
 }
 
@@ -1496,15 +1517,19 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
     bool done = false;
     if constexpr (NW == 8) {
       if (D <= 192) {
-        hipLaunchKernelGGL((k_eig_tri_reg<8, 3>), grid, dim3(NT), 0, s, a, b, D);
+        hipLaunchKernelGGL((k_eig_tri_reg<8, 3>), grid, dim3(NT), 0, s, a, b, D, 0);
         done = true;
       }
     }
-    if (!done) hipLaunchKernelGGL((k_eig_tri_reg<NW, RS>), grid, dim3(NT), 0, s, a, b, D);
-  } else
+    if (!done) hipLaunchKernelGGL((k_eig_tri_reg<NW, RS>), grid, dim3(NT), 0, s, a, b, D, 0);
+  } else {
+    // the leading n - kEigRegN columns with the matrix in the cluster's
+    // scratch, the trailing kEigRegN with the matrix in registers
     hipLaunchKernelGGL((k_eig_tri<NT, SL>), grid, dim3(NT),
                        sizeof(double) * ((size_t)zt + 3 * D + partials_len(D, NT) + kRed), s, a, b,
-                       zt, D);
+                       zt, D, 1);
+    hipLaunchKernelGGL((k_eig_tri_reg<8, 4>), grid, dim3(512), 0, s, a, b, D, 1);
+  }
   hipLaunchKernelGGL(k_eig_val<NT>, grid, dim3(NT), sizeof(double) * (4 * (size_t)D + kRed), s, a,
                      b, D);
   const size_t lv = sizeof(double) * ((size_t)zv + 4 * D + NT + kRed);
@@ -1524,7 +1549,8 @@ hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStre
     return hipErrorInvalidValue;
   // SL row slots per lane: a wave holds a column of up to 64 SL rows
   if (D > 512) return launch_nt<512, 16>(a, b, nclusters, D, s);
-  if (D > 256) return launch_nt<512, 8>(a, b, nclusters, D, s);
+  if (D > 320) return launch_nt<512, 8>(a, b, nclusters, D, s);
+  if (D > 256) return launch_nt<512, 5>(a, b, nclusters, D, s);
   switch (eig_threads(D)) {
     // row slots per lane: as many as the dimension needs (fewer registers
     // and no padding work in the eigenvector phases)

@@ -128,6 +128,7 @@ hipError_t launch_ceig_extract(const CEigArgs& a, const CEigArgs& b, int ncluste
 
 constexpr int kEigNmax = 1024;  // largest Gram dimension
 constexpr int kEigLdsN = 195;  // largest dimension whose packed triangle stays in LDS
+constexpr int kEigRegN = 256;  // largest dimension the register-resident reduction holds
 // scratch per cluster (doubles) the eigensolver needs for padded dimension D
 inline long long eig_scratch_doubles(int D) { return 7LL * D * D + 4LL * D + 8; }
 
