@@ -339,3 +339,50 @@ def test_fixed_basis_error_well_above_proposed():
         Ca, _ = mmp.h2_mmp(A, A, 1e-4)
         ef, ea = rel(h2ops.to_dense(Cf), ref), rel(h2ops.to_dense(Ca), ref)
         assert ef > 10 * ea and ea <= 1e-4, (ef, ea)
+
+
+# ------------------------------------------------------------ Newton-Schulz inverse
+def _ns_dense(D, alpha, steps):
+    X = alpha * np.eye(D.shape[0])
+    for _ in range(steps):
+        X = X @ (2.0 * np.eye(D.shape[0]) - D @ X)
+    return X
+
+
+def test_newton_schulz_exact_mode_equals_dense_iteration():
+    """With exact products every iterate equals the dense Newton-Schulz
+    iterate, in both a symmetric and a non-symmetric (complex) case."""
+    from oracle import inverse
+    A = cases.plates(1024, leaf=16, order=2)
+    D = h2ops.to_dense(A)
+    alpha = 1.0 / np.linalg.eigvalsh(D).max()
+    for steps in (1, 4):
+        X, _ = inverse.newton_schulz(A, 0.0, alpha, steps)
+        ref = _ns_dense(D, alpha, steps)
+        assert rel(h2ops.to_dense(X), ref) < 1e-12
+    Ac, _ = cases.random_pair(512, 16, 6, 5, 11, complex_=True)
+    Dc = h2ops.to_dense(Ac)
+    a = 0.5 / np.linalg.norm(Dc, 2) ** 2
+    # for a general matrix the iteration runs on A^H-scaled starts; here only
+    # the algebra of the first steps is compared
+    X, _ = inverse.newton_schulz(Ac, 0.0, a, 3)
+    assert rel(h2ops.to_dense(X), _ns_dense(Dc, a, 3)) < 1e-12
+
+
+def test_newton_schulz_converges_to_the_inverse():
+    """Symmetric positive definite A, alpha = 1/lambda_max: the residual
+    falls quadratically once below 1/2 and the limit is the inverse of the
+    dense matrix within the product's accuracy."""
+    from oracle import inverse
+    from h2inputs import vectors
+    A = cases.plates(1024)
+    D = h2ops.to_dense(A)
+    w = np.linalg.eigvalsh(D)
+    X, res = inverse.newton_schulz(A, 1e-6, 1.0 / w.max(), 12, probes=vectors.probes(A.n, 2, 7))
+    # I - A X_{j+1} = (I - A X_j)^2: the probe residual falls about quadratically
+    for a, b in zip(res, res[1:]):
+        if 1e-8 < a < 0.1:
+            assert b < 10 * a * a + 1e-10
+    assert res[-1] < 1e-8
+    Ainv = np.linalg.inv(D)
+    assert rel(h2ops.to_dense(X), Ainv) < 1e-8
