@@ -265,6 +265,25 @@ h2_status h2_mmp(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int trunc_mode, int
  * H2_ERR_DEVICE (a failed launch). */
 h2_status h2_sync(h2_mat M);
 
+/* a M + b I as a new matrix (a, b real): M's partition and bases, couplings
+ * and dense blocks scaled by a, b added to the diagonal of the dense diagonal
+ * leaf blocks (the identity of the partition lives there).  Errors:
+ * H2_ERR_ARG (null pointers, non-finite a or b, M of another context),
+ * H2_ERR_OOM. */
+h2_status h2_scale_shift(h2_ctx ctx, h2_mat M, double a, double b, h2_mat* out);
+
+/* Approximate inverse by repeated products (the use Section I names for the
+ * product: inverse-based fast solvers): Newton-Schulz iteration
+ * X_{j+1} = X_j (2 I - A X_j) from X_1 = 2 alpha I - alpha^2 A, `steps`
+ * iterates (steps - 1 rounds of two h2_mmp at eps, trunc_mode and precision,
+ * and one h2_scale_shift).  For A with eigenvalues in (0, 1/alpha] (e.g.
+ * symmetric positive definite, alpha <= 1/lambda_max) the residual I - A X_j
+ * squares every step until the truncation limits it.  X has A's partition.
+ * Synchronous.  Errors: H2_ERR_ARG (steps < 1, alpha <= 0), and those of
+ * h2_mmp. */
+h2_status h2_newton_schulz(h2_ctx ctx, h2_mat A, double alpha, int steps, double eps,
+                           int trunc_mode, int precision, h2_mat* X_out);
+
 /* y = M x for nrhs right-hand sides, x and y n x nrhs column-major in the
  * original point order, host memory (x_on_device = 0) or device memory
  * (x_on_device = 1, both pointers device); complex M: x and y hold the

@@ -110,6 +110,9 @@ def lib():
         L.h2_mmp.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.c_int, vp, C.POINTER(vp)]
         L.h2_matvec.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int, vp]
         L.h2_sync.argtypes = [vp]
+        L.h2_scale_shift.argtypes = [vp, vp, C.c_double, C.c_double, C.POINTER(vp)]
+        L.h2_newton_schulz.argtypes = [vp, vp, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int,
+                                       C.POINTER(vp)]
         L.h2_matvec_noalloc.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
         L.h2_to_dense.argtypes = [vp, vp, vp, C.c_int64]
         L.h2_export_size.argtypes = [vp, C.POINTER(_ExportSizes)]
@@ -132,7 +135,8 @@ def lib():
         for f in ("h2_ctx_create", "h2_load", "h2_build", "h2_submit", "h2_poll", "h2_wait",
                   "h2_release", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
                   "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling", "h2_serve_slots",
-                  "h2_save", "h2_load_file", "h2_sync", "h2_matvec_noalloc"):
+                  "h2_save", "h2_load_file", "h2_sync", "h2_matvec_noalloc",
+                  "h2_scale_shift", "h2_newton_schulz"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -380,6 +384,21 @@ def mmp(ctx, A, B, eps, mode="accuracy", precision="fp64", stream=None):
     h = C.c_void_p()
     _check(lib().h2_mmp(ctx.h, A.h, B.h, float(eps), TRUNC[mode], PREC[precision],
                         _stream_handle(stream), C.byref(h)))
+    return Matrix(ctx, h)
+
+
+def scale_shift(ctx, M, a, b):
+    """a M + b I (same partition and bases) as a new matrix."""
+    h = C.c_void_p()
+    _check(lib().h2_scale_shift(ctx.h, M.h, float(a), float(b), C.byref(h)))
+    return Matrix(ctx, h)
+
+
+def newton_schulz(ctx, A, alpha, steps, eps, mode="accuracy", precision="fp64"):
+    """Newton-Schulz approximate inverse X_steps of A (h2_newton_schulz)."""
+    h = C.c_void_p()
+    _check(lib().h2_newton_schulz(ctx.h, A.h, float(alpha), int(steps), float(eps), TRUNC[mode],
+                                  PREC[precision], C.byref(h)))
     return Matrix(ctx, h)
 
 

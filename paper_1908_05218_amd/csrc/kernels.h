@@ -170,6 +170,10 @@ hipError_t launch_build_coupling(const BuildCouplingArgs& a, hipStream_t s);
 hipError_t launch_build_dense(const BuildDenseArgs& a, hipStream_t s);
 
 hipError_t launch_fill(double* p, double v, long long n, hipStream_t s);
+hipError_t launch_scale(double* p, double a, long long n, hipStream_t s);
+// F[node[t] npad^2 + r (npad + 1)] += b for r < size[t], t < nblocks
+hipError_t launch_shift_diag(double* F, const int* node, const int* size, int nblocks, int npad,
+                             double b, hipStream_t s);
 hipError_t launch_fill_f(float* p, float v, long long n, hipStream_t s);
 hipError_t launch_d2f(const double* in, float* out, long long n, hipStream_t s);
 hipError_t launch_f2d(const float* in, double* out, long long n, hipStream_t s);

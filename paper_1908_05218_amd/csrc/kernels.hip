@@ -367,6 +367,19 @@ __global__ void k_convert(const Tin* in, Tout* out, long long n) {
   }
 }
 
+__global__ void k_scale(double* p, double a, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] *= a;
+}
+
+// F[node] += b I on the first size[t] diagonal entries of the dense diagonal
+// leaf blocks listed in node[] (one workgroup per block)
+__global__ void k_shift_diag(double* F, const int* node, const int* size, int npad, double b) {
+  const int t = blockIdx.x;
+  double* f = F + (long long)node[t] * npad * npad;
+  for (int r = threadIdx.x; r < size[t]; r += blockDim.x) f[r + (long long)r * npad] += b;
+}
+
 __global__ void k_fill(double* p, double v, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -477,6 +490,19 @@ hipError_t launch_segsum(const SegsumArgs<T>& a, hipStream_t s) {
 hipError_t launch_gram_norm(const GramNormArgs& a, int nclusters, hipStream_t s) {
   if (nclusters <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gram_norm, dim3(nclusters), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(double* p, double a, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3(cdiv(n, 256)), dim3(256), 0, s, p, a, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_diag(double* F, const int* node, const int* size, int nblocks, int npad,
+                             double b, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shift_diag, dim3(nblocks), dim3(64), 0, s, F, node, size, npad, b);
   return hipGetLastError();
 }
 
