@@ -74,16 +74,49 @@ def cpu_baseline(patch=(64, 64)):
 PEAK = {"fp64": FP64_PEAK_TFLOPS, "fp32_bulk": FP32_PEAK_TFLOPS}
 
 
-def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192):
+def newton_schulz_leg(n=16384, eps=1e-2, steps=12):
+    """Downstream workload: Newton-Schulz approximate inverse of the plates
+    family matrix at N = n (grid recipe of plates64k at another size) by
+    repeated products (h2_newton_schulz, FP32-bulk products at eps),
+    alpha = 1 / (1.02 lambda_max) from 40 power iterations; the residual
+    ||x - A X x|| / ||x|| over two seeded probes."""
+    import numpy as np
+    import paper_1908_05218_amd as h2
+    from h2inputs import configs, vectors
+    w = configs.plates_n(n)
+    ctx = h2.Context(0)
+    A = h2.build(ctx, w.pts, w.leaf_size, w.eta, w.order, w.kernel.self_value)
+    x = np.random.default_rng(1).standard_normal(n)
+    lam = 0.0
+    for _ in range(40):
+        y = h2.matvec(ctx, A, x)
+        lam = float(np.linalg.norm(y) / np.linalg.norm(x))
+        x = y / np.linalg.norm(y)
+    alpha = 1.0 / (1.02 * lam)
+    t0 = time.perf_counter()
+    X = h2.newton_schulz(ctx, A, alpha, steps, eps, precision="fp32_bulk")
+    secs = time.perf_counter() - t0
+    xp = vectors.probes(n, 2, 7)
+    r = xp - h2.matvec(ctx, A, h2.matvec(ctx, X, xp))
+    out = {"workload": f"plates{n // 1024}k inverse", "N": n, "eps": eps, "steps": steps,
+           "products": 2 * (steps - 1), "seconds": secs,
+           "residual": float(np.linalg.norm(r) / np.linalg.norm(xp)),
+           "rank_max": h2.stats(X)["rank_max_r"], "precision": "fp32_bulk"}
+    ctx.close()
+    return out
+
+
+def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192, mean_gap_s=0.05):
     """Served latency: a seeded stream of C = A A requests through the
     library's request loop (h2_submit / h2_wait) with `slots` requests on the
     device at once, admitted against a device-memory budget of budget_gib.
     Recipe: N = round(exp(U[ln 4096, ln 32768])), the unit cube or the two-plate family with probability
     1/2 each (plates: random points on both plates, panel self-term), leaf 32,
     eta 1, Chebyshev 3x3x3, eps 1e-4 or 1e-6 with probability 1/2,
-    exponential inter-arrival times of mean 50 ms; the points are generated
-    before the clock starts.  Latency = submission to completion (build of A
-    on the device plus the product)."""
+    exponential inter-arrival times of mean mean_gap_s (50 ms: 20 requests per
+    second); the points are generated before the clock starts.  Latency =
+    submission to completion (build of A on the device plus the product);
+    service = build plus product of one request."""
     import math
     import numpy as np
     import paper_1908_05218_amd as h2
@@ -95,7 +128,7 @@ def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192):
         n = int(round(math.exp(rng.uniform(math.log(4096), math.log(32768)))))
         cube = rng.random() < 0.5
         eps = 1e-4 if rng.random() < 0.5 else 1e-6
-        gap = float(rng.exponential(0.05))
+        gap = float(rng.exponential(1.0))
         if cube:
             pts, sv = points.cube(n, 1000 + i), 1.0
         else:
@@ -112,7 +145,7 @@ def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192):
     tickets = []
     t0 = time.perf_counter()
     for n, eps, gap, pts, sv in reqs:
-        time.sleep(gap)
+        time.sleep(gap * mean_gap_s)
         tickets.append((h2.submit(ctx, pts, 32, 1.0, 3, sv, eps, precision=precision), n))
     lat, svc, bad = [], [], 0
     for t, n in tickets:
@@ -125,8 +158,10 @@ def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192):
     ctx.close()
     lat = np.array(lat)
     return {"precision": precision, "requests": n_req, "failed": int(bad), "slots": slots,
-            "budget_gib": budget_gib,
+            "budget_gib": budget_gib, "arrivals_per_s": 1.0 / mean_gap_s,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "service_p50_ms": float(np.percentile(svc, 50)),
+            "service_p99_ms": float(np.percentile(svc, 99)),
             "mean_service_ms": float(np.mean(svc)),
             "unknowns_per_s": float(sum(n for _, n in tickets) / wall)}
 def sphere_leg(n, steps, eps=1e-3):
@@ -299,6 +334,8 @@ def main():
                     help="concurrent requests of the serving loop")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the served-latency stream (0: skip)")
+    ap.add_argument("--inverse-n", type=int, default=16384,
+                    help="points of the Newton-Schulz inverse leg (0: skip)")
     ap.add_argument("--sphere-n", type=int, default=32768,
                     help="points of the complex Helmholtz sphere product (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -392,6 +429,14 @@ def main():
     if args.serve_requests > 0:
         out["serving"] = {p: serve_stream(args.serve_requests, p, slots=args.serve_slots)
                           for p in ("fp32_bulk", "fp64")}
+        # the same stream at an arrival rate below the measured capacity
+        # (slots / mean service time), where latency is service, not backlog
+        fb = out["serving"]["fp32_bulk"]
+        cap = fb["slots"] / (fb["mean_service_ms"] * 1e-3)
+        out["serving"]["fp32_bulk_below_capacity"] = serve_stream(
+            args.serve_requests, "fp32_bulk", slots=args.serve_slots, mean_gap_s=1.0 / (0.7 * cap))
+    if args.inverse_n > 0:
+        out["newton_schulz"] = newton_schulz_leg(args.inverse_n)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
