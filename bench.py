@@ -106,11 +106,12 @@ def newton_schulz_leg(n=16384, eps=1e-2, steps=12):
     return out
 
 
-def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192, mean_gap_s=0.05):
+def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192, mean_gap_s=0.05,
+                 n_max=32768):
     """Served latency: a seeded stream of C = A A requests through the
     library's request loop (h2_submit / h2_wait) with `slots` requests on the
     device at once, admitted against a device-memory budget of budget_gib.
-    Recipe: N = round(exp(U[ln 4096, ln 32768])), the unit cube or the two-plate family with probability
+    Recipe: N = round(exp(U[ln 4096, ln n_max])), the unit cube or the two-plate family with probability
     1/2 each (plates: random points on both plates, panel self-term), leaf 32,
     eta 1, Chebyshev 3x3x3, eps 1e-4 or 1e-6 with probability 1/2,
     exponential inter-arrival times of mean mean_gap_s (50 ms: 20 requests per
@@ -125,7 +126,7 @@ def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192, mean_gap_s=0
     rng = np.random.default_rng(seed)
     reqs = []
     for i in range(n_req):
-        n = int(round(math.exp(rng.uniform(math.log(4096), math.log(32768)))))
+        n = int(round(math.exp(rng.uniform(math.log(4096), math.log(n_max)))))
         cube = rng.random() < 0.5
         eps = 1e-4 if rng.random() < 0.5 else 1e-6
         gap = float(rng.exponential(1.0))
@@ -144,26 +145,39 @@ def serve_stream(n_req, precision, seed=3, slots=2, budget_gib=192, mean_gap_s=0
     h2.release(ctx, warm)
     tickets = []
     t0 = time.perf_counter()
+    rejected = {}
     for n, eps, gap, pts, sv in reqs:
         time.sleep(gap * mean_gap_s)
-        tickets.append((h2.submit(ctx, pts, 32, 1.0, 3, sv, eps, precision=precision), n))
-    lat, svc, bad = [], [], 0
-    for t, n in tickets:
+        try:
+            tickets.append((h2.submit(ctx, pts, 32, 1.0, 3, sv, eps, precision=precision), n))
+        except h2.H2Error as e:  # its device-memory estimate exceeds the whole budget
+            key = str(e).split(":")[0]
+            rejected[key] = rejected.get(key, 0) + 1
+    lat, svc, bad, reasons = [], [], 0, {}
+    for i, (t, n) in enumerate(tickets):
         r = h2.wait(ctx, t)
-        bad += r["status"] != 0
-        lat.append(r["total_ms"])
-        svc.append(r["build_ms"] + r["mmp_ms"])
+        print(f"[bench] {precision} served {i + 1}/{len(tickets)}: N {n}, status {r['status']}, "
+              f"{r['total_ms']:.0f} ms", file=sys.stderr, flush=True)
+        if r["status"] != 0:
+            bad += 1
+            key = r["message"][:60]
+            reasons[key] = reasons.get(key, 0) + 1
+        else:
+            lat.append(r["total_ms"])
+            svc.append(r["build_ms"] + r["mmp_ms"])
         h2.release(ctx, t)
     wall = time.perf_counter() - t0
     ctx.close()
     lat = np.array(lat)
     return {"precision": precision, "requests": n_req, "failed": int(bad), "slots": slots,
+            "n_max": n_max, "rejected_at_submit": rejected, "failures": reasons,
             "budget_gib": budget_gib, "arrivals_per_s": 1.0 / mean_gap_s,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "service_p50_ms": float(np.percentile(svc, 50)),
-            "service_p99_ms": float(np.percentile(svc, 99)),
-            "mean_service_ms": float(np.mean(svc)),
-            "unknowns_per_s": float(sum(n for _, n in tickets) / wall)}
+            "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "service_p50_ms": float(np.percentile(svc, 50)) if svc else None,
+            "service_p99_ms": float(np.percentile(svc, 99)) if svc else None,
+            "mean_service_ms": float(np.mean(svc)) if svc else None,
+            "unknowns_per_s": float(sum(n for (t, n) in tickets) / wall)}
 def sphere_leg(n, steps, eps=1e-3):
     """Scattering-shaped complex128 product C = A B on a Fibonacci sphere:
     exp(-j kappa r)/(4 pi r) with kappa such that the point spacing
@@ -334,6 +348,9 @@ def main():
                     help="concurrent requests of the serving loop")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the served-latency stream (0: skip)")
+    ap.add_argument("--serve-nmax", type=int, default=32768,
+                    help="largest N of the served stream (131072: the full served workload, "
+                         "FP32-bulk only, no below-capacity run)")
     ap.add_argument("--inverse-n", type=int, default=16384,
                     help="points of the Newton-Schulz inverse leg (0: skip)")
     ap.add_argument("--sphere-n", type=int, default=32768,
@@ -427,14 +444,17 @@ def main():
     if args.sphere_n > 0:
         out["sphere_complex"] = sphere_leg(args.sphere_n, args.steps)
     if args.serve_requests > 0:
-        out["serving"] = {p: serve_stream(args.serve_requests, p, slots=args.serve_slots)
-                          for p in ("fp32_bulk", "fp64")}
+        precs = ("fp32_bulk", "fp64") if args.serve_nmax <= 32768 else ("fp32_bulk",)
+        out["serving"] = {p: serve_stream(args.serve_requests, p, slots=args.serve_slots,
+                                          n_max=args.serve_nmax) for p in precs}
         # the same stream at an arrival rate below the measured capacity
         # (slots / mean service time), where latency is service, not backlog
         fb = out["serving"]["fp32_bulk"]
-        cap = fb["slots"] / (fb["mean_service_ms"] * 1e-3)
-        out["serving"]["fp32_bulk_below_capacity"] = serve_stream(
-            args.serve_requests, "fp32_bulk", slots=args.serve_slots, mean_gap_s=1.0 / (0.7 * cap))
+        if args.serve_nmax <= 32768 and fb["mean_service_ms"]:
+            cap = fb["slots"] / (fb["mean_service_ms"] * 1e-3)
+            out["serving"]["fp32_bulk_below_capacity"] = serve_stream(
+                args.serve_requests, "fp32_bulk", slots=args.serve_slots,
+                mean_gap_s=1.0 / (0.7 * cap))
     if args.inverse_n > 0:
         out["newton_schulz"] = newton_schulz_leg(args.inverse_n)
     if not args.no_cpu_baseline:
