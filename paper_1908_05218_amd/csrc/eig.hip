@@ -205,62 +205,97 @@ __device__ __forceinline__ double start_vec(int r, int m) {
 // clamped to +-tiny (one hardware reciprocal refined by Newton steps serves
 // both the multiplier and the stored reciprocal pivot); a growing solution is
 // rescaled before it can overflow.
-__device__ void invit_solve(const double* dd, const double* ee, int n, double lm, double tiny,
+__device__ __forceinline__ void invit_solve(const double* dd, const double* ee, int n, double lm, double tiny,
                             double* F0, double* F1, double* F2, double* F3, int fs, int m,
                             double* zm, bool fresh, int seed) {
+  // Global loads and stores share one in-order completion counter, so a load
+  // issued after a store waits for that store too.  Every sweep below works
+  // in batches of C steps and issues the next batch's loads before the
+  // current batch's stores.
+  constexpr int C = 4;
   double di = dd[0] - lm;
   double ui = n > 1 ? ee[0] : 0.0;
   double bi = fresh ? start_vec(0, seed) : zm[0];
-  for (int i = 0; i < n - 1; ++i) {
-    const double li = ee[i];
-    const double dn = dd[i + 1] - lm;
-    const double un = i < n - 2 ? ee[i + 1] : 0.0;
-    const double bn = fresh ? start_vec(i + 1, seed) : zm[i + 1];
-    double rp, u1, u2, y;  // rp: reciprocal of the pivot
-    if (fabs(di) >= fabs(li)) {
-      if (fabs(di) < tiny) di = di < 0.0 ? -tiny : tiny;
-      rp = recip(di);
-      u1 = ui;
-      u2 = 0.0;
-      y = bi;
-      const double f = li * rp;
-      di = dn - f * ui;
-      ui = un;
-      bi = bn - f * bi;
-    } else {
-      const double lp = fabs(li) < tiny ? (li < 0.0 ? -tiny : tiny) : li;
-      rp = recip(lp);
-      u1 = dn;
-      u2 = un;
-      y = bn;
-      const double f = di * rp;
-      di = ui - f * dn;
-      ui = -f * un;
-      bi = bi - f * bn;
+  double rb[C], rn[C];  // right-hand side entries of this batch and the next
+  if (!fresh) {
+#pragma unroll
+    for (int t = 0; t < C; ++t) rb[t] = zm[1 + t < n ? 1 + t : n - 1];
+  }
+  for (int i0 = 0; i0 < n - 1; i0 += C) {
+    if (!fresh) {
+#pragma unroll
+      for (int t = 0; t < C; ++t) {
+        const int r = i0 + C + 1 + t;
+        rn[t] = zm[r < n ? r : n - 1];
+      }
     }
-    const long long o = (long long)i * fs + m;
-    F0[o] = rp;
-    F1[o] = u1;
-    F2[o] = u2;
-    F3[o] = y;
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      const int i = i0 + t;
+      if (i < n - 1) {
+        const double li = ee[i];
+        const double dn = dd[i + 1] - lm;
+        const double un = i < n - 2 ? ee[i + 1] : 0.0;
+        const double bn = fresh ? start_vec(i + 1, seed) : rb[t];
+        double rp, u1, u2, y;  // rp: reciprocal of the pivot
+        if (fabs(di) >= fabs(li)) {
+          if (fabs(di) < tiny) di = di < 0.0 ? -tiny : tiny;
+          rp = recip(di);
+          u1 = ui;
+          u2 = 0.0;
+          y = bi;
+          const double f = li * rp;
+          di = dn - f * ui;
+          ui = un;
+          bi = bn - f * bi;
+        } else {
+          const double lp = fabs(li) < tiny ? (li < 0.0 ? -tiny : tiny) : li;
+          rp = recip(lp);
+          u1 = dn;
+          u2 = un;
+          y = bn;
+          const double f = di * rp;
+          di = ui - f * dn;
+          ui = -f * un;
+          bi = bi - f * bn;
+        }
+        const long long o = (long long)i * fs + m;
+        F0[o] = rp;
+        F1[o] = u1;
+        F2[o] = u2;
+        F3[o] = y;
+      }
+    }
+    if (!fresh) {
+#pragma unroll
+      for (int t = 0; t < C; ++t) rb[t] = rn[t];
+    }
   }
   if (fabs(di) < tiny) di = di < 0.0 ? -tiny : tiny;
   double x1 = bi / di, x2 = 0.0;
   zm[n - 1] = x1;
   double amax = fabs(x1);
-  // backward sweep; the factor rows are fetched eight at a time ahead of use
-  int i = n - 2;
-  while (i >= 0) {
-    constexpr int C = 8;
-    double r0[C], r1[C], r2[C], r3[C];
+  // backward sweep: factor rows of the next batch fetched before this
+  // batch's solution entries are stored
+  double r0[C], r1[C], r2[C], r3[C], q0[C], q1[C], q2[C], q3[C];
+#pragma unroll
+  for (int t = 0; t < C; ++t) {
+    const int ii = n - 2 - t;
+    const long long o = (long long)(ii < 0 ? 0 : ii) * fs + m;
+    r0[t] = F0[o];
+    r1[t] = F1[o];
+    r2[t] = F2[o];
+    r3[t] = F3[o];
+  }
+  for (int i = n - 2; i >= 0; i -= C) {
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-      const int ii = i - t;
+      const int ii = i - C - t;
       const long long o = (long long)(ii < 0 ? 0 : ii) * fs + m;
-      r0[t] = F0[o];
-      r1[t] = F1[o];
-      r2[t] = F2[o];
-      r3[t] = F3[o];
+      q0[t] = F0[o];
+      q1[t] = F1[o];
+      q2[t] = F2[o];
+      q3[t] = F3[o];
     }
 #pragma unroll
     for (int t = 0; t < C; ++t) {
@@ -275,13 +310,21 @@ __device__ void invit_solve(const double* dd, const double* ee, int n, double lm
           for (int r = ii; r < n; ++r) zm[r] *= 1e-150;
           for (int r = 0; r < ii; ++r) F3[(long long)r * fs + m] *= 1e-150;
           for (int u = t + 1; u < C; ++u) r3[u] *= 1e-150;
+#pragma unroll
+          for (int u = 0; u < C; ++u) q3[u] *= 1e-150;
           x1 *= 1e-150;
           x2 *= 1e-150;
           amax *= 1e-150;
         }
       }
     }
-    i -= C;
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      r0[t] = q0[t];
+      r1[t] = q1[t];
+      r2[t] = q2[t];
+      r3[t] = q3[t];
+    }
   }
   if (!(amax > 0.0) || !(amax < 1e308)) return;
   double s = 0.0;
@@ -290,7 +333,22 @@ __device__ void invit_solve(const double* dd, const double* ee, int n, double lm
     s += v * v;
   }
   const double inv = 1.0 / (amax * sqrt(s));
-  for (int r = 0; r < n; ++r) zm[r] *= inv;
+  // scale in batches, the next batch loaded before this batch is stored
+  double v[C], w[C];
+#pragma unroll
+  for (int t = 0; t < C; ++t) v[t] = zm[t < n ? t : n - 1];
+  for (int r0b = 0; r0b < n; r0b += C) {
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      const int r = r0b + C + t;
+      w[t] = zm[r < n ? r : n - 1];
+    }
+#pragma unroll
+    for (int t = 0; t < C; ++t)
+      if (r0b + t < n) zm[r0b + t] = v[t] * inv;
+#pragma unroll
+    for (int t = 0; t < C; ++t) v[t] = w[t];
+  }
 }
 
 // Z[:, m] -= sum_{q0 <= q < m} (Z[:,q] . Z[:,m]) Z[:,q], twice (classical
@@ -496,25 +554,46 @@ __device__ void bcgs2_waves(double* Z, int ldz, int n, int k) {
       z[s] = (mine && r < n) ? zj[r] : 0.0;
     }
     if (mine && m0 > 0) {
+      // groups of eight earlier vectors, the next group loaded while this
+      // one is applied (the loads' latency, not the arithmetic, sets the pace)
+      double zq[8][SL], zn[8][SL];
       for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+        for (int qq = 0; qq < 8; ++qq) {
+          const double* col = Z + (long long)(qq < m0 ? qq : 0) * ldz;
+#pragma unroll
+          for (int s = 0; s < SL; ++s) {
+            const int r = lane + 64 * s;
+            zq[qq][s] = (qq < m0 && r < n) ? col[r] : 0.0;
+          }
+        }
         for (int q0 = 0; q0 < m0; q0 += 8) {
-          double zq[8][SL], t[8], d[8];
 #pragma unroll
           for (int qq = 0; qq < 8; ++qq) {
-            const double* col = Z + (long long)(q0 + qq) * ldz;
-            t[qq] = 0.0;
+            const int q = q0 + 8 + qq;
+            const double* col = Z + (long long)(q < m0 ? q : 0) * ldz;
 #pragma unroll
             for (int s = 0; s < SL; ++s) {
               const int r = lane + 64 * s;
-              zq[qq][s] = (q0 + qq < m0 && r < n) ? col[r] : 0.0;
-              t[qq] += zq[qq][s] * z[s];
+              zn[qq][s] = (q < m0 && r < n) ? col[r] : 0.0;
             }
+          }
+          double t[8], d[8];
+#pragma unroll
+          for (int qq = 0; qq < 8; ++qq) {
+            t[qq] = 0.0;
+#pragma unroll
+            for (int s = 0; s < SL; ++s) t[qq] += zq[qq][s] * z[s];
           }
           wave_sum8(t, d);
 #pragma unroll
           for (int qq = 0; qq < 8; ++qq)
 #pragma unroll
             for (int s = 0; s < SL; ++s) z[s] -= d[qq] * zq[qq][s];
+#pragma unroll
+          for (int qq = 0; qq < 8; ++qq)
+#pragma unroll
+            for (int s = 0; s < SL; ++s) zq[qq][s] = zn[qq][s];
         }
       }
     }
@@ -861,27 +940,38 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
         const int r = lane + 64 * s;
         z[v][s] = (b0 + v < k && r < n) ? Z[(long long)(b0 + v) * ldz + r] : 0.0;
       }
-    double un[SL];
-    if (n >= 3) {
-      const int ci = cs(n - 3, n);
+    // reflectors in groups of RG, the next group fetched while this one is
+    // applied (the loads' latency is several reflectors' arithmetic)
+    constexpr int RG = SL > 8 ? 1 : 2;
+    double ug[RG][SL], un[RG][SL];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      const int ii = n - 3 - g;
+      const int cn = ii >= 0 ? cs(ii, n) : 0;
 #pragma unroll
       for (int s = 0; s < SL; ++s) {
         const int r = lane + 64 * s;
-        un[s] = (r > n - 3 && r < n) ? Pg[ci + r - (n - 3)] : 0.0;
+        ug[g][s] = (ii >= 0 && r > ii && r < n) ? Pg[cn + r - ii] : 0.0;
       }
     }
-    for (int i = n - 3; i >= 0; --i) {
-      double u[SL];
+    for (int i0 = n - 3; i0 >= 0; i0 -= RG) {
 #pragma unroll
-      for (int s = 0; s < SL; ++s) u[s] = un[s];
-      if (i > 0) {  // fetch the next reflector while this one is applied
-        const int cn = cs(i - 1, n);
+      for (int g = 0; g < RG; ++g) {
+        const int ii = i0 - RG - g;
+        const int cn = ii >= 0 ? cs(ii, n) : 0;
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
           const int r = lane + 64 * s;
-          un[s] = (r > i - 1 && r < n) ? Pg[cn + r - (i - 1)] : 0.0;
+          un[g][s] = (ii >= 0 && r > ii && r < n) ? Pg[cn + r - ii] : 0.0;
         }
       }
+#pragma unroll
+      for (int g = 0; g < RG; ++g) {
+      const int i = i0 - g;
+      if (i < 0) break;
+      double u[SL];
+#pragma unroll
+      for (int s = 0; s < SL; ++s) u[s] = ug[g][s];
       double d[VB];
 #pragma unroll
       for (int v = 0; v < VB; ++v) {
@@ -905,6 +995,11 @@ __device__ __forceinline__ void eigvecs(double* Z, int ldz, const EigArgs& p, in
       for (int v = 0; v < VB; ++v)
 #pragma unroll
         for (int s = 0; s < SL; ++s) z[v][s] -= d[v] * u[s];
+      }
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int s = 0; s < SL; ++s) ug[g][s] = un[g][s];
     }
 #pragma unroll
     for (int v = 0; v < VB; ++v) {
