@@ -255,7 +255,8 @@ def run_precision(h2, ctx, dA, n, prec, steps, warmup, eps):
     walls, dev_ms = [], []
     prof = {"contraction_ms": 0.0, "contraction_launches": 0, "eig_ms": 0.0, "eig_launches": 0,
             "gram_ms": 0.0, "gram_launches": 0, "gram_flops": 0.0, "other_ms": 0.0,
-            "other_launches": 0, "contraction_flops": 0.0}
+            "other_launches": 0, "contraction_flops": 0.0, "target_ms": 0.0,
+            "target_launches": 0}
     C = None
     for i in range(steps):
         if C is not None:
@@ -281,11 +282,15 @@ def run_precision(h2, ctx, dA, n, prec, steps, warmup, eps):
     # kernel classes: summed device time of their launches (HIP events on the
     # library's stream around each launch), and the algorithmic work each
     # class performs per product at the actual ranks (h2_stats): one
-    # contraction per evaluated block product (k_bgemm_triple), 2 d^2 per
-    # Gram column, 9 d^3 per eigen-decomposition
+    # contraction per evaluated block product (k_bgemm_triple), the products
+    # that apply the projections once per target (k_bgemm_target; its count
+    # also holds the leaf targets' rank-form terms, which the leaf products
+    # absorb), 2 d^2 per Gram column, 9 d^3 per eigen-decomposition
     classes = {
         "triple_contraction": (prof["contraction_ms"], prof["contraction_launches"],
                                st["flops_triple"], "mfma", PEAK[prec]),
+        "target_products": (prof["target_ms"], prof["target_launches"], st["flops_target"],
+                            "mfma", PEAK[prec]),
         "gram_products": (prof["gram_ms"], prof["gram_launches"], st["flops_gram"], "mfma",
                           FP64_PEAK_TFLOPS),
         "eigensolver": (prof["eig_ms"], prof["eig_launches"], st["eig_flops"], "alu",

@@ -394,13 +394,16 @@ typedef struct {
    * product (operands, the product and its temporaries; blocks cached by
    * the context's pool are not counted) */
   int64_t bytes_device;
-  /* Gram-sum products, and all remaining batched products (projections,
-   * collects, per-target products, split) */
+  /* Gram-sum products, and the remaining batched products other than the
+   * per-target ones (projections, collects, split, cluster-basis products) */
   double gram_ms, other_ms;
   int64_t eig_launches, gram_launches, other_launches;
   double gram_flops, other_flops;
   double eig_flops;
   double flops_triple, flops_target, flops_gram;
+  /* the per-target products (k_bgemm_target): summed device ms and launches */
+  double target_ms;
+  int64_t target_launches;
 } h2_stats_t;
 h2_status h2_stats(h2_mat M, h2_stats_t* out);
 

@@ -61,7 +61,8 @@ class _Stats(C.Structure):
                 ("other_launches", C.c_int64), ("gram_flops", C.c_double),
                 ("other_flops", C.c_double), ("eig_flops", C.c_double),
                 ("flops_triple", C.c_double), ("flops_target", C.c_double),
-                ("flops_gram", C.c_double)]
+                ("flops_gram", C.c_double), ("target_ms", C.c_double),
+                ("target_launches", C.c_int64)]
 
 
 class _Kernel(C.Structure):
@@ -525,4 +526,5 @@ def stats(M):
                 other_launches=s.other_launches, gram_flops=s.gram_flops,
                 other_flops=s.other_flops, eig_flops=s.eig_flops,
                 flops_triple=s.flops_triple, flops_target=s.flops_target,
-                flops_gram=s.flops_gram)
+                flops_gram=s.flops_gram, target_ms=s.target_ms,
+                target_launches=s.target_launches)

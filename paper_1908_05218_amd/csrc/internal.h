@@ -251,7 +251,18 @@ struct Op {
   long long sub_r = 0, sub_c = 0;
 };
 
-enum KernelKind { kKindOther = 0, kKindTriple = 1, kKindGram = 2, kKindEig = 3, kKindCount = 4 };
+// kernel classes of a product: projections, collects, split and cluster-basis
+// products (other); one contraction per evaluated block product (triple);
+// Gram sums; eigen-decompositions; products that apply the projections once
+// per target (target)
+enum KernelKind {
+  kKindOther = 0,
+  kKindTriple = 1,
+  kKindGram = 2,
+  kKindEig = 3,
+  kKindTarget = 4,
+  kKindCount = 5
+};
 
 struct Profiler {
   bool on = false;

@@ -34,7 +34,8 @@ struct BgemmArgs {
   const int* a_idx;    // [ntask]
   const int* b_idx;    // [ntask]
   T alpha, beta;
-  int triple;  // launch under the block-product symbol (k_bgemm_triple)
+  int symbol;  // kernel symbol for traces: 0 k_bgemm, 1 k_bgemm_triple (per-triple
+               // contractions), 2 k_bgemm_target (per-target products)
   int tile;    // workgroup tile (kTile* id), -1: chosen from the output shape
   // symmetric outputs read only on and below the diagonal: compute only the
   // tiles there (m == n and a square tile; otherwise ignored)

@@ -285,6 +285,11 @@ __global__ __launch_bounds__(256) void k_bgemm_triple(BgemmArgs<T> p) {
   bgemm_body<T, TM, TN, TA, TB>(p);
 }
 
+template <typename T, int TM, int TN, typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_bgemm_target(BgemmArgs<T> p) {
+  bgemm_body<T, TM, TN, TA, TB>(p);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_segsum(SegsumArgs<T> p) {
   const int per = (p.m * p.n + 255) / 256;
@@ -445,8 +450,10 @@ static hipError_t launch_tile(BgemmArgs<T> a, hipStream_t s) {
     else                                                               \
       hipLaunchKernelGGL((K<T, TM, TN, double, double>), g, b, 0, s, a); \
   } while (0)
-  if (a.triple)
+  if (a.symbol == 1)
     H2K_LAUNCH(k_bgemm_triple);
+  else if (a.symbol == 2)
+    H2K_LAUNCH(k_bgemm_target);
   else
     H2K_LAUNCH(k_bgemm);
 #undef H2K_LAUNCH

@@ -657,12 +657,12 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     // case 1: T^C_I^T M_IK T^C_K (nonleafcoup_simple, first case)
     {
       Buf X1(ctx, (size_t)std::max(1, Q.n_case1) * cl * K * eb, bulk, cplx);
-      gemm(st, pp, kKindOther, dl(Q.c1X), cl, K, K, TCr, true, AccT, false, X1.p(),
+      gemm(st, pp, kKindTarget, dl(Q.c1X), cl, K, K, TCr, true, AccT, false, X1.p(),
            (long long)cl * K, cl, 0, 0, 1, 0, kConjA);
       const Op X1o{X1.p(), nullptr, (long long)cl * K, 0, cl};
-      gemm(st, pp, kKindOther, dl(Q.c1_R), cl, cl, K, X1o, false, TCc, false, C->S[l].p(), cs, cl,
+      gemm(st, pp, kKindTarget, dl(Q.c1_R), cl, cl, K, X1o, false, TCc, false, C->S[l].p(), cs, cl,
            0, 0, 1, 1, kConjB);
-      gemm(st, pp, kKindOther, dl(Q.c1_B), cl, cl, K, X1o, false, TCc, false, Acc_l.p(), acs,
+      gemm(st, pp, kKindTarget, dl(Q.c1_B), cl, cl, K, X1o, false, TCc, false, Acc_l.p(), acs,
            2 * cl, cl, (long long)cl * 2 * cl, 1, 1, kConjB);
     }
     // cases 2-4 (nonleafcoup_simple), re-associated: for an admissible B
@@ -702,17 +702,17 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
                       const Buf& Wn, const Buf& Wr, const Tgt& t) {
       if (rcB[l] == rrA[l] && Wn.bytes() && Wr.bytes()) {
         // one pass over the targets: [W_nl | P^A_I] x [P^B_K ; W_r]
-        gemm(st, pp, kKindOther, dl(fboth), cl, cl, rcB[l],
+        gemm(st, pp, kKindTarget, dl(fboth), cl, cl, rcB[l],
              Op{Wn.p(), PA_l.p(), wns, (long long)cl * rrA[l], cl}, false,
              Op{PB_l.p(), Wr.p(), (long long)rcB[l] * cl, wrs, rcB[l]}, false, t.p, t.stride, t.ld,
              t.sr, t.sc, 1, 1);
         return;
       }
       if (Wn.bytes())
-        gemm(st, pp, kKindOther, dl(fnl), cl, cl, rcB[l], Op{Wn.p(), nullptr, wns, 0, cl}, false,
+        gemm(st, pp, kKindTarget, dl(fnl), cl, cl, rcB[l], Op{Wn.p(), nullptr, wns, 0, cl}, false,
              PBo, false, t.p, t.stride, t.ld, t.sr, t.sc, 1, 1);
       if (Wr.bytes())
-        gemm(st, pp, kKindOther, dl(fr), cl, cl, rrA[l], PAo, false,
+        gemm(st, pp, kKindTarget, dl(fr), cl, cl, rrA[l], PAo, false,
              Op{Wr.p(), nullptr, wrs, 0, rrA[l]}, false, t.p, t.stride, t.ld, t.sr, t.sc, 1, 1);
     };
     {
@@ -848,6 +848,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     S.other_ms = pms[kKindOther];
     S.other_launches = pl[kKindOther];
     S.other_flops = pfl[kKindOther];
+    S.target_ms = pms[kKindTarget];
+    S.target_launches = pl[kKindTarget];
   }
   build_matvec_plan(ctx, C.get());
   *C_out = C.release();
