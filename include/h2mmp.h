@@ -404,6 +404,13 @@ typedef struct {
   /* the per-target products (k_bgemm_target): summed device ms and launches */
   double target_ms;
   int64_t target_launches;
+  /* the eigensolver's three kernels (eig_ms is their sum): tridiagonalisation,
+   * eigenvalues and kept count, eigenvectors */
+  double eig_tri_ms, eig_val_ms, eig_vec_ms;
+  /* algorithmic work of two of them: (4/3) d^3 per reduction, 6 d^2 k per
+   * set of k kept eigenvectors (not part of flops, whose eigensolver term is
+   * the 9 d^3 of eig_flops) */
+  double eig_tri_flops, eig_vec_flops;
 } h2_stats_t;
 h2_status h2_stats(h2_mat M, h2_stats_t* out);
 

@@ -62,7 +62,9 @@ class _Stats(C.Structure):
                 ("other_flops", C.c_double), ("eig_flops", C.c_double),
                 ("flops_triple", C.c_double), ("flops_target", C.c_double),
                 ("flops_gram", C.c_double), ("target_ms", C.c_double),
-                ("target_launches", C.c_int64)]
+                ("target_launches", C.c_int64), ("eig_tri_ms", C.c_double),
+                ("eig_val_ms", C.c_double), ("eig_vec_ms", C.c_double),
+                ("eig_tri_flops", C.c_double), ("eig_vec_flops", C.c_double)]
 
 
 class _Kernel(C.Structure):
@@ -527,4 +529,6 @@ def stats(M):
                 other_flops=s.other_flops, eig_flops=s.eig_flops,
                 flops_triple=s.flops_triple, flops_target=s.flops_target,
                 flops_gram=s.flops_gram, target_ms=s.target_ms,
-                target_launches=s.target_launches)
+                target_launches=s.target_launches, eig_tri_ms=s.eig_tri_ms,
+                eig_val_ms=s.eig_val_ms, eig_vec_ms=s.eig_vec_ms,
+                eig_tri_flops=s.eig_tri_flops, eig_vec_flops=s.eig_vec_flops)

@@ -1251,6 +1251,8 @@ h2_status h2_stats(h2_mat M, h2_stats_t* out) {
     M->stats.flops_target = fc.target * m4;
     M->stats.flops_gram = fc.gram * m4;
     M->stats.eig_flops = fc.eig * (M->cplx ? 8.0 : 1.0);  // real embedding of twice the size
+    M->stats.eig_tri_flops = fc.eig_tri * (M->cplx ? 8.0 : 1.0);
+    M->stats.eig_vec_flops = fc.eig_vec * (M->cplx ? 8.0 : 1.0);
     M->stats.flops = M->stats.flops_triple + M->stats.flops_target + M->stats.flops_gram +
                      M->stats.eig_flops;
     M->flops_pending = false;

@@ -1590,7 +1590,8 @@ int vec_zr(int D, int nt) {
 }
 
 template <int NT, int SL>
-hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, hipStream_t s) {
+hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, hipStream_t s,
+                     int phases) {
   static bool attr_set = false;
   if (!attr_set) {
     // kernels with dynamic LDS (the register-resident tridiagonalisation has
@@ -1607,7 +1608,8 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
   }
   const dim3 grid(nclusters, 2);
   const int zt = tri_zr(D, NT), zv = vec_zr(D, NT);
-  if constexpr (SL <= 4) {  // dimensions up to 4 x 64: the triangle in registers
+  if (!(phases & kEigPhaseTri)) {
+  } else if constexpr (SL <= 4) {  // dimensions up to 4 x 64: the triangle in registers
     constexpr int NW = NT / 64, RS = NW >= 4 ? NW / 2 : 1;
     bool done = false;
     if constexpr (NW == 8) {
@@ -1625,34 +1627,38 @@ hipError_t launch_nt(const EigArgs& a, const EigArgs& b, int nclusters, int D, h
                        zt, D, 1);
     hipLaunchKernelGGL((k_eig_tri_reg<8, 4>), grid, dim3(512), 0, s, a, b, D, 1);
   }
-  hipLaunchKernelGGL(k_eig_val<NT>, grid, dim3(NT), sizeof(double) * (4 * (size_t)D + kRed), s, a,
-                     b, D);
-  const size_t lv = sizeof(double) * ((size_t)zv + 4 * D + NT + kRed);
-  hipLaunchKernelGGL((k_eig_vec<NT, SL, true>), grid, dim3(NT), lv, s, a, b, zv, D);
-  hipLaunchKernelGGL((k_eig_vec<NT, SL, false>), grid, dim3(NT), sizeof(double) * (4 * D + NT + kRed),
-                     s, a, b, zv, D);
+  if (phases & kEigPhaseVal)
+    hipLaunchKernelGGL(k_eig_val<NT>, grid, dim3(NT), sizeof(double) * (4 * (size_t)D + kRed), s,
+                       a, b, D);
+  if (phases & kEigPhaseVec) {
+    const size_t lv = sizeof(double) * ((size_t)zv + 4 * D + NT + kRed);
+    hipLaunchKernelGGL((k_eig_vec<NT, SL, true>), grid, dim3(NT), lv, s, a, b, zv, D);
+    hipLaunchKernelGGL((k_eig_vec<NT, SL, false>), grid, dim3(NT),
+                       sizeof(double) * (4 * D + NT + kRed), s, a, b, zv, D);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStream_t s) {
+hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStream_t s,
+                      int phases) {
   if (nclusters <= 0) return hipSuccess;
   const int D = a.D > b.D ? a.D : b.D;
   if (D > kEigNmax || D < 1) return hipErrorInvalidValue;
   if (a.sstride < eig_scratch_doubles(a.D) || b.sstride < eig_scratch_doubles(b.D))
     return hipErrorInvalidValue;
   // SL row slots per lane: a wave holds a column of up to 64 SL rows
-  if (D > 512) return launch_nt<512, 16>(a, b, nclusters, D, s);
-  if (D > 320) return launch_nt<512, 8>(a, b, nclusters, D, s);
-  if (D > 256) return launch_nt<512, 5>(a, b, nclusters, D, s);
+  if (D > 512) return launch_nt<512, 16>(a, b, nclusters, D, s, phases);
+  if (D > 320) return launch_nt<512, 8>(a, b, nclusters, D, s, phases);
+  if (D > 256) return launch_nt<512, 5>(a, b, nclusters, D, s, phases);
   switch (eig_threads(D)) {
     // row slots per lane: as many as the dimension needs (fewer registers
     // and no padding work in the eigenvector phases)
-    case 64: return launch_nt<64, 1>(a, b, nclusters, D, s);
-    case 128: return launch_nt<128, 1>(a, b, nclusters, D, s);
-    case 256: return launch_nt<256, 2>(a, b, nclusters, D, s);
-    default: return launch_nt<512, 4>(a, b, nclusters, D, s);
+    case 64: return launch_nt<64, 1>(a, b, nclusters, D, s, phases);
+    case 128: return launch_nt<128, 1>(a, b, nclusters, D, s, phases);
+    case 256: return launch_nt<256, 2>(a, b, nclusters, D, s, phases);
+    default: return launch_nt<512, 4>(a, b, nclusters, D, s, phases);
   }
 }
 

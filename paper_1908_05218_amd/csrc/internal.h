@@ -51,6 +51,10 @@ struct FlopRanks {
 };
 struct FlopCounts {
   double triple = 0, target = 0, gram = 0, eig = 0;
+  // parts of the eigensolver's work: (4/3) d^3 Householder reduction and
+  // 6 d^2 k for the k kept eigenvectors (inverse iteration, Gram-Schmidt,
+  // back-transformation), per Gram matrix
+  double eig_tri = 0, eig_vec = 0;
 };
 }
 
@@ -259,9 +263,11 @@ enum KernelKind {
   kKindOther = 0,
   kKindTriple = 1,
   kKindGram = 2,
-  kKindEig = 3,
+  kKindEig = 3,  // the tridiagonalisation kernels
   kKindTarget = 4,
-  kKindCount = 5
+  kKindEigVal = 5,
+  kKindEigVec = 6,
+  kKindCount = 7
 };
 
 struct Profiler {

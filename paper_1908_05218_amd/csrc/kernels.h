@@ -138,8 +138,12 @@ hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_segsum(const SegsumArgs<T>& a, hipStream_t s);
 hipError_t launch_gram_norm(const GramNormArgs& a, int nclusters, hipStream_t s);
-// two problem sets (row and column bases of one level) in one launch
-hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStream_t s);
+// two problem sets (row and column bases of one level) in one launch per
+// phase: tridiagonalisation, eigenvalues and kept count, eigenvectors (the
+// phases in order, any subset per call)
+constexpr int kEigPhaseTri = 1, kEigPhaseVal = 2, kEigPhaseVec = 4, kEigPhaseAll = 7;
+hipError_t launch_eig(const EigArgs& a, const EigArgs& b, int nclusters, hipStream_t s,
+                      int phases = kEigPhaseAll);
 // Kernel entries of h2_build (1/(4 pi r), self_value at r = 0).  Coupling
 // matrices of one level: node q (rows[q], cols[q], types[q]; type 0 =
 // admissible) gets the kernel at the row and column clusters' p^3 tensor

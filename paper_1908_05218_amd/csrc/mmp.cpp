@@ -146,6 +146,8 @@ FlopCounts flop_counts(const Structure& s, const FlopRanks& r) {
     for (int c = 0; c < ncl; ++c) {
       f.gram += 2.0 * dr[c] * dr[c] * rcols[c] + 2.0 * dc[c] * dc[c] * ccols[c];
       f.eig += 9.0 * (dr[c] * dr[c] * dr[c] + dc[c] * dc[c] * dc[c]);
+      f.eig_tri += (4.0 / 3.0) * (dr[c] * dr[c] * dr[c] + dc[c] * dc[c] * dc[c]);
+      f.eig_vec += 6.0 * (dr[c] * dr[c] * at(r.cr, l, c) + dc[c] * dc[c] * at(r.cc, l, c));
     }
     acc.swap(next);
   }
@@ -261,6 +263,17 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
          (long long)rcA[l] * rrB[l], rcA[l], 0, 0, 1.0, 0.0);
   }
 
+  // the three eigensolver phases, each timed as its own kernel class
+  auto run_eig = [&](const h2k::EigArgs* ea, int ncl) {
+    const int phase[3] = {h2k::kEigPhaseTri, h2k::kEigPhaseVal, h2k::kEigPhaseVec};
+    const int kind[3] = {kKindEig, kKindEigVal, kKindEigVec};
+    for (int ph = 0; ph < 3; ++ph) {
+      hipEvent_t e = nullptr;
+      prof.begin(kind[ph], 0, &e);
+      H2_HIP(h2k::launch_eig(ea[0], ea[1], ncl, st, phase[ph]));
+      prof.end(e, kind[ph], 0);
+    }
+  };
   // truncated eigen-decompositions of a level's normalised row and column
   // Grams, both sets in one launch
   auto eig_level = [&](int l, int D, Buf Gr[3], Buf Gc[3], Buf& Ur_, Buf& Uc_, Buf& rank_r_,
@@ -328,11 +341,11 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
         e.exact = exact ? 1 : 0;
         e.status = status.as<int>();
       }
+      run_eig(ea, ncl);
       hipEvent_t ev = nullptr;
-      prof.begin(kKindEig, 0, &ev);
-      H2_HIP(h2k::launch_eig(ea[0], ea[1], ncl, st));
+      prof.begin(kKindEigVec, 0, &ev);
       H2_HIP(h2k::launch_ceig_extract(ca[0], ca[1], ncl, st));
-      prof.end(ev, kKindEig, 0);
+      prof.end(ev, kKindEigVec, 0);
       return;
     }
     Buf Gnr(ctx, (size_t)ncl * D * D * sizeof(double)), Gnc(ctx, (size_t)ncl * D * D * sizeof(double));
@@ -371,10 +384,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       e.exact = exact ? 1 : 0;
       e.status = status.as<int>();
     }
-    hipEvent_t e = nullptr;
-    prof.begin(kKindEig, 0, &e);
-    H2_HIP(h2k::launch_eig(ea[0], ea[1], ncl, st));
-    prof.end(e, kKindEig, 0);
+    run_eig(ea, ncl);
   };
   auto read_ranks = [&](int l, Buf& rr_, Buf& rc_) {
     const int ncl = 1 << l;
@@ -840,8 +850,11 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     S.contraction_ms = pms[kKindTriple];
     S.contraction_launches = pl[kKindTriple];
     S.contraction_flops = pfl[kKindTriple];
-    S.eig_ms = pms[kKindEig];
-    S.eig_launches = pl[kKindEig];
+    S.eig_ms = pms[kKindEig] + pms[kKindEigVal] + pms[kKindEigVec];
+    S.eig_launches = pl[kKindEig] + pl[kKindEigVal] + pl[kKindEigVec];
+    S.eig_tri_ms = pms[kKindEig];
+    S.eig_val_ms = pms[kKindEigVal];
+    S.eig_vec_ms = pms[kKindEigVec];
     S.gram_ms = pms[kKindGram];
     S.gram_launches = pl[kKindGram];
     S.gram_flops = pfl[kKindGram];
