@@ -158,11 +158,13 @@ typedef struct {
  * points (all leaves at one depth); eta: strong admissibility
  * max(diam t, diam s) <= eta dist(t, s) on tight bounding boxes (Section II);
  * cheb_order p: nested tensor Chebyshev interpolation of order p per axis,
- * rank p^3 at every cluster. */
+ * rank p^3 at every cluster; recompress_eps: 0 = off, else the built matrix
+ * is recompressed at this accuracy as by h2_recompress (>= 1e-8). */
 typedef struct {
   int64_t leaf_size;
   double eta;
   int32_t cheb_order;
+  double recompress_eps;
 } h2_build_opts;
 
 /* Build the H^2 matrix (Section II: binary cluster tree by median bisection
@@ -175,11 +177,37 @@ typedef struct {
  * assembled on the host.  share_tree_with (nullable): a matrix of the same
  * points and options whose structure object is then shared.  Synchronous.
  * Errors: H2_ERR_ARG (null pointer, n < 1, leaf_size < 1, eta <= 0,
- * cheb_order outside 1..6, non-finite input, share_tree_with of another size
- * or structure), H2_ERR_UNSUPPORTED (another kernel), H2_ERR_OOM,
- * H2_ERR_DEVICE. */
+ * cheb_order outside 1..6, non-finite input, recompress_eps neither 0 nor a
+ * finite value >= 1e-8, share_tree_with of another size or structure),
+ * H2_ERR_UNSUPPORTED (another kernel), H2_ERR_OOM, H2_ERR_DEVICE. */
 h2_status h2_build(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* kernel,
                    const h2_build_opts* opts, h2_mat share_tree_with, h2_mat* out);
+
+/* Smallest accuracy h2_recompress accepts: a Gram matrix's eigenvalues are
+ * the squared singular values of a cluster's far field, so FP64 resolves
+ * singular values down to about 1e-8 of the largest. */
+#define H2_RECOMPRESS_EPS_MIN 1e-8
+
+/* Recompression of M (input construction; the paper cites its construction
+ * of the inputs without describing it, Section VI): new orthonormal nested
+ * bases of the smallest ranks that keep every cluster's whole far field (the
+ * admissible blocks of the cluster and of its ancestors, restricted to its
+ * rows; for the column side its columns) to relative accuracy eps, and the
+ * couplings projected onto them; partition and dense blocks are M's.  Steps
+ * on the device: basis Grams B_t = X_t^T X_t^* bottom-up; far-field weights
+ * K_t = sum S_ts B_s S_ts^H + E_t K_parent E_t^H top-down; at the leaves the
+ * dominant eigenvectors of V_t K_t V_t^H, above them of Z_t K_t Z_t^H with
+ * Z_t the old basis written in the children's new bases; couplings
+ * S'_ts = P^row_t S_ts (P^col_s)^T with P_t = (new basis)^H (old basis).
+ * Eigenvalues above (eps / n_t)^2 lambda_1 are kept (n_t = L - l_min + 1,
+ * the product's ACCURACY rule), at most the old rank and at least one; levels
+ * above l_min carry no basis, as in a product.  FP64 (complex128 for complex
+ * M).  *out is a new matrix of ctx (h2_free); M is unchanged.  Synchronous.
+ * Errors: H2_ERR_ARG (null pointer, eps not finite or below
+ * H2_RECOMPRESS_EPS_MIN, M of another context), H2_ERR_UNSUPPORTED (a Gram
+ * matrix beyond the eigensolver's dimension limit), H2_ERR_NUMERIC
+ * (non-finite data), H2_ERR_OOM, H2_ERR_DEVICE. */
+h2_status h2_recompress(h2_ctx ctx, h2_mat M, double eps, h2_mat* out);
 
 /* Serving: a request loop of the context with continuous batching.  A
  * request names a point set and a kernel (built as by h2_build) and a

@@ -73,7 +73,8 @@ class _Kernel(C.Structure):
 
 
 class _BuildOpts(C.Structure):
-    _fields_ = [("leaf_size", C.c_int64), ("eta", C.c_double), ("cheb_order", C.c_int32)]
+    _fields_ = [("leaf_size", C.c_int64), ("eta", C.c_double), ("cheb_order", C.c_int32),
+                ("recompress_eps", C.c_double)]
 
 
 KERNELS = {"laplace": 0, "helmholtz": 1}
@@ -114,6 +115,7 @@ def lib():
         L.h2_matvec.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int, vp]
         L.h2_sync.argtypes = [vp]
         L.h2_scale_shift.argtypes = [vp, vp, C.c_double, C.c_double, C.POINTER(vp)]
+        L.h2_recompress.argtypes = [vp, vp, C.c_double, C.POINTER(vp)]
         L.h2_newton_schulz.argtypes = [vp, vp, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int,
                                        C.POINTER(vp)]
         L.h2_matvec_noalloc.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
@@ -139,7 +141,7 @@ def lib():
                   "h2_release", "h2_plan_info", "h2_mmp", "h2_matvec", "h2_to_dense",
                   "h2_export_size", "h2_export", "h2_stats", "h2_set_profiling", "h2_serve_slots",
                   "h2_save", "h2_load_file", "h2_sync", "h2_matvec_noalloc",
-                  "h2_scale_shift", "h2_newton_schulz"):
+                  "h2_scale_shift", "h2_newton_schulz", "h2_recompress"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -308,17 +310,17 @@ def load_file(ctx, path):
 
 
 def build(ctx, points, leaf_size, eta, order, self_value, kernel="laplace", share_tree_with=None,
-          wavenumber=0.0):
+          wavenumber=0.0, recompress_eps=0.0):
     """h2_build: the H^2 matrix of the kernel over `points` (n x 3), built by
     the library (tree and bases on the host, couplings and dense blocks on
     the device).  kernel "helmholtz": exp(-j wavenumber r)/(4 pi r), complex
-    self_value."""
+    self_value.  recompress_eps > 0: recompressed at that accuracy."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     if pts.ndim != 2 or pts.shape[1] != 3:
         raise ValueError("points must be n x 3")
     sv = complex(self_value)
     k = _Kernel(KERNELS[kernel], sv.real, float(wavenumber), sv.imag)
-    o = _BuildOpts(int(leaf_size), float(eta), int(order))
+    o = _BuildOpts(int(leaf_size), float(eta), int(order), float(recompress_eps))
     h = C.c_void_p()
     _check(lib().h2_build(ctx.h, _ptr(pts), pts.shape[0], C.byref(k), C.byref(o),
                           share_tree_with.h if share_tree_with is not None else None, C.byref(h)))
@@ -394,6 +396,13 @@ def scale_shift(ctx, M, a, b):
     """a M + b I (same partition and bases) as a new matrix."""
     h = C.c_void_p()
     _check(lib().h2_scale_shift(ctx.h, M.h, float(a), float(b), C.byref(h)))
+    return Matrix(ctx, h)
+
+
+def recompress(ctx, M, eps):
+    """h2_recompress: M recompressed at accuracy eps as a new matrix."""
+    h = C.c_void_p()
+    _check(lib().h2_recompress(ctx.h, M.h, float(eps), C.byref(h)))
     return Matrix(ctx, h)
 
 

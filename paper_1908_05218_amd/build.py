@@ -8,7 +8,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libh2mmp.so")
 SOURCES = ["kernels.hip", "eig.hip", "build.hip", "structure.cpp", "api.cpp", "mmp.cpp", "build.cpp",
-           "serve.cpp", "tune.cpp", "npz.cpp", "noalloc.cpp", "inverse.cpp"]
+           "serve.cpp", "tune.cpp", "npz.cpp", "noalloc.cpp", "inverse.cpp",
+           "recompress.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -186,6 +186,9 @@ h2_status build_impl(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* 
   if (n < 1 || opts->leaf_size < 1 || !(opts->eta > 0.0) || opts->cheb_order < 1 ||
       opts->cheb_order > 6)
     return set_error(H2_ERR_ARG, "need n >= 1, leaf_size >= 1, eta > 0, 1 <= cheb_order <= 6");
+  if (opts->recompress_eps != 0.0 &&
+      !(std::isfinite(opts->recompress_eps) && opts->recompress_eps >= H2_RECOMPRESS_EPS_MIN))
+    return set_error(H2_ERR_ARG, "recompress_eps must be 0 (off) or finite and >= 1e-8");
   if (kernel->kind != H2_KERNEL_LAPLACE && kernel->kind != H2_KERNEL_HELMHOLTZ)
     return set_error(H2_ERR_UNSUPPORTED, "unsupported kernel");
   const bool helm = kernel->kind == H2_KERNEL_HELMHOLTZ;
@@ -345,6 +348,11 @@ h2_status build_impl(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* 
       }
       // the staging buffers return to the pool only after the launches ran
       H2_HIP(hipStreamSynchronize(strm));
+    }
+    if (opts->recompress_eps > 0.0) {
+      h2_mat R = recompress_impl(ctx, M, opts->recompress_eps);
+      h2_free(M);
+      M = R;
     }
     *out = M;
     return H2_OK;

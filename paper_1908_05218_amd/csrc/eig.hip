@@ -1478,6 +1478,10 @@ __global__ __launch_bounds__(NT) void k_eig_val(EigArgs p0, EigArgs p1, int dv) 
       lo0 = fmin(thr, lo) - tol;
     }
   }
+  if (p.kmax) {
+    const int m = p.kmax[v.c];
+    k = k < m ? k : (m < 1 ? 1 : m);
+  }
   // the k leading eigenvalues by grouped multisection: G lanes per
   // eigenvalue, two points each.  The Sturm counts are issue-bound, so G
   // minimises (waves per SIMD) x (iterations) rather than the iterations
@@ -1680,7 +1684,8 @@ __global__ __launch_bounds__(256) void k_ceig_embed(CEigArgs p0, CEigArgs p1) {
   double w[3];
   for (int m = 0; m < 3; ++m) {
     double t = 0.0;
-    for (int i = tid; i < D; i += 256) t += p.G[m][gs + i + (long long)i * D];
+    if (p.G[m])
+      for (int i = tid; i < D; i += 256) t += p.G[m][gs + i + (long long)i * D];
     t = block_sum<256>(t, red);
     w[m] = t > 0.0 ? 1.0 / t : 0.0;
   }
@@ -1695,6 +1700,7 @@ __global__ __launch_bounds__(256) void k_ceig_embed(CEigArgs p0, CEigArgs p1) {
     double xr = 0.0, xi = 0.0;
     for (int m = 0; m < 3; ++m) {
       const double* g = p.G[m];
+      if (!g) continue;
       xr += w[m] * 0.5 * (g[a] + g[b]);
       xi += w[m] * 0.5 * (g[p.gplane + a] - g[p.gplane + b]);
     }
@@ -1727,7 +1733,8 @@ __global__ __launch_bounds__(256) void k_ceig_extract(CEigArgs p0, CEigArgs p1) 
   }
   __syncthreads();
   int acc = 0;
-  for (int m = 0; m < ke && acc < n; ++m) {
+  const int cap = p.kmax ? (p.kmax[c] < 1 ? 1 : (p.kmax[c] < n ? p.kmax[c] : n)) : n;
+  for (int m = 0; m < ke && acc < cap; ++m) {
     for (int r = tid; r < n; r += NT) {
       zr[r] = Ue[r + (long long)m * D2];
       zi[r] = Ue[D + r + (long long)m * D2];

@@ -327,6 +327,28 @@ struct BulkScope {
 };
 
 h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C);
+// Truncated eigen-decompositions of one level's row and column Gram sums,
+// both sets in one launch per phase (complex Grams through their real
+// embedding).  Gr / Gc: three components per side, each divided by its trace
+// (an empty Buf is an absent component; the first must be present); k1/k2:
+// live rows as in h2k::EigArgs; kmax_r / kmax_c (nullable, per cluster): at
+// most that many vectors are kept.  Outputs U (D x D per cluster) and ranks.
+struct EigLevel {
+  h2_ctx ctx;
+  hipStream_t st;
+  Profiler* prof;
+  int* status;  // device flags: [0] non-finite, [1] dimension over limit
+  bool cplx;
+  double tau;   // relative eigenvalue threshold
+  bool exact;   // keep every eigenvector
+};
+void eig_level(const EigLevel& e, int l, int D, const Buf* Gr, const Buf* Gc, Buf& Ur, Buf& Uc,
+               Buf& rank_r, Buf& rank_c, const int* k1r, const int* k2r, const int* k1c,
+               const int* k2c, int kstride, int half, const int* kmax_r = nullptr,
+               const int* kmax_c = nullptr);
+// H^2 recompression of M at eps (new nested orthonormal bases, projected
+// couplings, M's dense blocks), a new matrix of ctx
+h2_mat recompress_impl(h2_ctx ctx, h2_mat M, double eps);
 // measured tile choices of the batched GEMM (tiles.txt), tuning hooks
 std::string tile_key(int tsize, int af32, int bf32, int triple, int tA, int tB, int m, int n, int k,
                      int nout, long long ntask);

@@ -63,7 +63,7 @@ struct SegsumArgs {
 };
 
 struct GramNormArgs {
-  const double* G[3];
+  const double* G[3];  // G[1], G[2] may be null (absent components)
   long long stride;
   int D;
   double* out;
@@ -91,6 +91,7 @@ struct EigArgs {
   long long sstride;
   double tau;
   int exact;
+  const int* kmax;  // nullable: kmax[c] caps the kept count of cluster c (at least 1 kept)
   int* status;  // [0] non-finite, [1] dimension over limit
 };
 
@@ -109,7 +110,7 @@ struct EigArgs {
 //    direction and is dropped.  The accepted vectors go to U (D x D, planes
 //    [real | imaginary] at +uplane, padded rows), rank[c] = their count.
 struct CEigArgs {
-  const double* G[3];  // complex Gram components (cluster stride D*D, planes at +gplane)
+  const double* G[3];  // complex Gram components (cluster stride D*D, planes at +gplane; G[1], G[2] may be null)
   long long gplane;
   int D, half;
   const int* k1;
@@ -122,6 +123,7 @@ struct CEigArgs {
   double* U;
   long long uplane;
   int* rank;
+  const int* kmax;  // nullable: kmax[c] caps the accepted count (at least 1)
   int* status;
 };
 hipError_t launch_ceig_embed(const CEigArgs& a, const CEigArgs& b, int nclusters, hipStream_t s);

@@ -319,9 +319,11 @@ __global__ __launch_bounds__(256) void k_gram_norm(GramNormArgs p) {
   __shared__ double tr[3];
   __shared__ double red[256];
   for (int comp = 0; comp < 3; ++comp) {
-    const double* g = p.G[comp] + (long long)c * p.stride;
     double s = 0;
-    for (int i = threadIdx.x; i < D; i += 256) s += g[i + (long long)i * D];
+    if (p.G[comp]) {
+      const double* g = p.G[comp] + (long long)c * p.stride;
+      for (int i = threadIdx.x; i < D; i += 256) s += g[i + (long long)i * D];
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -340,7 +342,9 @@ __global__ __launch_bounds__(256) void k_gram_norm(GramNormArgs p) {
   // products may leave the part above it unwritten)
   for (int e = threadIdx.x; e < D * D; e += 256) {
     if (e % D < e / D) continue;
-    const double v = w0 * p.G[0][base + e] + w1 * p.G[1][base + e] + w2 * p.G[2][base + e];
+    double v = w0 * p.G[0][base + e];
+    if (p.G[1]) v += w1 * p.G[1][base + e];
+    if (p.G[2]) v += w2 * p.G[2][base + e];
     if (!(v == v) || v - v != 0.0) bad = 1;
     p.out[base + e] = v;
   }

@@ -154,6 +154,135 @@ FlopCounts flop_counts(const Structure& s, const FlopRanks& r) {
   return f;
 }
 
+// the three eigensolver phases, each timed as its own kernel class
+static void run_eig(const EigLevel& e, const h2k::EigArgs* ea, int ncl) {
+  const int phase[3] = {h2k::kEigPhaseTri, h2k::kEigPhaseVal, h2k::kEigPhaseVec};
+  const int kind[3] = {kKindEig, kKindEigVal, kKindEigVec};
+  for (int ph = 0; ph < 3; ++ph) {
+    hipEvent_t ev = nullptr;
+    e.prof->begin(kind[ph], 0, &ev);
+    H2_HIP(h2k::launch_eig(ea[0], ea[1], ncl, e.st, phase[ph]));
+    e.prof->end(ev, kind[ph], 0);
+  }
+}
+
+void eig_level(const EigLevel& e, int l, int D, const Buf* Gr, const Buf* Gc, Buf& Ur_, Buf& Uc_,
+               Buf& rank_r_, Buf& rank_c_, const int* k1r, const int* k2r, const int* k1c,
+               const int* k2c, int kstride, int half, const int* kmax_r, const int* kmax_c) {
+  h2_ctx ctx = e.ctx;
+  hipStream_t st = e.st;
+  const bool cplx = e.cplx;
+  const size_t gb = cplx ? 2 * sizeof(double) : sizeof(double);
+  const int ncl = 1 << l;
+  if ((cplx ? 2 * D : D) > h2k::kEigNmax)
+    throw Error(H2_ERR_UNSUPPORTED, "the Gram matrices at level " + std::to_string(l) +
+                                        " have dimension " + std::to_string(D) +
+                                        (cplx ? " (complex)" : "") +
+                                        ", beyond the eigensolver limit of " +
+                                        std::to_string(cplx ? h2k::kEigNmax / 2 : h2k::kEigNmax));
+  if (cplx) {
+    // Hermitian Grams through their real embedding (dimension 2D)
+    const int D2 = 2 * D;
+    Buf E[2] = {Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double)),
+                Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double))};
+    Buf Ue[2] = {Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double)),
+                 Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double))};
+    Buf nlive(ctx, (size_t)2 * ncl * sizeof(int)), rank_e(ctx, (size_t)2 * ncl * sizeof(int));
+    Ur_ = Buf(ctx, (size_t)ncl * D * D * gb, false, true);
+    Uc_ = Buf(ctx, (size_t)ncl * D * D * gb, false, true);
+    rank_r_ = Buf(ctx, (size_t)ncl * sizeof(int));
+    rank_c_ = Buf(ctx, (size_t)ncl * sizeof(int));
+    h2k::CEigArgs ca[2];
+    for (int side = 0; side < 2; ++side) {
+      h2k::CEigArgs& a = ca[side];
+      a = h2k::CEigArgs{};
+      for (int c = 0; c < 3; ++c) a.G[c] = (side ? Gc : Gr)[c].d();
+      a.gplane = ctx->plane((side ? Gc : Gr)[0].p());
+      a.D = D;
+      a.half = half;
+      a.k1 = side ? k1c : k1r;
+      a.k2 = side ? k2c : k2r;
+      a.kstride = kstride;
+      a.E = E[side].d();
+      a.nlive = nlive.as<int>() + side * ncl;
+      a.Ue = Ue[side].d();
+      a.rank_e = rank_e.as<int>() + side * ncl;
+      a.U = (side ? Uc_ : Ur_).d();
+      a.uplane = ctx->plane((side ? Uc_ : Ur_).p());
+      a.rank = (side ? rank_c_ : rank_r_).as<int>();
+      a.kmax = side ? kmax_c : kmax_r;
+      a.status = e.status;
+    }
+    H2_HIP(h2k::launch_ceig_embed(ca[0], ca[1], ncl, st));
+    const long long ss = h2k::eig_scratch_doubles(D2);
+    Buf scratch(ctx, (size_t)2 * ncl * ss * sizeof(double));
+    h2k::EigArgs ea[2];
+    for (int side = 0; side < 2; ++side) {
+      h2k::EigArgs& x = ea[side];
+      x = h2k::EigArgs{};
+      x.G = E[side].d();
+      x.gstride = (long long)D2 * D2;
+      x.D = D2;
+      x.U = Ue[side].d();
+      x.ustride = (long long)D2 * D2;
+      x.rank = rank_e.as<int>() + side * ncl;
+      x.k1 = nlive.as<int>() + side * ncl;
+      x.k2 = nlive.as<int>() + side * ncl;
+      x.kstride = 1;
+      x.half = D;
+      x.scratch = scratch.d() + (size_t)side * ncl * ss;
+      x.sstride = ss;
+      x.tau = e.tau;
+      x.exact = e.exact ? 1 : 0;
+      x.status = e.status;
+    }
+    run_eig(e, ea, ncl);
+    hipEvent_t ev = nullptr;
+    e.prof->begin(kKindEigVec, 0, &ev);
+    H2_HIP(h2k::launch_ceig_extract(ca[0], ca[1], ncl, st));
+    e.prof->end(ev, kKindEigVec, 0);
+    return;
+  }
+  Buf Gnr(ctx, (size_t)ncl * D * D * sizeof(double)), Gnc(ctx, (size_t)ncl * D * D * sizeof(double));
+  for (int side = 0; side < 2; ++side) {
+    h2k::GramNormArgs ga{};
+    for (int c = 0; c < 3; ++c) ga.G[c] = (side ? Gc : Gr)[c].d();
+    ga.stride = (long long)D * D;
+    ga.D = D;
+    ga.out = (side ? Gnc : Gnr).d();
+    ga.status = e.status;
+    H2_HIP(h2k::launch_gram_norm(ga, ncl, st));
+  }
+  Ur_ = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
+  Uc_ = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
+  rank_r_ = Buf(ctx, (size_t)ncl * sizeof(int));
+  rank_c_ = Buf(ctx, (size_t)ncl * sizeof(int));
+  const long long ss = h2k::eig_scratch_doubles(D);
+  Buf scratch(ctx, (size_t)2 * ncl * ss * sizeof(double));
+  h2k::EigArgs ea[2];
+  for (int side = 0; side < 2; ++side) {
+    h2k::EigArgs& x = ea[side];
+    x = h2k::EigArgs{};
+    x.G = (side ? Gnc : Gnr).d();
+    x.gstride = (long long)D * D;
+    x.D = D;
+    x.U = (side ? Uc_ : Ur_).d();
+    x.ustride = (long long)D * D;
+    x.rank = (side ? rank_c_ : rank_r_).as<int>();
+    x.k1 = side ? k1c : k1r;
+    x.k2 = side ? k2c : k2r;
+    x.kstride = kstride;
+    x.half = half;
+    x.scratch = scratch.d() + (size_t)side * ncl * ss;
+    x.sstride = ss;
+    x.tau = e.tau;
+    x.exact = e.exact ? 1 : 0;
+    x.kmax = side ? kmax_c : kmax_r;
+    x.status = e.status;
+  }
+  run_eig(e, ea, ncl);
+}
+
 h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C_out) {
   ActiveCtx active(ctx);
   // FP32-bulk: block products on FP32 MFMA over float copies of the operands;
@@ -264,127 +393,11 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   }
 
   // the three eigensolver phases, each timed as its own kernel class
-  auto run_eig = [&](const h2k::EigArgs* ea, int ncl) {
-    const int phase[3] = {h2k::kEigPhaseTri, h2k::kEigPhaseVal, h2k::kEigPhaseVec};
-    const int kind[3] = {kKindEig, kKindEigVal, kKindEigVec};
-    for (int ph = 0; ph < 3; ++ph) {
-      hipEvent_t e = nullptr;
-      prof.begin(kind[ph], 0, &e);
-      H2_HIP(h2k::launch_eig(ea[0], ea[1], ncl, st, phase[ph]));
-      prof.end(e, kind[ph], 0);
-    }
-  };
-  // truncated eigen-decompositions of a level's normalised row and column
-  // Grams, both sets in one launch
   auto eig_level = [&](int l, int D, Buf Gr[3], Buf Gc[3], Buf& Ur_, Buf& Uc_, Buf& rank_r_,
                        Buf& rank_c_, const int* k1r, const int* k2r, const int* k1c,
                        const int* k2c, int kstride, int half) {
-    const int ncl = 1 << l;
-    if ((cplx ? 2 * D : D) > h2k::kEigNmax)
-      throw Error(H2_ERR_UNSUPPORTED, "the Gram matrices at level " + std::to_string(l) +
-                                          " have dimension " + std::to_string(D) +
-                                          (cplx ? " (complex)" : "") +
-                                          ", beyond the eigensolver limit of " +
-                                          std::to_string(cplx ? h2k::kEigNmax / 2 : h2k::kEigNmax));
-    if (cplx) {
-      // Hermitian Grams through their real embedding (dimension 2D)
-      const int D2 = 2 * D;
-      Buf E[2] = {Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double)),
-                  Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double))};
-      Buf Ue[2] = {Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double)),
-                   Buf(ctx, (size_t)ncl * D2 * D2 * sizeof(double))};
-      Buf nlive(ctx, (size_t)2 * ncl * sizeof(int)), rank_e(ctx, (size_t)2 * ncl * sizeof(int));
-      Ur_ = Buf(ctx, (size_t)ncl * D * D * gb, false, true);
-      Uc_ = Buf(ctx, (size_t)ncl * D * D * gb, false, true);
-      rank_r_ = Buf(ctx, (size_t)ncl * sizeof(int));
-      rank_c_ = Buf(ctx, (size_t)ncl * sizeof(int));
-      h2k::CEigArgs ca[2];
-      for (int side = 0; side < 2; ++side) {
-        h2k::CEigArgs& a = ca[side];
-        a = h2k::CEigArgs{};
-        for (int c = 0; c < 3; ++c) a.G[c] = (side ? Gc : Gr)[c].d();
-        a.gplane = ctx->plane((side ? Gc : Gr)[0].p());
-        a.D = D;
-        a.half = half;
-        a.k1 = side ? k1c : k1r;
-        a.k2 = side ? k2c : k2r;
-        a.kstride = kstride;
-        a.E = E[side].d();
-        a.nlive = nlive.as<int>() + side * ncl;
-        a.Ue = Ue[side].d();
-        a.rank_e = rank_e.as<int>() + side * ncl;
-        a.U = (side ? Uc_ : Ur_).d();
-        a.uplane = ctx->plane((side ? Uc_ : Ur_).p());
-        a.rank = (side ? rank_c_ : rank_r_).as<int>();
-        a.status = status.as<int>();
-      }
-      H2_HIP(h2k::launch_ceig_embed(ca[0], ca[1], ncl, st));
-      const long long ss = h2k::eig_scratch_doubles(D2);
-      Buf scratch(ctx, (size_t)2 * ncl * ss * sizeof(double));
-      h2k::EigArgs ea[2];
-      for (int side = 0; side < 2; ++side) {
-        h2k::EigArgs& e = ea[side];
-        e = h2k::EigArgs{};
-        e.G = E[side].d();
-        e.gstride = (long long)D2 * D2;
-        e.D = D2;
-        e.U = Ue[side].d();
-        e.ustride = (long long)D2 * D2;
-        e.rank = rank_e.as<int>() + side * ncl;
-        e.k1 = nlive.as<int>() + side * ncl;
-        e.k2 = nlive.as<int>() + side * ncl;
-        e.kstride = 1;
-        e.half = D;
-        e.scratch = scratch.d() + (size_t)side * ncl * ss;
-        e.sstride = ss;
-        e.tau = tau;
-        e.exact = exact ? 1 : 0;
-        e.status = status.as<int>();
-      }
-      run_eig(ea, ncl);
-      hipEvent_t ev = nullptr;
-      prof.begin(kKindEigVec, 0, &ev);
-      H2_HIP(h2k::launch_ceig_extract(ca[0], ca[1], ncl, st));
-      prof.end(ev, kKindEigVec, 0);
-      return;
-    }
-    Buf Gnr(ctx, (size_t)ncl * D * D * sizeof(double)), Gnc(ctx, (size_t)ncl * D * D * sizeof(double));
-    for (int side = 0; side < 2; ++side) {
-      h2k::GramNormArgs ga{};
-      for (int c = 0; c < 3; ++c) ga.G[c] = (side ? Gc : Gr)[c].d();
-      ga.stride = (long long)D * D;
-      ga.D = D;
-      ga.out = (side ? Gnc : Gnr).d();
-      ga.status = status.as<int>();
-      H2_HIP(h2k::launch_gram_norm(ga, ncl, st));
-    }
-    Ur_ = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
-    Uc_ = Buf(ctx, (size_t)ncl * D * D * sizeof(double));
-    rank_r_ = Buf(ctx, (size_t)ncl * sizeof(int));
-    rank_c_ = Buf(ctx, (size_t)ncl * sizeof(int));
-    const long long ss = h2k::eig_scratch_doubles(D);
-    Buf scratch(ctx, (size_t)2 * ncl * ss * sizeof(double));
-    h2k::EigArgs ea[2];
-    for (int side = 0; side < 2; ++side) {
-      h2k::EigArgs& e = ea[side];
-      e = h2k::EigArgs{};
-      e.G = (side ? Gnc : Gnr).d();
-      e.gstride = (long long)D * D;
-      e.D = D;
-      e.U = (side ? Uc_ : Ur_).d();
-      e.ustride = (long long)D * D;
-      e.rank = (side ? rank_c_ : rank_r_).as<int>();
-      e.k1 = side ? k1c : k1r;
-      e.k2 = side ? k2c : k2r;
-      e.kstride = kstride;
-      e.half = half;
-      e.scratch = scratch.d() + (size_t)side * ncl * ss;
-      e.sstride = ss;
-      e.tau = tau;
-      e.exact = exact ? 1 : 0;
-      e.status = status.as<int>();
-    }
-    run_eig(ea, ncl);
+    const EigLevel e{ctx, st, &prof, status.as<int>(), cplx, tau, exact};
+    h2::eig_level(e, l, D, Gr, Gc, Ur_, Uc_, rank_r_, rank_c_, k1r, k2r, k1c, k2c, kstride, half);
   };
   auto read_ranks = [&](int l, Buf& rr_, Buf& rc_) {
     const int ncl = 1 << l;
