@@ -346,6 +346,40 @@ def fixed_basis_leg(h2, ctx, dA, n, eps):
     return {"ms": ms, "eps_rel": erel, "rank_max": rmax, "precision": "fp32_bulk"}
 
 
+def recompress_leg(h2, ctx, dA, n, eps, steps=3):
+    """The input recompressed at eps on the device (h2_recompress; the paper
+    cites its input construction without describing it, Section VI): its
+    time, the new rank profile (the input has rank 27 everywhere), and the
+    FP32-bulk product of the recompressed inputs at eps with its time and its
+    error against the exact product of the original inputs."""
+    import numpy as np
+    h2.recompress(ctx, dA, eps).free()
+    t = time.perf_counter()
+    R = h2.recompress(ctx, dA, eps)
+    rec_ms = 1e3 * (time.perf_counter() - t)
+    x = np.random.default_rng(7).standard_normal(n)
+    erel_in = float(np.linalg.norm(h2.matvec(ctx, R, x) - h2.matvec(ctx, dA, x)) /
+                    np.linalg.norm(h2.matvec(ctx, dA, x)))
+    h2.mmp(ctx, R, R, eps, precision="fp32_bulk").free()
+    t = time.perf_counter()
+    for _ in range(steps):
+        h2.mmp(ctx, R, R, eps, precision="fp32_bulk").free()
+    ms = 1e3 * (time.perf_counter() - t) / steps
+    C = h2.mmp(ctx, R, R, eps, precision="fp32_bulk")
+    ref = h2.matvec(ctx, dA, h2.matvec(ctx, dA, x))
+    erel = float(np.linalg.norm(h2.matvec(ctx, C, x) - ref) / np.linalg.norm(ref))
+    out = {"recompress_ms": rec_ms, "eps": eps, "input_eps_rel": erel_in,
+           "rank_max_input": 27, "rank_max_recompressed": h2.stats(R)["rank_max_r"],
+           "rank_mean_recompressed": h2.stats(R)["rank_mean_r"],
+           "product_ms": ms, "product_value": n / (ms * 1e-3), "product_eps_rel": erel,
+           "product_rank_max": h2.stats(C)["rank_max_r"]}
+    C.free()
+    R.free()
+    print(f"[bench] recompression {rec_ms:.1f} ms, product of recompressed inputs {ms:.1f} ms "
+          f"(eps_rel {erel:.2e})", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,6 +401,9 @@ def main():
                     help="points of the Newton-Schulz inverse leg (0: skip)")
     ap.add_argument("--sphere-n", type=int, default=32768,
                     help="points of the complex Helmholtz sphere product (0: skip)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="only the headline products (no fixed-basis, recompression, sphere, "
+                         "serving, inverse or CPU legs): the command the kernel traces profile")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device copies (scale of the HBM byte counters)")
     args = ap.parse_args()
@@ -412,7 +449,11 @@ def main():
     if not args.no_compare:
         op = "fp64" if args.precision == "fp32_bulk" else "fp32_bulk"
         other = run_precision(h2, ctx, dA, A.n, op, args.steps, args.warmup, args.eps)
-    fixed = fixed_basis_leg(h2, ctx, dA, A.n, args.eps)
+    if args.no_legs:
+        args.sphere_n = args.serve_requests = args.inverse_n = 0
+        args.no_cpu_baseline = True
+    fixed = None if args.no_legs else fixed_basis_leg(h2, ctx, dA, A.n, args.eps)
+    recomp = None if args.no_legs else recompress_leg(h2, ctx, dA, A.n, args.eps)
     ctx.close()
     st = head["stats"]
     ms = head["ms"]
@@ -452,7 +493,10 @@ def main():
                     "device_ms_per_step": other["device_ms"], "eps_rel": other["eps_rel"],
                     "speedup_of_headline": other["ms"] / ms,
                     "breakdown": other["breakdown"], "roofline": other["roofline"]}
-    out["fixed_basis"] = fixed
+    if fixed is not None:
+        out["fixed_basis"] = fixed
+    if recomp is not None:
+        out["recompressed_inputs"] = recomp
     if args.sphere_n > 0:
         out["sphere_complex"] = sphere_leg(args.sphere_n, args.steps)
     if args.serve_requests > 0:

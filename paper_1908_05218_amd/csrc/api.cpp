@@ -131,10 +131,11 @@ static void launch_gemm(hipStream_t s, Profiler* prof, int kind, const DevList& 
   a.b_idx = tl.b;
   a.alpha = (T)alpha;
   a.beta = (T)beta;
-  a.symbol = kind == kKindTriple ? 1 : kind == kKindTarget ? 2 : 0;
+  a.symbol = kind == kKindTriple ? 1 : kind == kKindTarget ? 2 : kind == kKindGram ? 3 : 0;
   a.lower = lower ? 1 : 0;
-  const std::string key = tile_key((int)sizeof(T), a.A.f32, a.B.f32, a.symbol, tA, tB, m, n, k,
-                                   tl.nout, (long long)tl.ntask);
+  // the Gram sums share the tile table's keys with the other plain batches
+  const std::string key = tile_key((int)sizeof(T), a.A.f32, a.B.f32, a.symbol == 3 ? 0 : a.symbol,
+                                   tA, tB, m, n, k, tl.nout, (long long)tl.ntask);
   a.tile = tile_for(key);
   hipEvent_t ev = nullptr;
   // a symmetric output computed on and below its diagonal: n (n + 1) / 2 entries

@@ -35,7 +35,8 @@ struct BgemmArgs {
   const int* b_idx;    // [ntask]
   T alpha, beta;
   int symbol;  // kernel symbol for traces: 0 k_bgemm, 1 k_bgemm_triple (per-triple
-               // contractions), 2 k_bgemm_target (per-target products)
+               // contractions), 2 k_bgemm_target (per-target products),
+               // 3 k_bgemm_gram (Gram sums, FP64 only)
   int tile;    // workgroup tile (kTile* id), -1: chosen from the output shape
   // symmetric outputs read only on and below the diagonal: compute only the
   // tiles there (m == n and a square tile; otherwise ignored)

@@ -24,6 +24,8 @@
 // child block inside its parent's 2x2 tile (the "collected" non-leaf blocks
 // of equations nonleafA and nonleafB) is addressed in place.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 #include "kernels.h"
@@ -272,9 +274,10 @@ __device__ __forceinline__ void bgemm_body(const BgemmArgs<T>& p) {
     }
 }
 
-// Two entry points over the same body: the block-product ("triple") batches of
-// the coupling step get their own symbol so that traces separate them from
-// the projections, collects, Gram sums and splits.
+// Entry points over the same body, one per kernel class so that traces and
+// counters separate them: the block-product ("triple") batches of the
+// coupling step, the per-target products, the Gram sums (FP64) and the rest
+// (projections, collects, splits, basis products).
 template <typename T, int TM, int TN, typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
   bgemm_body<T, TM, TN, TA, TB>(p);
@@ -287,6 +290,11 @@ __global__ __launch_bounds__(256) void k_bgemm_triple(BgemmArgs<T> p) {
 
 template <typename T, int TM, int TN, typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_bgemm_target(BgemmArgs<T> p) {
+  bgemm_body<T, TM, TN, TA, TB>(p);
+}
+
+template <typename T, int TM, int TN, typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_bgemm_gram(BgemmArgs<T> p) {
   bgemm_body<T, TM, TN, TA, TB>(p);
 }
 
@@ -458,7 +466,12 @@ static hipError_t launch_tile(BgemmArgs<T> a, hipStream_t s) {
     H2K_LAUNCH(k_bgemm_triple);
   else if (a.symbol == 2)
     H2K_LAUNCH(k_bgemm_target);
-  else
+  else if constexpr (std::is_same<T, double>::value) {
+    if (a.symbol == 3)
+      H2K_LAUNCH(k_bgemm_gram);
+    else
+      H2K_LAUNCH(k_bgemm);
+  } else
     H2K_LAUNCH(k_bgemm);
 #undef H2K_LAUNCH
   return hipGetLastError();
