@@ -346,6 +346,47 @@ def fixed_basis_leg(h2, ctx, dA, n, eps):
     return {"ms": ms, "eps_rel": erel, "rank_max": rmax, "precision": "fp32_bulk"}
 
 
+def matvec_graph_leg(h2, ctx, dA, n, reps=100):
+    """The exact mat-vec of the input with device vectors (the inner step of
+    an iterative solver): `reps` eager calls of h2_matvec_noalloc against
+    `reps` replays of one HIP graph that captured it (torch's graph capture
+    on a torch stream), both timed with events on that stream; the graph's
+    result is checked against the eager one."""
+    import torch
+    x = torch.randn(n, dtype=torch.float64, device="cuda", generator=None)
+    y = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        h2.matvec_noalloc(ctx, dA, x, y, stream=s)
+    torch.cuda.synchronize()
+    ref = y.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        h2.matvec_noalloc(ctx, dA, x, y, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    eager_us = 1e3 * e0.elapsed_time(e1) / reps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        h2.matvec_noalloc(ctx, dA, x, y, stream=s)
+    torch.cuda.synchronize()
+    y.zero_()
+    e0.record(s)
+    with torch.cuda.stream(s):
+        for _ in range(reps):
+            g.replay()
+    e1.record(s)
+    torch.cuda.synchronize()
+    graph_us = 1e3 * e0.elapsed_time(e1) / reps
+    same = bool(torch.equal(y, ref))
+    print(f"[bench] mat-vec: eager {eager_us:.1f} us, graph replay {graph_us:.1f} us", file=sys.stderr,
+          flush=True)
+    return {"eager_us_per_call": eager_us, "graph_us_per_call": graph_us, "calls": reps,
+            "graph_equals_eager": same}
+
+
 def recompress_leg(h2, ctx, dA, n, eps, steps=3):
     """The input recompressed at eps on the device (h2_recompress; the paper
     cites its input construction without describing it, Section VI): its
@@ -454,6 +495,7 @@ def main():
         args.no_cpu_baseline = True
     fixed = None if args.no_legs else fixed_basis_leg(h2, ctx, dA, A.n, args.eps)
     recomp = None if args.no_legs else recompress_leg(h2, ctx, dA, A.n, args.eps)
+    mvg = None if args.no_legs else matvec_graph_leg(h2, ctx, dA, A.n)
     ctx.close()
     st = head["stats"]
     ms = head["ms"]
@@ -497,6 +539,8 @@ def main():
         out["fixed_basis"] = fixed
     if recomp is not None:
         out["recompressed_inputs"] = recomp
+    if mvg is not None:
+        out["matvec_graph"] = mvg
     if args.sphere_n > 0:
         out["sphere_complex"] = sphere_leg(args.sphere_n, args.steps)
     if args.serve_requests > 0:
