@@ -154,3 +154,32 @@ def test_recompress_plates64k_full_size(ctx):
         n0 = np.linalg.norm(y0)
         assert np.linalg.norm(y - y_ref) <= (1e-6 if same == 1.0 else 1e-4) * n0
         assert np.linalg.norm(y - y0) <= 1e-4 * n0
+
+
+@pytest.mark.parametrize("name", ["plates2048", "random_nonsym", "random_complex"])
+def test_product_of_recompressed_matches_checker(ctx, name):
+    """Products of recompressed inputs (orthonormal variable-rank bases, levels
+    above l_min without a basis) against the checker's product of the very
+    same inputs (exported from the device)."""
+    from oracle import mmp as omp
+    print(f"case product of recompressed {name}", flush=True)
+    M = SMALL[name]
+    eps = 1e-5
+    R = h2.recompress(ctx, h2.load(ctx, M.to_flat()), 1e-4)
+    Rh = H2Matrix.from_flat(h2.export(R), tree=M.tree)
+    Co, info = omp.h2_mmp(Rh, Rh, eps)
+    C = h2.mmp(ctx, R, R, eps)
+    ref = h2ops.to_dense(Rh) @ h2ops.to_dense(Rh)
+    Dg, Do = h2.to_dense(ctx, C, M.n), h2ops.to_dense(Co)
+    nref = np.linalg.norm(ref)
+    assert np.linalg.norm(Dg - ref) <= eps * nref
+    assert np.linalg.norm(Do - ref) <= eps * nref
+    assert np.linalg.norm(Dg - Do) <= eps * np.linalg.norm(Do)
+    flat = h2.export(C)
+    got = np.concatenate([np.asarray(flat["krow"]), np.asarray(flat["kcol"])])
+    want = []
+    for key in ("ranks_row", "ranks_col"):
+        for lev, r in enumerate(info[key]):
+            want.extend(r if lev >= info["lmin"] else [0] * len(r))
+    want = np.asarray(want)
+    assert float(np.mean(got == want)) >= 0.99 and np.abs(got - want).max() <= 2
