@@ -320,7 +320,10 @@ __global__ __launch_bounds__(256) void k_segsum(SegsumArgs<T> p) {
 }
 
 // Normalised Gram sum of one cluster: sum over the non-empty components of
-// G_c / trace(G_c) (each component divided by its trace).
+// G_c / trace(G_c) (each component divided by its trace).  The workgroups
+// blockIdx.y of a cluster each take every gridDim.y-th group of four columns
+// (one column per wave, the lanes down its rows: coalesced), after computing
+// the cluster's traces themselves.
 __global__ __launch_bounds__(256) void k_gram_norm(GramNormArgs p) {
   const int c = blockIdx.x;
   const int D = p.D;
@@ -345,16 +348,23 @@ __global__ __launch_bounds__(256) void k_gram_norm(GramNormArgs p) {
   const double w1 = tr[1] > 0 ? 1.0 / tr[1] : 0.0;
   const double w2 = tr[2] > 0 ? 1.0 / tr[2] : 0.0;
   const long long base = (long long)c * p.stride;
+  const double* g0 = p.G[0] + base;
+  const double* g1 = p.G[1] ? p.G[1] + base : nullptr;
+  const double* g2 = p.G[2] ? p.G[2] + base : nullptr;
+  double* out = p.out + base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bad = 0;
   // the sums are symmetric and read on and below the diagonal only (the
   // products may leave the part above it unwritten)
-  for (int e = threadIdx.x; e < D * D; e += 256) {
-    if (e % D < e / D) continue;
-    double v = w0 * p.G[0][base + e];
-    if (p.G[1]) v += w1 * p.G[1][base + e];
-    if (p.G[2]) v += w2 * p.G[2][base + e];
-    if (!(v == v) || v - v != 0.0) bad = 1;
-    p.out[base + e] = v;
+  for (int j = 4 * blockIdx.y + wave; j < D; j += 4 * gridDim.y) {
+    const long long cj = (long long)j * D;
+    for (int i = j + lane; i < D; i += 64) {
+      double v = w0 * g0[cj + i];
+      if (g1) v += w1 * g1[cj + i];
+      if (g2) v += w2 * g2[cj + i];
+      if (!(v == v) || v - v != 0.0) bad = 1;
+      out[cj + i] = v;
+    }
   }
   if (bad) p.status[0] = 1;
 }
@@ -513,7 +523,11 @@ hipError_t launch_segsum(const SegsumArgs<T>& a, hipStream_t s) {
 
 hipError_t launch_gram_norm(const GramNormArgs& a, int nclusters, hipStream_t s) {
   if (nclusters <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gram_norm, dim3(nclusters), dim3(256), 0, s, a);
+  // about 2048 workgroups in all, at most one per group of four columns
+  const int groups = (a.D + 3) / 4;
+  int per = (2048 + nclusters - 1) / nclusters;
+  per = per < 1 ? 1 : (per > groups ? groups : per);
+  hipLaunchKernelGGL(k_gram_norm, dim3(nclusters, per), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
