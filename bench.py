@@ -387,6 +387,46 @@ def matvec_graph_leg(h2, ctx, dA, n, reps=100):
             "graph_equals_eager": same}
 
 
+def cube_recompressed_leg(n=65536, eps=1e-4, steps=2):
+    """The 2^20-point cube workload's pipeline at a sixteenth of its size
+    (the product's leaf-level temporaries, n_pad^2 doubles per leaf block,
+    keep the full size beyond one GPU's memory): N uniform points in the unit
+    cube (seed 0), leaf 64, eta 1, 1/(4 pi r) with unit diagonal, Chebyshev
+    4x4x4 bases recompressed on the device at eps, then C = A A at eps in
+    FP32-bulk; eps_rel by the exact H^2 mat-vec."""
+    import numpy as np
+    import paper_1908_05218_amd as h2
+    from h2inputs import points
+    ctx = h2.Context(0)
+    pts = points.cube(n, 0)
+    t0 = time.perf_counter()
+    A = h2.build(ctx, pts, 64, 1.0, 4, 1.0, recompress_eps=eps)
+    build_ms = 1e3 * (time.perf_counter() - t0)
+    h2.mmp(ctx, A, A, eps, precision="fp32_bulk").free()
+    walls = []
+    C = None
+    for _ in range(steps):
+        if C is not None:
+            C.free()
+        t0 = time.perf_counter()
+        C = h2.mmp(ctx, A, A, eps, precision="fp32_bulk")
+        walls.append(time.perf_counter() - t0)
+    st = h2.stats(C)
+    x = np.random.default_rng(1).standard_normal(n)
+    ref = h2.matvec(ctx, A, h2.matvec(ctx, A, x))
+    erel = float(np.linalg.norm(h2.matvec(ctx, C, x) - ref) / np.linalg.norm(ref))
+    out = {"workload": f"cube{n // 1024}k", "N": n, "leaf_size": 64,
+           "basis": "chebyshev 4x4x4 recompressed on the device", "eps": eps,
+           "build_and_recompress_ms": build_ms, "input_rank_max": h2.stats(A)["rank_max_r"],
+           "ms_per_step": 1e3 * float(np.mean(walls)), "unknowns_per_s": n / float(np.mean(walls)),
+           "eps_rel": erel, "rank_max": st["rank_max_r"], "peak_bytes": st["bytes_device"],
+           "precision": "fp32_bulk"}
+    ctx.close()
+    print(f"[bench] cube {n}: {out['ms_per_step']:.0f} ms per product, eps_rel {erel:.2e}",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def recompress_leg(h2, ctx, dA, n, eps, steps=3):
     """The input recompressed at eps on the device (h2_recompress; the paper
     cites its input construction without describing it, Section VI): its
@@ -442,6 +482,8 @@ def main():
                     help="points of the Newton-Schulz inverse leg (0: skip)")
     ap.add_argument("--sphere-n", type=int, default=32768,
                     help="points of the complex Helmholtz sphere product (0: skip)")
+    ap.add_argument("--cube-n", type=int, default=65536,
+                    help="points of the recompressed-cube product leg (0: skip)")
     ap.add_argument("--no-legs", action="store_true",
                     help="only the headline products (no fixed-basis, recompression, sphere, "
                          "serving, inverse or CPU legs): the command the kernel traces profile")
@@ -491,7 +533,7 @@ def main():
         op = "fp64" if args.precision == "fp32_bulk" else "fp32_bulk"
         other = run_precision(h2, ctx, dA, A.n, op, args.steps, args.warmup, args.eps)
     if args.no_legs:
-        args.sphere_n = args.serve_requests = args.inverse_n = 0
+        args.sphere_n = args.serve_requests = args.inverse_n = args.cube_n = 0
         args.no_cpu_baseline = True
     fixed = None if args.no_legs else fixed_basis_leg(h2, ctx, dA, A.n, args.eps)
     recomp = None if args.no_legs else recompress_leg(h2, ctx, dA, A.n, args.eps)
@@ -543,6 +585,8 @@ def main():
         out["matvec_graph"] = mvg
     if args.sphere_n > 0:
         out["sphere_complex"] = sphere_leg(args.sphere_n, args.steps)
+    if args.cube_n > 0:
+        out["cube_recompressed"] = cube_recompressed_leg(args.cube_n)
     if args.serve_requests > 0:
         precs = ("fp32_bulk", "fp64") if args.serve_nmax <= 32768 else ("fp32_bulk",)
         out["serving"] = {p: serve_stream(args.serve_requests, p, slots=args.serve_slots,
