@@ -77,9 +77,11 @@ struct Mfma<float> {
 // each wave holds (TM/32) x (TN/32) 16x16 MFMA accumulators.  The segment's
 // (task, k-chunk) steps are software-pipelined: the global loads of step s+1
 // are issued into registers before the MFMAs of step s run from one LDS
-// buffer, then stored into the other buffer (one barrier per step).  Plain
-// and transposed operands both load coalesced.
-template <typename T, int TM, int TN, typename TA, typename TB>
+// buffer, then stored into the other buffer (one barrier per step).  PF2
+// (the Gram sums and the block products, measured faster there): two
+// register sets, the loads of step s+2 issued before the MFMAs of step s and
+// stored one step later.  Plain and transposed operands both load coalesced.
+template <typename T, int TM, int TN, typename TA, typename TB, bool PF2>
 __device__ __forceinline__ void bgemm_body(const BgemmArgs<T>& p) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KC = 16;
@@ -138,9 +140,9 @@ __device__ __forceinline__ void bgemm_body(const BgemmArgs<T>& p) {
   // prefetch registers hold the operands in their storage types TA/TB; the
   // conversion to T happens at the LDS store, after the step's MFMAs, so the
   // loads stay in flight across them
-  TA ra[LA];
-  TB rb[LB];
-  auto load_step = [&](int st) {
+  TA ra[LA], ra2[LA];
+  TB rb[LB], rb2[LB];
+  auto load_into = [&](int st, TA (&xa)[LA], TB (&xb)[LB]) {
     const int t = s0 + st / nk;
     const int kk = (st % nk) * KC;
     int sa, sb;
@@ -151,33 +153,25 @@ __device__ __forceinline__ void bgemm_body(const BgemmArgs<T>& p) {
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
       const int gi = row0 + ai[r];
-      ra[r] = gi < p.m ? (p.transA ? Ab[(kk + aq[r]) + (long long)gi * lda]
+      xa[r] = gi < p.m ? (p.transA ? Ab[(kk + aq[r]) + (long long)gi * lda]
                                    : Ab[gi + (long long)(kk + aq[r]) * lda])
                        : (TA)0;
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
       const int gj = col0 + bj[r];
-      rb[r] = gj < p.n ? (p.transB ? Bb[gj + (long long)(kk + bq[r]) * ldb]
+      xb[r] = gj < p.n ? (p.transB ? Bb[gj + (long long)(kk + bq[r]) * ldb]
                                    : Bb[(kk + bq[r]) + (long long)gj * ldb])
                        : (TB)0;
     }
   };
-  auto store_step = [&](int buf) {
+  auto store_from = [&](int buf, const TA (&xa)[LA], const TB (&xb)[LB]) {
 #pragma unroll
-    for (int r = 0; r < LA; ++r) As[buf][aq[r]][ai[r]] = (T)ra[r];
+    for (int r = 0; r < LA; ++r) As[buf][aq[r]][ai[r]] = (T)xa[r];
 #pragma unroll
-    for (int r = 0; r < LB; ++r) Bs[buf][bq[r]][bj[r]] = (T)rb[r];
+    for (int r = 0; r < LB; ++r) Bs[buf][bq[r]][bj[r]] = (T)xb[r];
   };
-  if (nsteps > 0) {
-    load_step(0);
-    store_step(0);
-    __syncthreads();
-  }
-  for (int st = 0; st < nsteps; ++st) {
-    const int buf = st & 1;
-    const bool more = st + 1 < nsteps;
-    if (more) load_step(st + 1);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int q4 = 0; q4 < KC / 4; ++q4) {
       T av[SM], bv[SN];
@@ -190,8 +184,41 @@ __device__ __forceinline__ void bgemm_body(const BgemmArgs<T>& p) {
 #pragma unroll
         for (int b = 0; b < SN; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
     }
-    if (more) store_step(buf ^ 1);
-    __syncthreads();
+  };
+  if constexpr (PF2) {
+    // two steps in flight: the loads of step s + 2 are issued before the
+    // MFMAs of step s and stored to LDS one step later
+    if (nsteps > 0) {
+      load_into(0, ra, rb);
+      store_from(0, ra, rb);
+      if (nsteps > 1) load_into(1, ra2, rb2);
+      __syncthreads();
+    }
+    for (int st = 0; st < nsteps; st += 2) {
+      if (st + 2 < nsteps) load_into(st + 2, ra, rb);
+      compute(0);
+      if (st + 1 < nsteps) store_from(1, ra2, rb2);
+      __syncthreads();
+      if (st + 1 >= nsteps) break;
+      if (st + 3 < nsteps) load_into(st + 3, ra2, rb2);
+      compute(1);
+      if (st + 2 < nsteps) store_from(0, ra, rb);
+      __syncthreads();
+    }
+  } else {
+    if (nsteps > 0) {
+      load_into(0, ra, rb);
+      store_from(0, ra, rb);
+      __syncthreads();
+    }
+    for (int st = 0; st < nsteps; ++st) {
+      const int buf = st & 1;
+      const bool more = st + 1 < nsteps;
+      if (more) load_into(st + 1, ra, rb);
+      compute(buf);
+      if (more) store_from(buf ^ 1, ra, rb);
+      __syncthreads();
+    }
   }
   const int ov = p.out_idx[o];
   const long long coff = (long long)(ov >> 3) * p.cstride + ((ov & 1) ? p.csub_r : 0LL) +
@@ -280,22 +307,22 @@ __device__ __forceinline__ void bgemm_body(const BgemmArgs<T>& p) {
 // (projections, collects, splits, basis products).
 template <typename T, int TM, int TN, typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_bgemm(BgemmArgs<T> p) {
-  bgemm_body<T, TM, TN, TA, TB>(p);
+  bgemm_body<T, TM, TN, TA, TB, false>(p);
 }
 
 template <typename T, int TM, int TN, typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_bgemm_triple(BgemmArgs<T> p) {
-  bgemm_body<T, TM, TN, TA, TB>(p);
+  bgemm_body<T, TM, TN, TA, TB, true>(p);
 }
 
 template <typename T, int TM, int TN, typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_bgemm_target(BgemmArgs<T> p) {
-  bgemm_body<T, TM, TN, TA, TB>(p);
+  bgemm_body<T, TM, TN, TA, TB, false>(p);
 }
 
 template <typename T, int TM, int TN, typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_bgemm_gram(BgemmArgs<T> p) {
-  bgemm_body<T, TM, TN, TA, TB>(p);
+  bgemm_body<T, TM, TN, TA, TB, true>(p);
 }
 
 template <typename T>
