@@ -183,3 +183,44 @@ def test_product_of_recompressed_matches_checker(ctx, name):
             want.extend(r if lev >= info["lmin"] else [0] * len(r))
     want = np.asarray(want)
     assert float(np.mean(got == want)) >= 0.99 and np.abs(got - want).max() <= 2
+
+
+def test_recompress_degenerate_inputs(ctx):
+    """A single leaf (no admissible block: the dense block is copied) and a
+    partition with every leaf block dense: the recompressed matrix is the
+    input exactly."""
+    from h2inputs import points
+    from h2inputs.build import LaplaceKernel, chebyshev_h2
+    from h2inputs.structure import BlockTree, ClusterTree
+    for n, leaf, eta in ((1, 8, 1.0), (5, 8, 1.0), (31, 32, 1.0), (600, 16, 1e-6)):
+        print(f"case recompress degenerate n={n} leaf={leaf} eta={eta}", flush=True)
+        pts = points.plates_random(n, 0.1, 1e-3, 4) if n > 100 else points.cube(n, 3)
+        t = ClusterTree(pts, leaf)
+        A = chebyshev_h2(t, BlockTree(t, eta), LaplaceKernel(1.0), 2)
+        R = h2.recompress(ctx, h2.load(ctx, A.to_flat()), 1e-3)
+        assert np.array_equal(h2.to_dense(ctx, R, n), h2ops.to_dense(A))
+
+
+def test_recompress_a_product(ctx):
+    """A product C = A A (levels above l_min without a basis) recompressed on
+    the device against the checker's recompression of the exported C."""
+    from oracle import mmp as omp
+    print("case recompress product plates2048", flush=True)
+    M = SMALL["plates2048"]
+    dM = h2.load(ctx, M.to_flat())
+    C = h2.mmp(ctx, dM, dM, 1e-6)
+    Ch = H2Matrix.from_flat(h2.export(C), tree=M.tree)
+    eps = 1e-4
+    ref, _ = rc.recompress(Ch, eps)
+    R = h2.recompress(ctx, C, eps)
+    rg, rr = _ranks(h2.export(R)), _ranks(ref.to_flat())
+    same = float(np.mean(rg == rr))
+    assert same >= 0.99 and np.abs(rg - rr).max() <= 2
+    Dc = h2ops.to_dense(Ch)
+    nD = np.linalg.norm(Dc)
+    Dg = h2.to_dense(ctx, R, M.n)
+    assert np.linalg.norm(Dg - Dc) <= eps * nD
+    assert np.linalg.norm(Dg - h2ops.to_dense(ref)) <= (eps / 100 if same == 1.0 else eps) * nD
+    # ranks never above the product's own
+    rc_ = _ranks(h2.export(C))
+    assert np.all(rg <= np.maximum(rc_, 1))
