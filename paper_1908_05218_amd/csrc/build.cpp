@@ -370,5 +370,13 @@ h2_status build_impl(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* 
 
 extern "C" h2_status h2_build(h2_ctx ctx, const double* xyz, int64_t n, const h2_kernel* kernel,
                               const h2_build_opts* opts, h2_mat share_tree_with, h2_mat* out) {
-  return h2::build_impl(ctx, xyz, n, kernel, opts, share_tree_with, out);
+  if (!ctx) return h2::set_error(H2_ERR_ARG, "null argument");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  const size_t start = ctx->live_bytes;
+  ctx->mark();
+  const h2_status r = h2::build_impl(ctx, xyz, n, kernel, opts, share_tree_with, out);
+  // the pool keeps at most twice the call's peak temporaries (the
+  // recompression's are large)
+  ctx->end_call(start);
+  return r;
 }

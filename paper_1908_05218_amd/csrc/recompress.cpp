@@ -448,18 +448,22 @@ h2_status h2_recompress(h2_ctx ctx, h2_mat M, double eps, h2_mat* out) {
   ctx = home_of(ctx, M);
   if (!ctx) return set_error(H2_ERR_ARG, "M belongs to another context");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  const size_t start = ctx->live_bytes;
+  ctx->mark();
+  h2_status r = H2_OK;
   try {
     hipSetDevice(ctx->device);
     M->finish();
-    ctx->mark();
     *out = recompress_impl(ctx, M, eps);
-    return H2_OK;
   } catch (const Error& e) {
     (void)hipGetLastError();
-    return set_error(e.code, e.msg);
+    r = set_error(e.code, e.msg);
   } catch (const std::exception& e) {
-    return set_error(H2_ERR_INTERNAL, e.what());
+    r = set_error(H2_ERR_INTERNAL, e.what());
   }
+  // keep in the pool at most twice the call's peak temporaries
+  ctx->end_call(start);
+  return r;
 }
 
 }  // extern "C"
