@@ -506,29 +506,80 @@ void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64
     H2_HIP(h2k::launch_fill(yh[l], 0.0, (long long)(1 << l) * M->rr[l] * R * nc, st));
   }
   const long long ldx = nt;
-  size_t li = 0;
-  // forward
+  // independent branches on the helper streams (when the context has them):
+  // the near field y_t = F x_t right after the gather, and each level's
+  // couplings as soon as the forward sweep has produced that level; the
+  // caller's stream joins them before the backward sweep and the leaf
+  // expansion.  Events order the branches, so the call stays one stream
+  // program (a graph with parallel branches when captured); the temporaries
+  // return to the pool after the join, in the caller's stream order.
+  const bool fork = ctx->aux[0] != nullptr;
+  std::vector<int> used(h2_ctx_s::kAux, 0);
+  // a call that fails between a fork and its join waits for the branches
+  // before its temporaries go back to the pool
+  struct Joined {
+    h2_ctx c;
+    const std::vector<int>& used;
+    bool done = false;
+    ~Joined() {
+      if (done) return;
+      for (int i = 0; i < h2_ctx_s::kAux; ++i)
+        if (used[i]) (void)hipStreamSynchronize(c->aux[i]);
+    }
+  } joined{ctx, used};
+  auto branch = [&](int i) -> hipStream_t {
+    if (!fork) return st;
+    H2_HIP(hipEventRecord(ctx->fork_ev, st));
+    H2_HIP(hipStreamWaitEvent(ctx->aux[i], ctx->fork_ev, 0));
+    used[i] = 1;
+    return ctx->aux[i];
+  };
+  // task lists of the plan: forward (L - lo + 1), couplings (L - lo + 1),
+  // backward (L - lo), leaves (1), near field (1)
+  const size_t li_fwd = 0, li_cpl = li_fwd + (size_t)(L - lo + 1);
+  const size_t li_bwd = li_cpl + (size_t)(L - lo + 1), li_leaf = li_bwd + (size_t)(L - lo);
+  const size_t li_near = li_leaf + 1;
+  {
+    // the near field into y_t (zeroed by a fill kernel: a captured call
+    // records no memset)
+    const hipStream_t sd = branch(0);
+    H2_HIP(h2k::launch_fill(yt, 0.0, nt * R * nc, sd));
+    Op A{M->F.d(), nullptr, (long long)np * np, 0, np, 0, 0};
+    Op B{xt, nullptr, np, 0, (int)ldx, 0, 0};
+    gemm(sd, nullptr, 0, ml[li_near], np, R, np, A, false, B, false, yt, np, (int)ldx, 0, 0, 1.0,
+         1.0);
+  }
+  auto couplings = [&](int l) {
+    const DevList& d = ml[li_cpl + (size_t)(l - lo)];
+    if (d.nout == 0) return;
+    const hipStream_t sc = branch(1 + (l % (h2_ctx_s::kAux - 1)));
+    Op A{M->S[l].d(), nullptr, (long long)M->rr[l] * M->rc[l], 0, M->rr[l], 0, 0};
+    Op B{xh[l], nullptr, (long long)M->rc[l] * R, 0, M->rc[l], 0, 0};
+    gemm(sc, nullptr, 0, d, M->rr[l], R, M->rc[l], A, false, B, false, yh[l],
+         (long long)M->rr[l] * R, M->rr[l], 0, 0, 1.0, 1.0);
+  };
+  // forward, each level's couplings forked once its coefficients exist
   {
     Op A{M->W.d(), nullptr, M->W_stride, 0, np, 0, 0};
     Op B{xt, nullptr, np, 0, (int)ldx, 0, 0};
-    gemm(st, nullptr, 0, ml[li++], M->rc[L], R, np, A, true, B, false, xh[L],
+    gemm(st, nullptr, 0, ml[li_fwd], M->rc[L], R, np, A, true, B, false, xh[L],
          (long long)M->rc[L] * R, M->rc[L], 0, 0, 1.0, 0.0);
+    couplings(L);
   }
   for (int l = L - 1; l >= lo; --l) {
     Op A{M->Tc[l].d(), nullptr, M->Tc_stride[l], 0, 2 * M->rc[l + 1], M->rc[l + 1], 0};
     Op B{xh[l + 1], nullptr, (long long)M->rc[l + 1] * R, 0, M->rc[l + 1], 0, 0};
-    gemm(st, nullptr, 0, ml[li++], M->rc[l], R, M->rc[l + 1], A, true, B, false, xh[l],
-         (long long)M->rc[l] * R, M->rc[l], 0, 0, 1.0, 0.0);
+    gemm(st, nullptr, 0, ml[li_fwd + (size_t)(L - l)], M->rc[l], R, M->rc[l + 1], A, true, B,
+         false, xh[l], (long long)M->rc[l] * R, M->rc[l], 0, 0, 1.0, 0.0);
+    couplings(l);
   }
-  // couplings
-  for (int l = lo; l <= L; ++l) {
-    const DevList& d = ml[li++];
-    if (d.nout == 0) continue;
-    Op A{M->S[l].d(), nullptr, (long long)M->rr[l] * M->rc[l], 0, M->rr[l], 0, 0};
-    Op B{xh[l], nullptr, (long long)M->rc[l] * R, 0, M->rc[l], 0, 0};
-    gemm(st, nullptr, 0, d, M->rr[l], R, M->rc[l], A, false, B, false, yh[l],
-         (long long)M->rr[l] * R, M->rr[l], 0, 0, 1.0, 1.0);
-  }
+  size_t li = li_bwd;
+  // join the couplings before the backward sweep
+  for (int i = 1; i < h2_ctx_s::kAux; ++i)
+    if (used[i]) {
+      H2_HIP(hipEventRecord(ctx->join_ev[i], ctx->aux[i]));
+      H2_HIP(hipStreamWaitEvent(st, ctx->join_ev[i], 0));
+    }
   // backward
   for (int l = lo; l < L; ++l) {
     Op A{M->Tr[l].d(), nullptr, M->Tr_stride[l], 0, 2 * M->rr[l + 1], M->rr[l + 1], 0};
@@ -536,17 +587,17 @@ void matvec_impl(h2_ctx ctx, h2_mat M, const double* x_dev, double* y_dev, int64
     gemm(st, nullptr, 0, ml[li++], M->rr[l + 1], R, M->rr[l], A, false, B, false, yh[l + 1],
          (long long)M->rr[l + 1] * R, M->rr[l + 1], 0, 0, 1.0, 1.0);
   }
+  // the near field must be complete before the leaf expansion adds to y_t
+  if (used[0]) {
+    H2_HIP(hipEventRecord(ctx->join_ev[0], ctx->aux[0]));
+    H2_HIP(hipStreamWaitEvent(st, ctx->join_ev[0], 0));
+  }
+  joined.done = true;
   {
     Op A{M->V.d(), nullptr, M->V_stride, 0, np, 0, 0};
     Op B{yh[L], nullptr, (long long)M->rr[L] * R, 0, M->rr[L], 0, 0};
     gemm(st, nullptr, 0, ml[li++], np, R, M->rr[L], A, false, B, false, yt, np, (int)ldx, 0, 0,
-         1.0, 0.0);
-  }
-  {
-    Op A{M->F.d(), nullptr, (long long)np * np, 0, np, 0, 0};
-    Op B{xt, nullptr, np, 0, (int)ldx, 0, 0};
-    gemm(st, nullptr, 0, ml[li++], np, R, np, A, false, B, false, yt, np, (int)ldx, 0, 0, 1.0,
-         1.0);
+         1.0, 1.0);
   }
   H2_HIP(h2k::launch_scatter_rows(yt, y_dev, sh.d_perm.as<long long>(),
                                   sh.d_leaf_off.as<long long>(), nleaf, np, s.n, R * nc, st));
@@ -673,6 +724,14 @@ h2_ctx_s::~h2_ctx_s() {
     else
       hipFree(kv.first);
   }
+  for (int i = 0; i < kAux; ++i) {
+    if (aux[i]) {
+      hipStreamSynchronize(aux[i]);
+      hipStreamDestroy(aux[i]);
+    }
+    if (join_ev[i]) hipEventDestroy(join_ev[i]);
+  }
+  if (fork_ev) hipEventDestroy(fork_ev);
   if (stream) hipStreamDestroy(stream);
 }
 
@@ -721,6 +780,15 @@ h2_status h2_ctx_create(int device, size_t hbm_budget, const h2_allocator* alloc
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return h2::set_error(H2_ERR_DEVICE, "hipStreamCreate failed");
+  }
+  // the mat-vec's helper streams (default priority) and events
+  bool aux_ok = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < h2_ctx_s::kAux && aux_ok; ++i)
+    aux_ok = hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!aux_ok) {
+    delete c;
+    return h2::set_error(H2_ERR_DEVICE, "creating the mat-vec's helper streams failed");
   }
   // the allocation-free mat-vec's scratch array of this device
   if (h2::noalloc_setup(device) != H2_OK) {

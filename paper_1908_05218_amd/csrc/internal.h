@@ -73,6 +73,14 @@ struct h2_ctx_s {
   // results are used through the parent)
   h2_ctx_s* parent = nullptr;
   hipStream_t stream = nullptr;
+  // helper streams and events of the mat-vec's independent branches (the
+  // near field and the couplings of each level), forked from and joined
+  // back into the caller's stream; created with the context (none: the
+  // branches run in order on the caller's stream)
+  static constexpr int kAux = 3;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kAux] = {};
   bool profiling = false;
   // external supplier of device memory (h2_ctx_create); without one the
   // context calls hipMalloc and pools freed blocks
