@@ -325,6 +325,131 @@ __global__ __launch_bounds__(256) void k_bgemm_gram(BgemmArgs<T> p) {
   bgemm_body<T, TM, TN, TA, TB, true>(p);
 }
 
+// Wave-split 32 x 32 FP64 tile for segments of many tasks (the Gram sums):
+// each wave takes every fourth task of the output's segment for the whole
+// tile (four independent 16 x 16 accumulators), stages its operands in a
+// wave-private LDS region (no workgroup barrier in the main loop, the next
+// step's loads in flight during the MFMAs), and the four partial tiles are
+// summed in wave order at the end (deterministic).
+template <typename TA, typename TB, bool TRA, bool TRB>
+__global__ __launch_bounds__(256) void k_bgemm_gram_ws(BgemmArgs<double> p) {
+  typedef Mfma<double>::v4 v4;
+  constexpr int TM = 32, KC = 16, LD = TM + 1;
+  constexpr int LA = TM * KC / 64;  // elements per lane and step, A and B alike
+  constexpr int WREG = 2 * KC * LD;  // a wave's staging region (A then B)
+  __shared__ double sm[4 * WREG];    // also the reduction buffer (4 x 32 x 32)
+  static_assert(4 * WREG >= 4 * TM * TM, "reduction buffer");
+  const bool low = p.lower && p.tiles_m == p.tiles_n;
+  const int ntile = low ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+  const int o = blockIdx.x / ntile;
+  const int tt = blockIdx.x - o * ntile;
+  int tm, tn;
+  if (low) {
+    int r = (int)((sqrtf(8.0f * (float)tt + 1.0f) - 1.0f) * 0.5f);
+    while (r * (r + 1) / 2 > tt) --r;
+    while ((r + 1) * (r + 2) / 2 <= tt) ++r;
+    tm = r;
+    tn = tt - r * (r + 1) / 2;
+  } else {
+    tm = tt % p.tiles_m;
+    tn = tt / p.tiles_m;
+  }
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int row0 = tm * TM, col0 = tn * TM;
+  const int lda = p.A.ld, ldb = p.B.ld;
+  const int s0 = p.seg[o], ntask = p.seg[o + 1] - s0;
+  const int nk = p.k / KC;
+  const int mine = ntask > wave ? (ntask - wave + 3) / 4 : 0;
+  const int nsteps = mine * nk;
+  // element r of a lane's share of a step (e = lane + 64 r): plain
+  // operands take row e % 32 of column e / 32, transposed ones column e % 16
+  // of row e / 16, so the coordinates are affine in r
+  const int l32 = lane & 31, h32 = lane >> 5, l16 = lane & 15, h16 = lane >> 4;
+  constexpr bool ta = TRA, tb = TRB;
+  auto ai = [&](int r) { return ta ? h16 + 4 * r : l32; };
+  auto aq = [&](int r) { return ta ? l16 : h32 + 2 * r; };
+  auto bj = [&](int r) { return tb ? l32 : h16 + 4 * r; };
+  auto bq = [&](int r) { return tb ? h32 + 2 * r : l16; };
+  TA ra[LA];
+  TB rb[LA];
+  auto load_step = [&](int st) {
+    const int t = __builtin_amdgcn_readfirstlane(s0 + wave + 4 * (st / nk));
+    const int kk = (st % nk) * KC;
+    int sa, sb;
+    const long long oa = opnd_off(p.A, p.a_idx[t], sa);
+    const long long ob = opnd_off(p.B, p.b_idx[t], sb);
+    const TA* Ab = (const TA*)p.A.base[sa] + oa;
+    const TB* Bb = (const TB*)p.B.base[sb] + ob;
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int gi = row0 + ai(r), ka = kk + aq(r);
+      ra[r] = gi < p.m ? Ab[ta ? ka + gi * lda : gi + ka * lda] : (TA)0;
+      const int gj = col0 + bj(r), kb = kk + bq(r);
+      rb[r] = gj < p.n ? Bb[tb ? gj + kb * ldb : kb + gj * ldb] : (TB)0;
+    }
+  };
+  double* Aw = sm + wave * WREG;
+  double* Bw = Aw + KC * LD;
+  v4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+  if (nsteps > 0) load_step(0);
+  for (int st = 0; st < nsteps; ++st) {
+    // the region is the wave's own: its LDS operations run in program order,
+    // so the compiler barrier alone orders this step's stores after the
+    // previous step's reads
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      Aw[aq(r) * LD + ai(r)] = (double)ra[r];
+      Bw[bq(r) * LD + bj(r)] = (double)rb[r];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (st + 1 < nsteps) load_step(st + 1);
+#pragma unroll
+    for (int q4 = 0; q4 < KC / 4; ++q4) {
+      const int kq = (q4 * 4 + (lane >> 4)) * LD + (lane & 15);
+      const double a0 = Aw[kq], a1 = Aw[kq + 16], b0 = Bw[kq], b1 = Bw[kq + 16];
+      acc[0][0] = Mfma<double>::op(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<double>::op(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<double>::op(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<double>::op(a1, b1, acc[1][1]);
+    }
+  }
+  __syncthreads();
+  // partial tiles, column-major 32 x 32 per wave
+  double* red = sm;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = a * 16 + Mfma<double>::row(lane, v), c = b * 16 + (lane & 15);
+        red[wave * TM * TM + r + c * TM] = acc[a][b][v];
+      }
+  __syncthreads();
+  const int ov = p.out_idx[o];
+  const long long coff = (long long)(ov >> 3) * p.cstride + ((ov & 1) ? p.csub_r : 0LL) +
+                         ((ov & 2) ? p.csub_c : 0LL);
+  double* Cb = (double*)p.C + coff;
+#pragma unroll
+  for (int i = 0; i < TM * TM / 256; ++i) {
+    const int e = tid + 256 * i, r = e & (TM - 1), c = e / TM;
+    const int gi = row0 + r, gj = col0 + c;
+    if (gi < p.m && gj < p.n) {
+      const double sum = ((red[e] + red[TM * TM + e]) + red[2 * TM * TM + e]) + red[3 * TM * TM + e];
+      double* cp = Cb + gi + (long long)gj * p.ldc;
+      double val = p.alpha * sum;
+      if (p.beta != 0.0) val += p.beta * (*cp);
+      *cp = val;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_segsum(SegsumArgs<T> p) {
   const int per = (p.m * p.n + 255) / 256;
@@ -514,6 +639,36 @@ static hipError_t launch_tile(BgemmArgs<T> a, hipStream_t s) {
   return hipGetLastError();
 }
 
+static hipError_t launch_gram_ws(BgemmArgs<double> a, hipStream_t s) {
+  a.tiles_m = cdiv(a.m, 32);
+  a.tiles_n = cdiv(a.n, 32);
+  const bool low = a.lower && a.tiles_m == a.tiles_n;
+  const long long per = low ? (long long)a.tiles_m * (a.tiles_m + 1) / 2
+                            : (long long)a.tiles_m * a.tiles_n;
+  const dim3 g((unsigned)((long long)a.nout * per)), b(256);
+#define H2K_WS(TRA, TRB)                                                                \
+  do {                                                                                  \
+    if (a.A.f32 && a.B.f32)                                                             \
+      hipLaunchKernelGGL((k_bgemm_gram_ws<float, float, TRA, TRB>), g, b, 0, s, a);     \
+    else if (a.A.f32)                                                                   \
+      hipLaunchKernelGGL((k_bgemm_gram_ws<float, double, TRA, TRB>), g, b, 0, s, a);    \
+    else if (a.B.f32)                                                                   \
+      hipLaunchKernelGGL((k_bgemm_gram_ws<double, float, TRA, TRB>), g, b, 0, s, a);    \
+    else                                                                                \
+      hipLaunchKernelGGL((k_bgemm_gram_ws<double, double, TRA, TRB>), g, b, 0, s, a);   \
+  } while (0)
+  if (a.transA && a.transB)
+    H2K_WS(true, true);
+  else if (a.transA)
+    H2K_WS(true, false);
+  else if (a.transB)
+    H2K_WS(false, true);
+  else
+    H2K_WS(false, false);
+#undef H2K_WS
+  return hipGetLastError();
+}
+
 // Workgroup tile: the whole output when it fits 96 x 96 (96 x 32, 32 x 96 and
 // 96 x 96 shapes), otherwise 32 or 64 per side.
 template <typename T>
@@ -522,6 +677,11 @@ hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s) {
   if (a.c_f32 != (sizeof(T) == sizeof(float))) return hipErrorInvalidValue;  // C has type T
   switch (a.tile) {  // a measured choice (every tile masks partial edges)
     case kTile32x32: return launch_tile<T, 32, 32>(a, s);
+    case kTile32x32ws:
+      if constexpr (std::is_same<T, double>::value) {
+        if (a.symbol == 3) return launch_gram_ws(a, s);
+      }
+      return launch_tile<T, 32, 32>(a, s);
     case kTile96x32: return launch_tile<T, 96, 32>(a, s);
     case kTile32x96: return launch_tile<T, 32, 96>(a, s);
     case kTile96x96: return launch_tile<T, 96, 96>(a, s);
