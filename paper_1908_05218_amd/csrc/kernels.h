@@ -44,8 +44,8 @@ struct BgemmArgs {
 };
 
 // Workgroup tiles of the batched GEMM (rows x columns of C per workgroup)
-// (kTile32x32ws: the Gram sums' wave-split 32 x 32 tile, each wave a quarter
-// of the segment's tasks; other batches take the plain 32 x 32 tile)
+// (kTile32x32ws: the wave-split 32 x 32 tile, each wave a quarter of the
+// segment's tasks)
 enum {
   kTile32x32 = 0, kTile96x32 = 1, kTile32x96 = 2, kTile96x96 = 3,
   kTile32x64 = 4, kTile64x32 = 5, kTile64x64 = 6, kTile32x32ws = 7, kTileCount = 8

@@ -325,19 +325,19 @@ __global__ __launch_bounds__(256) void k_bgemm_gram(BgemmArgs<T> p) {
   bgemm_body<T, TM, TN, TA, TB, true>(p);
 }
 
-// Wave-split 32 x 32 FP64 tile for segments of many tasks (the Gram sums):
-// each wave takes every fourth task of the output's segment for the whole
-// tile (four independent 16 x 16 accumulators), stages its operands in a
-// wave-private LDS region (no workgroup barrier in the main loop, the next
-// step's loads in flight during the MFMAs), and the four partial tiles are
-// summed in wave order at the end (deterministic).
-template <typename TA, typename TB, bool TRA, bool TRB>
-__global__ __launch_bounds__(256) void k_bgemm_gram_ws(BgemmArgs<double> p) {
-  typedef Mfma<double>::v4 v4;
+// Wave-split 32 x 32 tile for segments of many tasks: each wave takes every
+// fourth task of the output's segment for the whole tile (four independent
+// 16 x 16 accumulators), stages its operands in a wave-private LDS region (no
+// workgroup barrier in the main loop, the next step's loads in flight during
+// the MFMAs), and the four partial tiles are summed in wave order at the end
+// (deterministic).
+template <typename T, typename TA, typename TB, bool TRA, bool TRB>
+__device__ __forceinline__ void bgemm_ws_body(const BgemmArgs<T>& p) {
+  typedef typename Mfma<T>::v4 v4;
   constexpr int TM = 32, KC = 16, LD = TM + 1;
   constexpr int LA = TM * KC / 64;  // elements per lane and step, A and B alike
   constexpr int WREG = 2 * KC * LD;  // a wave's staging region (A then B)
-  __shared__ double sm[4 * WREG];    // also the reduction buffer (4 x 32 x 32)
+  __shared__ T sm[4 * WREG];    // also the reduction buffer (4 x 32 x 32)
   static_assert(4 * WREG >= 4 * TM * TM, "reduction buffer");
   const bool low = p.lower && p.tiles_m == p.tiles_n;
   const int ntile = low ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
@@ -389,8 +389,8 @@ __global__ __launch_bounds__(256) void k_bgemm_gram_ws(BgemmArgs<double> p) {
       rb[r] = gj < p.n ? Bb[tb ? gj + kb * ldb : kb + gj * ldb] : (TB)0;
     }
   };
-  double* Aw = sm + wave * WREG;
-  double* Bw = Aw + KC * LD;
+  T* Aw = sm + wave * WREG;
+  T* Bw = Aw + KC * LD;
   v4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -404,50 +404,67 @@ __global__ __launch_bounds__(256) void k_bgemm_gram_ws(BgemmArgs<double> p) {
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
-      Aw[aq(r) * LD + ai(r)] = (double)ra[r];
-      Bw[bq(r) * LD + bj(r)] = (double)rb[r];
+      Aw[aq(r) * LD + ai(r)] = (T)ra[r];
+      Bw[bq(r) * LD + bj(r)] = (T)rb[r];
     }
     __builtin_amdgcn_wave_barrier();
     if (st + 1 < nsteps) load_step(st + 1);
 #pragma unroll
     for (int q4 = 0; q4 < KC / 4; ++q4) {
       const int kq = (q4 * 4 + (lane >> 4)) * LD + (lane & 15);
-      const double a0 = Aw[kq], a1 = Aw[kq + 16], b0 = Bw[kq], b1 = Bw[kq + 16];
-      acc[0][0] = Mfma<double>::op(a0, b0, acc[0][0]);
-      acc[0][1] = Mfma<double>::op(a0, b1, acc[0][1]);
-      acc[1][0] = Mfma<double>::op(a1, b0, acc[1][0]);
-      acc[1][1] = Mfma<double>::op(a1, b1, acc[1][1]);
+      const T a0 = Aw[kq], a1 = Aw[kq + 16], b0 = Bw[kq], b1 = Bw[kq + 16];
+      acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
     }
   }
   __syncthreads();
   // partial tiles, column-major 32 x 32 per wave
-  double* red = sm;
+  T* red = sm;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = a * 16 + Mfma<double>::row(lane, v), c = b * 16 + (lane & 15);
+        const int r = a * 16 + Mfma<T>::row(lane, v), c = b * 16 + (lane & 15);
         red[wave * TM * TM + r + c * TM] = acc[a][b][v];
       }
   __syncthreads();
   const int ov = p.out_idx[o];
   const long long coff = (long long)(ov >> 3) * p.cstride + ((ov & 1) ? p.csub_r : 0LL) +
                          ((ov & 2) ? p.csub_c : 0LL);
-  double* Cb = (double*)p.C + coff;
+  T* Cb = (T*)p.C + coff;
 #pragma unroll
   for (int i = 0; i < TM * TM / 256; ++i) {
     const int e = tid + 256 * i, r = e & (TM - 1), c = e / TM;
     const int gi = row0 + r, gj = col0 + c;
     if (gi < p.m && gj < p.n) {
-      const double sum = ((red[e] + red[TM * TM + e]) + red[2 * TM * TM + e]) + red[3 * TM * TM + e];
-      double* cp = Cb + gi + (long long)gj * p.ldc;
-      double val = p.alpha * sum;
-      if (p.beta != 0.0) val += p.beta * (*cp);
+      const T sum = ((red[e] + red[TM * TM + e]) + red[2 * TM * TM + e]) + red[3 * TM * TM + e];
+      T* cp = Cb + gi + (long long)gj * p.ldc;
+      T val = p.alpha * sum;
+      if (p.beta != (T)0) val += p.beta * (*cp);
       *cp = val;
     }
   }
+}
+
+template <typename T, typename TA, typename TB, bool TRA, bool TRB>
+__global__ __launch_bounds__(256) void k_bgemm_ws(BgemmArgs<T> p) {
+  bgemm_ws_body<T, TA, TB, TRA, TRB>(p);
+}
+template <typename T, typename TA, typename TB, bool TRA, bool TRB>
+__global__ __launch_bounds__(256) void k_bgemm_triple_ws(BgemmArgs<T> p) {
+  bgemm_ws_body<T, TA, TB, TRA, TRB>(p);
+}
+template <typename T, typename TA, typename TB, bool TRA, bool TRB>
+__global__ __launch_bounds__(256) void k_bgemm_target_ws(BgemmArgs<T> p) {
+  bgemm_ws_body<T, TA, TB, TRA, TRB>(p);
+}
+template <typename T, typename TA, typename TB, bool TRA, bool TRB>
+__global__ __launch_bounds__(256) void k_bgemm_gram_ws(BgemmArgs<T> p) {
+  bgemm_ws_body<T, TA, TB, TRA, TRB>(p);
 }
 
 template <typename T>
@@ -639,33 +656,49 @@ static hipError_t launch_tile(BgemmArgs<T> a, hipStream_t s) {
   return hipGetLastError();
 }
 
-static hipError_t launch_gram_ws(BgemmArgs<double> a, hipStream_t s) {
+template <typename T>
+static hipError_t launch_ws(BgemmArgs<T> a, hipStream_t s) {
   a.tiles_m = cdiv(a.m, 32);
   a.tiles_n = cdiv(a.n, 32);
   const bool low = a.lower && a.tiles_m == a.tiles_n;
   const long long per = low ? (long long)a.tiles_m * (a.tiles_m + 1) / 2
                             : (long long)a.tiles_m * a.tiles_n;
   const dim3 g((unsigned)((long long)a.nout * per)), b(256);
-#define H2K_WS(TRA, TRB)                                                                \
-  do {                                                                                  \
-    if (a.A.f32 && a.B.f32)                                                             \
-      hipLaunchKernelGGL((k_bgemm_gram_ws<float, float, TRA, TRB>), g, b, 0, s, a);     \
-    else if (a.A.f32)                                                                   \
-      hipLaunchKernelGGL((k_bgemm_gram_ws<float, double, TRA, TRB>), g, b, 0, s, a);    \
-    else if (a.B.f32)                                                                   \
-      hipLaunchKernelGGL((k_bgemm_gram_ws<double, float, TRA, TRB>), g, b, 0, s, a);    \
-    else                                                                                \
-      hipLaunchKernelGGL((k_bgemm_gram_ws<double, double, TRA, TRB>), g, b, 0, s, a);   \
+#define H2K_WS1(K, TRA, TRB)                                                           \
+  do {                                                                                 \
+    if (a.A.f32 && a.B.f32)                                                            \
+      hipLaunchKernelGGL((K<T, float, float, TRA, TRB>), g, b, 0, s, a);               \
+    else if (a.A.f32)                                                                  \
+      hipLaunchKernelGGL((K<T, float, double, TRA, TRB>), g, b, 0, s, a);              \
+    else if (a.B.f32)                                                                  \
+      hipLaunchKernelGGL((K<T, double, float, TRA, TRB>), g, b, 0, s, a);              \
+    else                                                                               \
+      hipLaunchKernelGGL((K<T, double, double, TRA, TRB>), g, b, 0, s, a);             \
   } while (0)
-  if (a.transA && a.transB)
-    H2K_WS(true, true);
-  else if (a.transA)
-    H2K_WS(true, false);
-  else if (a.transB)
-    H2K_WS(false, true);
-  else
-    H2K_WS(false, false);
+#define H2K_WS(K)                     \
+  do {                                \
+    if (a.transA && a.transB)         \
+      H2K_WS1(K, true, true);         \
+    else if (a.transA)                \
+      H2K_WS1(K, true, false);        \
+    else if (a.transB)                \
+      H2K_WS1(K, false, true);        \
+    else                              \
+      H2K_WS1(K, false, false);       \
+  } while (0)
+  if (a.symbol == 1)
+    H2K_WS(k_bgemm_triple_ws);
+  else if (a.symbol == 2)
+    H2K_WS(k_bgemm_target_ws);
+  else if constexpr (std::is_same<T, double>::value) {
+    if (a.symbol == 3)
+      H2K_WS(k_bgemm_gram_ws);
+    else
+      H2K_WS(k_bgemm_ws);
+  } else
+    H2K_WS(k_bgemm_ws);
 #undef H2K_WS
+#undef H2K_WS1
   return hipGetLastError();
 }
 
@@ -677,11 +710,7 @@ hipError_t launch_bgemm(const BgemmArgs<T>& a, hipStream_t s) {
   if (a.c_f32 != (sizeof(T) == sizeof(float))) return hipErrorInvalidValue;  // C has type T
   switch (a.tile) {  // a measured choice (every tile masks partial edges)
     case kTile32x32: return launch_tile<T, 32, 32>(a, s);
-    case kTile32x32ws:
-      if constexpr (std::is_same<T, double>::value) {
-        if (a.symbol == 3) return launch_gram_ws(a, s);
-      }
-      return launch_tile<T, 32, 32>(a, s);
+    case kTile32x32ws: return launch_ws<T>(a, s);
     case kTile96x32: return launch_tile<T, 96, 32>(a, s);
     case kTile32x96: return launch_tile<T, 32, 96>(a, s);
     case kTile96x96: return launch_tile<T, 96, 96>(a, s);

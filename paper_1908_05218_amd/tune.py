@@ -87,7 +87,7 @@ def main():
                 "# complex Helmholtz sphere of 32,768 points); key: element bytes, A float,\n"
                 "# B float, block-product symbol, transA, transB, m, n, k, log2 outputs,\n"
                 "# log2 tasks per output; value: tile id (0 32x32, 1 96x32, 2 32x96, 3 96x96,\n"
-                "# 4 32x64, 5 64x32, 6 64x64, 7 32x32 wave-split Gram)\n"
+                "# 4 32x64, 5 64x32, 6 64x64, 7 32x32 wave-split)\n"
                 f"# timed launches: {total:.2f} ms with the heuristic, {total - gain:.2f} ms with this table\n")
         for r in rows:
             f.write(r + "\n")
