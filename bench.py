@@ -24,7 +24,7 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 MFMA
 
 
-def cpu_baseline(patch=(64, 64)):
+def cpu_baseline(patch=(64, 128)):
     """The CPU oracle (plain FP64 NumPy, as it stands) timed on a bounded
     sample of the headline workload: a patch of nx x ny cells of the plates64k
     grid on each plate (same spacing, gap, jitter, self-term, leaf size,
