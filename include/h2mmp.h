@@ -46,7 +46,7 @@ typedef enum {
   H2_ERR_OOM = 3,         /* device allocation failed or over the context's budget */
   H2_ERR_STRUCTURE = 4,   /* A and B do not share tree and block partition */
   H2_ERR_NUMERIC = 5,     /* non-finite input or result */
-  H2_ERR_UNSUPPORTED = 6, /* a size or feature this build does not handle */
+  H2_ERR_UNSUPPORTED = 6, /* a size or feature the library does not handle */
   H2_ERR_INTERNAL = 7,
   H2_ERR_BUSY = 8         /* a served request is not finished yet */
 } h2_status;
