@@ -91,3 +91,26 @@ def test_async_products_on_two_streams(torch):
             assert np.array_equal(h2.to_dense(ctx, C, A.n), ref)
     finally:
         ctx.close()
+
+
+def test_torch_allocator_recompression_and_build(torch):
+    """h2_build with recompression and h2_recompress drawing their device
+    memory from torch's allocator give the same matrices, bit for bit, as a
+    context with its own pool."""
+    from h2inputs import configs
+    print("case torch allocator: build + recompress plates4096", flush=True)
+    w = configs.plates_n(4096)
+    ref_ctx = h2.Context(0)
+    ctx = h2.Context(0, allocator="torch")
+    try:
+        R1 = h2.build(ctx, w.pts, w.leaf_size, w.eta, w.order, w.kernel.self_value, recompress_eps=1e-5)
+        R2 = h2.build(ref_ctx, w.pts, w.leaf_size, w.eta, w.order, w.kernel.self_value,
+                      recompress_eps=1e-5)
+        e, r = h2.export(R1), h2.export(R2)
+        for k in ("krow", "kcol", "V", "W", "Er", "Ec", "S", "F"):
+            assert np.array_equal(np.asarray(e[k]), np.asarray(r[k])), k
+        R1.free()
+        R2.free()
+    finally:
+        ctx.close()
+        ref_ctx.close()
