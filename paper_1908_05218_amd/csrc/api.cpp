@@ -6,6 +6,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <exception>
+#include <memory>
+#include <thread>
 
 #include "internal.h"
 
@@ -819,6 +822,32 @@ namespace h2 {
 // Upload of a host matrix.  device_blocks: the couplings and dense blocks are
 // left zero on the device for the caller to fill (S, F and their offsets are
 // not read).
+// f(begin, end) over [0, n) split across host threads (one range when n is
+// small); the first exception of any range is rethrown
+template <typename F>
+static void parallel_ranges(long long n, F&& f) {
+  const unsigned hc = std::max(1u, std::thread::hardware_concurrency());
+  const long long nt = n < 256 ? 1 : std::min<long long>(std::min(16u, hc), n / 128);
+  if (nt <= 1) {
+    f(0LL, n);
+    return;
+  }
+  std::exception_ptr ep;
+  std::mutex emu;
+  std::vector<std::thread> th;
+  for (long long t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      try {
+        f(n * t / nt, n * (t + 1) / nt);
+      } catch (...) {
+        std::lock_guard<std::mutex> g(emu);
+        if (!ep) ep = std::current_exception();
+      }
+    });
+  for (auto& x : th) x.join();
+  if (ep) std::rethrow_exception(ep);
+}
+
 h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_mat* out) {
   if (!ctx || !m || !out) return set_error(H2_ERR_ARG, "null argument");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -842,12 +871,12 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
     // complex input: interleaved (real, imaginary) pairs; on the device two
     // planes [real | imaginary] per buffer
     const int nc = M->cplx ? 2 : 1;
-    auto upload = [&](const std::vector<double>& h) {
-      Buf b(ctx, h.size() * sizeof(double), false, M->cplx);
-      if (!h.empty())
-        H2_HIP(hipMemcpy(b.d(), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    auto upload_n = [&](const double* h, size_t count) {
+      Buf b(ctx, count * sizeof(double), false, M->cplx);
+      if (count) H2_HIP(hipMemcpy(b.d(), h, count * sizeof(double), hipMemcpyHostToDevice));
       return b;
     };
+    auto upload = [&](const std::vector<double>& h) { return upload_n(h.data(), h.size()); };
     M->krow.assign(m->krow, m->krow + ncl);
     M->kcol.assign(m->kcol, m->kcol + ncl);
     M->rr.assign(L + 1, 16);
@@ -927,24 +956,31 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
         zero(ctx->stream, M->S[l].p(), (long long)pl);
         continue;
       }
-      std::vector<double> h(pl * nc, 0.0);
-      for (int q = 0; q < ln.size(); ++q) {
-        const long long g = s.node_base[l] + q;
-        if (ln.type[q] != kR) {
-          need(m->S_off, g, 0, "S");
-          continue;
+      // each node's slot (zero padding included) is written by one thread
+      std::unique_ptr<double[]> h(new double[pl * nc]);
+      if (ln.size() == 0) std::fill(h.get(), h.get() + pl * nc, 0.0);
+      parallel_ranges(ln.size(), [&](long long q0, long long q1) {
+        for (long long q = q0; q < q1; ++q) {
+          for (int part = 0; part < nc; ++part)
+            std::fill(h.get() + part * pl + (size_t)q * bs, h.get() + part * pl + (size_t)(q + 1) * bs,
+                      0.0);
+          const long long g = s.node_base[l] + q;
+          if (ln.type[q] != kR) {
+            need(m->S_off, g, 0, "S");
+            continue;
+          }
+          const int kr = (int)M->krow[cidx(l, ln.row[q])], kc = (int)M->kcol[cidx(l, ln.col[q])];
+          need(m->S_off, g, (long long)kr * kc, "S");
+          for (int j = 0; j < kc; ++j)
+            for (int i = 0; i < kr; ++i)
+              for (int part = 0; part < nc; ++part) {
+                const double v = m->S[(m->S_off[g] + i + (size_t)j * kr) * nc + part];
+                if (!std::isfinite(v)) throw Error(H2_ERR_NUMERIC, "non-finite coupling entry");
+                h[part * pl + (size_t)q * bs + i + (size_t)j * M->rr[l]] = v;
+              }
         }
-        const int kr = (int)M->krow[cidx(l, ln.row[q])], kc = (int)M->kcol[cidx(l, ln.col[q])];
-        need(m->S_off, g, (long long)kr * kc, "S");
-        for (int j = 0; j < kc; ++j)
-          for (int i = 0; i < kr; ++i)
-            for (int part = 0; part < nc; ++part) {
-              const double v = m->S[(m->S_off[g] + i + (size_t)j * kr) * nc + part];
-              if (!std::isfinite(v)) throw Error(H2_ERR_NUMERIC, "non-finite coupling entry");
-              h[part * pl + (size_t)q * bs + i + (size_t)j * M->rr[l]] = v;
-            }
-      }
-      M->S[l] = upload(h);
+      });
+      M->S[l] = upload_n(h.get(), pl * nc);
     }
     if (device_blocks) {
       const long long nb = (long long)np * np * s.lev[L].size();
@@ -954,25 +990,30 @@ h2_status load_impl(h2_ctx ctx, const h2_host_matrix* m, bool device_blocks, h2_
       const LevelNodes& ln = s.lev[L];
       const long long bs = (long long)np * np;
       const size_t pl = (size_t)bs * ln.size();
-      std::vector<double> h(pl * nc, 0.0);
-      for (int q = 0; q < ln.size(); ++q) {
-        const long long g = s.node_base[L] + q;
-        if (ln.type[q] != kF) {
-          need(m->F_off, g, 0, "F");
-          continue;
+      std::unique_ptr<double[]> h(new double[pl * nc]);
+      parallel_ranges(ln.size(), [&](long long q0, long long q1) {
+        for (long long q = q0; q < q1; ++q) {
+          for (int part = 0; part < nc; ++part)
+            std::fill(h.get() + part * pl + (size_t)q * bs, h.get() + part * pl + (size_t)(q + 1) * bs,
+                      0.0);
+          const long long g = s.node_base[L] + q;
+          if (ln.type[q] != kF) {
+            need(m->F_off, g, 0, "F");
+            continue;
+          }
+          const int ni = s.leaf_size[ln.row[q]], nj = s.leaf_size[ln.col[q]];
+          need(m->F_off, g, (long long)ni * nj, "F");
+          if (!m->F) throw Error(H2_ERR_ARG, "null F");
+          for (int j = 0; j < nj; ++j)
+            for (int i = 0; i < ni; ++i)
+              for (int part = 0; part < nc; ++part) {
+                const double v = m->F[(m->F_off[g] + i + (size_t)j * ni) * nc + part];
+                if (!std::isfinite(v)) throw Error(H2_ERR_NUMERIC, "non-finite dense entry");
+                h[part * pl + (size_t)q * bs + i + (size_t)j * np] = v;
+              }
         }
-        const int ni = s.leaf_size[ln.row[q]], nj = s.leaf_size[ln.col[q]];
-        need(m->F_off, g, (long long)ni * nj, "F");
-        if (!m->F) throw Error(H2_ERR_ARG, "null F");
-        for (int j = 0; j < nj; ++j)
-          for (int i = 0; i < ni; ++i)
-            for (int part = 0; part < nc; ++part) {
-              const double v = m->F[(m->F_off[g] + i + (size_t)j * ni) * nc + part];
-              if (!std::isfinite(v)) throw Error(H2_ERR_NUMERIC, "non-finite dense entry");
-              h[part * pl + (size_t)q * bs + i + (size_t)j * np] = v;
-            }
-      }
-      M->F = upload(h);
+      });
+      M->F = upload_n(h.get(), pl * nc);
     }
     shape->d_perm = Buf(ctx, s.n * sizeof(long long));
     shape->d_leaf_off = Buf(ctx, (nleaf + 1) * sizeof(long long));
