@@ -735,7 +735,26 @@ h2_ctx_s::~h2_ctx_s() {
     if (join_ev[i]) hipEventDestroy(join_ev[i]);
   }
   if (fork_ev) hipEventDestroy(fork_ev);
+  if (rb_ev) hipEventDestroy(rb_ev);
+  if (rb_host) hipHostFree(rb_host);
   if (stream) hipStreamDestroy(stream);
+}
+
+int* h2_ctx_s::readback(size_t n) {
+  if (!rb_ev) H2_HIP(hipEventCreateWithFlags(&rb_ev, hipEventDisableTiming));
+  if (n > rb_n) {
+    if (rb_host) {
+      // a call that failed between posting and reading may leave copies in flight
+      H2_HIP(hipEventSynchronize(rb_ev));
+      H2_HIP(hipHostFree(rb_host));
+      rb_host = nullptr;
+      rb_n = 0;
+    }
+    const size_t cap = std::max<size_t>(n, 4096);
+    H2_HIP(hipHostMalloc((void**)&rb_host, cap * sizeof(int), hipHostMallocDefault));
+    rb_n = cap;
+  }
+  return rb_host;
 }
 
 void h2_mat_s::finish() {

@@ -81,6 +81,12 @@ struct h2_ctx_s {
   hipStream_t aux[kAux] = {};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kAux] = {};
+  // pinned host memory for the ranks and flags a product reads back per
+  // level, and the event that marks their arrival (created on first use)
+  int* rb_host = nullptr;
+  size_t rb_n = 0;
+  hipEvent_t rb_ev = nullptr;
+  int* readback(size_t n);  // at least n ints
   bool profiling = false;
   // external supplier of device memory (h2_ctx_create); without one the
   // context calls hipMalloc and pools freed blocks
@@ -349,11 +355,19 @@ struct EigLevel {
   bool cplx;
   double tau;   // relative eigenvalue threshold
   bool exact;   // keep every eigenvector
+  // pinned [rank_r (2^l) | rank_c (2^l) | status (4)] of the level, written
+  // as soon as the ranks are fixed (before the eigenvectors), and the event
+  // recorded after those copies
+  int* host;
+  hipEvent_t ready;
 };
 void eig_level(const EigLevel& e, int l, int D, const Buf* Gr, const Buf* Gc, Buf& Ur, Buf& Uc,
                Buf& rank_r, Buf& rank_c, const int* k1r, const int* k2r, const int* k1c,
                const int* k2c, int kstride, int half, const int* kmax_r = nullptr,
                const int* kmax_c = nullptr);
+// waits for the level's read-back of eig_level; raises the eigensolver's
+// flags; the pinned ranks: rows at [0, 2^l), columns at [2^l, 2^(l+1))
+const int* wait_ranks(const EigLevel& e, int l);
 // H^2 recompression of M at eps (new nested orthonormal bases, projected
 // couplings, M's dense blocks), a new matrix of ctx
 h2_mat recompress_impl(h2_ctx ctx, h2_mat M, double eps);

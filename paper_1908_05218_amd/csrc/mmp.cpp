@@ -154,11 +154,35 @@ FlopCounts flop_counts(const Structure& s, const FlopRanks& r) {
   return f;
 }
 
-// the three eigensolver phases, each timed as its own kernel class
-static void run_eig(const EigLevel& e, const h2k::EigArgs* ea, int ncl) {
+// the level's ranks and flags to pinned host memory, then the event
+static void post_ranks(const EigLevel& e, int ncl, const int* rr, const int* rc) {
+  H2_HIP(hipMemcpyAsync(e.host, rr, ncl * sizeof(int), hipMemcpyDeviceToHost, e.st));
+  H2_HIP(hipMemcpyAsync(e.host + ncl, rc, ncl * sizeof(int), hipMemcpyDeviceToHost, e.st));
+  H2_HIP(hipMemcpyAsync(e.host + 2 * ncl, e.status, 4 * sizeof(int), hipMemcpyDeviceToHost, e.st));
+  H2_HIP(hipEventRecord(e.ready, e.st));
+}
+
+const int* wait_ranks(const EigLevel& e, int l) {
+  H2_HIP(hipEventSynchronize(e.ready));
+  const int* stv = e.host + 2 * (1 << l);
+  if (stv[0]) throw Error(H2_ERR_NUMERIC, "non-finite Gram matrix at level " + std::to_string(l));
+  if (stv[1])
+    throw Error(H2_ERR_UNSUPPORTED, "a Gram matrix at level " + std::to_string(l) +
+                                        " exceeds the eigensolver limit of " +
+                                        std::to_string(h2k::kEigNmax));
+  return e.host;
+}
+
+// the three eigensolver phases, each timed as its own kernel class; with
+// rank arrays given, their read-back is posted between the eigenvalue phase
+// (which fixes the ranks) and the eigenvector phase, so the host sizes and
+// enqueues the next launches while the eigenvectors are computed
+static void run_eig(const EigLevel& e, const h2k::EigArgs* ea, int ncl, const int* rr = nullptr,
+                    const int* rc = nullptr) {
   const int phase[3] = {h2k::kEigPhaseTri, h2k::kEigPhaseVal, h2k::kEigPhaseVec};
   const int kind[3] = {kKindEig, kKindEigVal, kKindEigVec};
   for (int ph = 0; ph < 3; ++ph) {
+    if (ph == 2 && rr) post_ranks(e, ncl, rr, rc);
     hipEvent_t ev = nullptr;
     e.prof->begin(kind[ph], 0, &ev);
     H2_HIP(h2k::launch_eig(ea[0], ea[1], ncl, e.st, phase[ph]));
@@ -241,6 +265,7 @@ void eig_level(const EigLevel& e, int l, int D, const Buf* Gr, const Buf* Gc, Bu
     e.prof->begin(kKindEigVec, 0, &ev);
     H2_HIP(h2k::launch_ceig_extract(ca[0], ca[1], ncl, st));
     e.prof->end(ev, kKindEigVec, 0);
+    post_ranks(e, ncl, rank_r_.as<int>(), rank_c_.as<int>());  // fixed by the extraction
     return;
   }
   Buf Gnr(ctx, (size_t)ncl * D * D * sizeof(double)), Gnc(ctx, (size_t)ncl * D * D * sizeof(double));
@@ -280,7 +305,7 @@ void eig_level(const EigLevel& e, int l, int D, const Buf* Gr, const Buf* Gc, Bu
     x.kmax = side ? kmax_c : kmax_r;
     x.status = e.status;
   }
-  run_eig(e, ea, ncl);
+  run_eig(e, ea, ncl, rank_r_.as<int>(), rank_c_.as<int>());
 }
 
 h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int prec, h2_mat* C_out) {
@@ -393,29 +418,21 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   }
 
   // the three eigensolver phases, each timed as its own kernel class
+  const EigLevel eg{ctx, st, &prof, status.as<int>(), cplx, tau, exact,
+                    ctx->readback(2 * (size_t)nleaf + 4), ctx->rb_ev};
   auto eig_level = [&](int l, int D, Buf Gr[3], Buf Gc[3], Buf& Ur_, Buf& Uc_, Buf& rank_r_,
                        Buf& rank_c_, const int* k1r, const int* k2r, const int* k1c,
                        const int* k2c, int kstride, int half) {
-    const EigLevel e{ctx, st, &prof, status.as<int>(), cplx, tau, exact};
-    h2::eig_level(e, l, D, Gr, Gc, Ur_, Uc_, rank_r_, rank_c_, k1r, k2r, k1c, k2c, kstride, half);
+    h2::eig_level(eg, l, D, Gr, Gc, Ur_, Uc_, rank_r_, rank_c_, k1r, k2r, k1c, k2c, kstride, half);
   };
-  auto read_ranks = [&](int l, Buf& rr_, Buf& rc_) {
+  auto read_ranks = [&](int l) {
     const int ncl = 1 << l;
-    std::vector<int> hr(ncl), hc(ncl), stv(4);
-    H2_HIP(hipMemcpyAsync(hr.data(), rr_.as<int>(), ncl * sizeof(int), hipMemcpyDeviceToHost, st));
-    H2_HIP(hipMemcpyAsync(hc.data(), rc_.as<int>(), ncl * sizeof(int), hipMemcpyDeviceToHost, st));
-    H2_HIP(hipMemcpyAsync(stv.data(), status.as<int>(), 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-    H2_HIP(hipStreamSynchronize(st));
-    if (stv[0]) throw Error(H2_ERR_NUMERIC, "non-finite Gram matrix at level " + std::to_string(l));
-    if (stv[1])
-      throw Error(H2_ERR_UNSUPPORTED, "a Gram matrix at level " + std::to_string(l) +
-                                          " exceeds the eigensolver limit of " +
-                                          std::to_string(h2k::kEigNmax));
+    const int* h = wait_ranks(eg, l);
     int mx = 1;
     for (int c = 0; c < ncl; ++c) {
-      C->krow[cidx(l, c)] = hr[c];
-      C->kcol[cidx(l, c)] = hc[c];
-      mx = std::max(mx, std::max(hr[c], hc[c]));
+      C->krow[cidx(l, c)] = h[c];
+      C->kcol[cidx(l, c)] = h[ncl + c];
+      mx = std::max(mx, std::max(h[c], h[ncl + c]));
     }
     return pad16(mx);
   };
@@ -480,7 +497,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     eig_level(L, np, G, Gc, Ur_L, Uc_L, rank_r[L], rank_c[L], leaf_sizes.as<int>(), nullptr,
               leaf_sizes.as<int>(), nullptr, 1, np);
   }
-  c = read_ranks(L, rank_r[L], rank_c[L]);
+  c = read_ranks(L);
   cpad[L] = c;
   {
     const Op VC{Ur_L.p(), nullptr, nn2, 0, np}, WC{Uc_L.p(), nullptr, nn2, 0, np};
@@ -631,7 +648,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       G[k].reset();
       Gc[k].reset();
     }
-    const int cl = read_ranks(l, rank_r[l], rank_c[l]);
+    const int cl = read_ranks(l);
     cpad[l] = cl;
     const Op TCr{Ur[l].p(), nullptr, K2, 0, K}, TCc{Uc[l].p(), nullptr, K2, 0, K};
     // projections (nonleafproj)

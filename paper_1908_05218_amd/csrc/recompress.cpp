@@ -97,7 +97,8 @@ h2_mat recompress_impl(h2_ctx ctx, h2_mat M, double eps) {
   Profiler prof;  // off: the recompression is not timed per kernel class
   Buf status(ctx, 4 * sizeof(int));
   H2_HIP(hipMemsetAsync(status.as<int>(), 0, 4 * sizeof(int), st));
-  const EigLevel eg{ctx, st, &prof, status.as<int>(), cplx, sv * sv, false};
+  const EigLevel eg{ctx, st, &prof, status.as<int>(), cplx, sv * sv, false,
+                    ctx->readback(2 * (size_t)nleaf + 4), ctx->rb_ev};
   const std::vector<int>&rr = M->rr, &rc = M->rc;
 
   // ---------------------------------------------------------- task lists
@@ -291,20 +292,12 @@ h2_mat recompress_impl(h2_ctx ctx, h2_mat M, double eps) {
   std::vector<Buf> Ur(L + 1), Uc(L + 1), rank_r(L + 1), rank_c(L + 1), PR(L + 1), PC(L + 1);
   auto read_ranks = [&](int l) {
     const int ncl = 1 << l;
-    std::vector<int> hr(ncl), hc(ncl), stv(4);
-    H2_HIP(hipMemcpyAsync(hr.data(), rank_r[l].as<int>(), ncl * sizeof(int), hipMemcpyDeviceToHost, st));
-    H2_HIP(hipMemcpyAsync(hc.data(), rank_c[l].as<int>(), ncl * sizeof(int), hipMemcpyDeviceToHost, st));
-    H2_HIP(hipMemcpyAsync(stv.data(), status.as<int>(), 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-    H2_HIP(hipStreamSynchronize(st));
-    if (stv[0]) throw Error(H2_ERR_NUMERIC, "non-finite Gram matrix at level " + std::to_string(l));
-    if (stv[1])
-      throw Error(H2_ERR_UNSUPPORTED, "a Gram matrix at level " + std::to_string(l) +
-                                          " exceeds the eigensolver limit");
+    const int* h = wait_ranks(eg, l);
     int mx = 1;
     for (int c = 0; c < ncl; ++c) {
-      X->krow[cidx(l, c)] = hr[c];
-      X->kcol[cidx(l, c)] = hc[c];
-      mx = std::max(mx, std::max(hr[c], hc[c]));
+      X->krow[cidx(l, c)] = h[c];
+      X->kcol[cidx(l, c)] = h[ncl + c];
+      mx = std::max(mx, std::max(h[c], h[ncl + c]));
     }
     return pad16(mx);
   };
