@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <functional>
 #include <unordered_map>
 #include <unordered_set>
 
@@ -437,6 +438,42 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     return pad16(mx);
   };
 
+  // Products whose targets nothing later in the upward pass reads (the
+  // admissible couplings of C, the non-leaf targets kept for the top-down
+  // split, the dense leaf blocks) wait in `later`.  They are enqueued on a
+  // helper stream once the main stream reaches the eigen-decompositions of
+  // a level with at most kFewClusters clusters: those launches (one
+  // workgroup per cluster and side, 64 workgroups on 256 compute units)
+  // leave most of the chip idle, while at the levels below the products
+  // would slow the main stream's Gram sums and eigensolvers about as much
+  // as they gain.  The streams join before the top-down split.  Every
+  // buffer such a product touches stays in `held` until the join, so no
+  // block returns to the pool while the helper stream may still use it.
+  constexpr int kFewClusters = 32;
+  hipStream_t ax = ctx->aux[0];
+  Profiler prof_ax;
+  prof_ax.on = prof.on;
+  prof_ax.stream = ax;
+  Profiler* pax = &prof_ax;
+  std::vector<std::function<void()>> later;
+  std::vector<Buf> held;
+  // a failed product waits for the helper stream before `held` is released
+  struct AuxWait {
+    hipStream_t s;
+    bool armed = false;
+    ~AuxWait() {
+      if (armed) (void)hipStreamSynchronize(s);
+    }
+  } ax_wait{ax};
+  auto flush = [&]() {
+    if (later.empty()) return;
+    H2_HIP(hipEventRecord(ctx->fork_ev, st));
+    H2_HIP(hipStreamWaitEvent(ax, ctx->fork_ev, 0));
+    ax_wait.armed = true;
+    for (auto& f : later) f();
+    later.clear();
+  };
+
   // ============================================================== leaf level
   const LeafPlan& LP = P.leaf;
   const int nnL = s.lev[L].size();
@@ -550,37 +587,43 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     const int nbt = std::max(1, LP.n_blue_tiles);
     Acc_L = Buf(ctx, (size_t)nbt * 4 * c * c * eb, bulk, cplx);
     zero(st, Acc_L.p(), (long long)nbt * 4 * c * c);
-    gemm(st, pp, kKindTriple, dl(LP.adm_R), c, c, np, Op{LA.p(), nullptr, las, 0, c}, false,
-         Op{RB.p(), nullptr, las, 0, np}, false, C->S[L].p(), (long long)c * c, c, 0, 0, 1, 1);
     gemm(st, pp, kKindTriple, dl(LP.adm_B), c, c, np, Op{LA.p(), nullptr, las, 0, c}, false,
          Op{RB.p(), nullptr, las, 0, np}, false, Acc_L.p(), 4LL * c * c, 2 * c, c,
          (long long)c * 2 * c, 1, 1);
+    later.push_back([=, &dl, &LP, la = LA.p(), rb = RB.p(), out = C->S[L].p()] {
+      gemm(ax, pax, kKindTriple, dl(LP.adm_R), c, c, np, Op{la, nullptr, las, 0, c}, false,
+           Op{rb, nullptr, las, 0, np}, false, out, (long long)c * c, c, 0, 0, 1, 1);
+    });
+    held.push_back(std::move(LA));
+    held.push_back(std::move(RB));
   }
-  {
-    // dense targets: exact leaf products with admissible factors densified
-    FC = Buf(ctx, (size_t)nnL * nn2 * eb, bulk, cplx);
-    zero(st, FC.p(), nnL * nn2);
-    Buf DA(ctx, (size_t)nnL * nn2 * eb, bulk, cplx), DB(ctx, (size_t)nnL * nn2 * eb, bulk, cplx);
-    {
-      Buf T(ctx, (size_t)nnL * np * std::max(rcA[L], rcB[L]) * eb, bulk, cplx);
-      gemm(st, pp, kKindOther, dl(LP.densA1), np, rcA[L], rrA[L],
-           Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, false,
-           Op{Ad->S[L].p(), nullptr, (long long)rrA[L] * rcA[L], 0, rrA[L]}, false, T.p(),
-           (long long)np * rcA[L], np, 0, 0, 1, 0);
-      gemm(st, pp, kKindOther, dl(LP.densA2), np, np, rcA[L],
-           Op{T.p(), nullptr, (long long)np * rcA[L], 0, np}, false,
-           Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, true, DA.p(), nn2, np, 0, 0, 1, 0);
-      gemm(st, pp, kKindOther, dl(LP.densB1), np, rcB[L], rrB[L],
-           Op{Bd->V.p(), nullptr, B->V_stride, 0, np}, false,
-           Op{Bd->S[L].p(), nullptr, (long long)rrB[L] * rcB[L], 0, rrB[L]}, false, T.p(),
-           (long long)np * rcB[L], np, 0, 0, 1, 0);
-      gemm(st, pp, kKindOther, dl(LP.densB2), np, np, rcB[L],
-           Op{T.p(), nullptr, (long long)np * rcB[L], 0, np}, false,
-           Op{Bd->W.p(), nullptr, B->W_stride, 0, np}, true, DB.p(), nn2, np, 0, 0, 1, 0);
-    }
-    gemm(st, pp, kKindTriple, dl(LP.dense), np, np, np, Op{Ad->F.p(), DA.p(), nn2, nn2, np}, false,
-         Op{Bd->F.p(), DB.p(), nn2, nn2, np}, false, FC.p(), nn2, np, 0, 0, 1, 1);
-  }
+  // dense targets: exact leaf products with admissible factors densified
+  FC = Buf(ctx, (size_t)nnL * nn2 * eb, bulk, cplx);
+  zero(st, FC.p(), nnL * nn2);
+  later.push_back([=, &dl, &LP, &held, &rrA, &rcA, &rrB, &rcB, fc = FC.p()] {
+    held.emplace_back(ctx, (size_t)nnL * nn2 * eb, bulk, cplx);
+    void* DA = held.back().p();
+    held.emplace_back(ctx, (size_t)nnL * nn2 * eb, bulk, cplx);
+    void* DB = held.back().p();
+    held.emplace_back(ctx, (size_t)nnL * np * std::max(rcA[L], rcB[L]) * eb, bulk, cplx);
+    void* T = held.back().p();
+    gemm(ax, pax, kKindOther, dl(LP.densA1), np, rcA[L], rrA[L],
+         Op{Ad->V.p(), nullptr, A->V_stride, 0, np}, false,
+         Op{Ad->S[L].p(), nullptr, (long long)rrA[L] * rcA[L], 0, rrA[L]}, false, T,
+         (long long)np * rcA[L], np, 0, 0, 1, 0);
+    gemm(ax, pax, kKindOther, dl(LP.densA2), np, np, rcA[L],
+         Op{T, nullptr, (long long)np * rcA[L], 0, np}, false,
+         Op{Ad->W.p(), nullptr, A->W_stride, 0, np}, true, DA, nn2, np, 0, 0, 1, 0);
+    gemm(ax, pax, kKindOther, dl(LP.densB1), np, rcB[L], rrB[L],
+         Op{Bd->V.p(), nullptr, B->V_stride, 0, np}, false,
+         Op{Bd->S[L].p(), nullptr, (long long)rrB[L] * rcB[L], 0, rrB[L]}, false, T,
+         (long long)np * rcB[L], np, 0, 0, 1, 0);
+    gemm(ax, pax, kKindOther, dl(LP.densB2), np, np, rcB[L],
+         Op{T, nullptr, (long long)np * rcB[L], 0, np}, false,
+         Op{Bd->W.p(), nullptr, B->W_stride, 0, np}, true, DB, nn2, np, 0, 0, 1, 0);
+    gemm(ax, pax, kKindTriple, dl(LP.dense), np, np, np, Op{Ad->F.p(), DA, nn2, nn2, np}, false,
+         Op{Bd->F.p(), DB, nn2, nn2, np}, false, fc, nn2, np, 0, 0, 1, 1);
+  });
 
   // ========================================================= non-leaf levels
   std::vector<Buf> Ur(L + 1), Uc(L + 1), SNL(L + 1);
@@ -641,7 +684,9 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
          K, cc, 0, 1, 0);
     gemm(st, pp, kKindGram, dl(Q.G3c), K, K, rcB[l], Op{Qm.p(), nullptr, qs, 0, K}, false,
          Op{Qm.p(), nullptr, qs, 0, K}, true, Gc[2].p(), K2, K, 0, 0, 1, 0, kConjB | kLowerOnly);
-    // new transfer matrices
+    // new transfer matrices (the deferred products start here when the
+    // level's eigen-decompositions leave most compute units idle)
+    if ((1 << l) <= kFewClusters) flush();
     eig_level(l, K, G, Gc, Ur[l], Uc[l], rank_r[l], rank_c[l], rank_r[ch].as<int>(),
               rank_r[ch].as<int>() + 1, rank_c[ch].as<int>(), rank_c[ch].as<int>() + 1, 2, cc);
     for (int k = 0; k < 3; ++k) {
@@ -700,10 +745,13 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       gemm(st, pp, kKindTarget, dl(Q.c1X), cl, K, K, TCr, true, AccT, false, X1.p(),
            (long long)cl * K, cl, 0, 0, 1, 0, kConjA);
       const Op X1o{X1.p(), nullptr, (long long)cl * K, 0, cl};
-      gemm(st, pp, kKindTarget, dl(Q.c1_R), cl, cl, K, X1o, false, TCc, false, C->S[l].p(), cs, cl,
-           0, 0, 1, 1, kConjB);
       gemm(st, pp, kKindTarget, dl(Q.c1_B), cl, cl, K, X1o, false, TCc, false, Acc_l.p(), acs,
            2 * cl, cl, (long long)cl * 2 * cl, 1, 1, kConjB);
+      later.push_back([=, &dl, d = &Q.c1_R, out = C->S[l].p()] {
+        gemm(ax, pax, kKindTarget, dl(*d), cl, cl, K, X1o, false, TCc, false, out, cs, cl, 0, 0, 1,
+             1, kConjB);
+      });
+      held.push_back(std::move(X1));
     }
     // cases 2-4 (nonleafcoup_simple), re-associated: for an admissible B
     // factor sum_J Ahat_IJ (S^B_JK P^B_K) = (sum_J Ahat_IJ S^B_JK) P^B_K, and
@@ -724,58 +772,85 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     };
     const Tgt tR{C->S[l].p(), cs, cl, 0, 0}, tB{Acc_l.p(), acs, 2 * cl, cl, (long long)cl * 2 * cl},
         tNL{SNL[l].p(), cs, cl, 0, 0};
-    const long long wns = (long long)cl * rcB[l], wrs = (long long)rrA[l] * cl;
-    auto stage1 = [&](const TaskList& wnl, const TaskList& wr, Buf& Wn, Buf& Wr) {
-      const DevList &dn = dl(wnl), &dr = dl(wr);
-      if (dn.nout) {
-        Wn = Buf(ctx, (size_t)dn.nout * wns * eb, bulk, cplx);
-        gemm(st, pp, kKindTriple, dn, cl, rcB[l], rrB[l], AhatT, false, SBo, false, Wn.p(), wns,
-             cl, 0, 0, 1, 0);
-      }
-      if (dr.nout) {
-        Wr = Buf(ctx, (size_t)dr.nout * wrs * eb, bulk, cplx);
-        gemm(st, pp, kKindTriple, dr, rrA[l], cl, rcA[l], SAo, false, BhatT, false, Wr.p(), wrs,
-             rrA[l], 0, 0, 1, 0);
+    // stage 1: W_nl = Ahat S^B and W_r = S^A Bhat of one target class
+    // (temporaries into `keep`); stage 2: the projections into the targets
+    struct Cases24 {
+      h2_ctx ctx;
+      bool bulk, cplx;
+      size_t eb;
+      int cl, rcB, rrA, rrB, rcA;
+      Op AhatT, BhatT, SBo, SAo, PBo, PAo;
+      void *PA, *PB;
+      long long wns, wrs;
+      void run(hipStream_t s, Profiler* pp, const DevList& dn, const DevList& dr,
+               const DevList& fnl, const DevList& fr, const DevList& fboth, const Tgt& t,
+               std::vector<Buf>& keep) const {
+        void *Wn = nullptr, *Wr = nullptr;
+        if (dn.nout) {
+          keep.emplace_back(ctx, (size_t)dn.nout * wns * eb, bulk, cplx);
+          Wn = keep.back().p();
+          gemm(s, pp, kKindTriple, dn, cl, rcB, rrB, AhatT, false, SBo, false, Wn, wns, cl, 0, 0,
+               1, 0);
+        }
+        if (dr.nout) {
+          keep.emplace_back(ctx, (size_t)dr.nout * wrs * eb, bulk, cplx);
+          Wr = keep.back().p();
+          gemm(s, pp, kKindTriple, dr, rrA, cl, rcA, SAo, false, BhatT, false, Wr, wrs, rrA, 0, 0,
+               1, 0);
+        }
+        if (rcB == rrA && Wn && Wr) {
+          // one pass over the targets: [W_nl | P^A_I] x [P^B_K ; W_r]
+          gemm(s, pp, kKindTarget, fboth, cl, cl, rcB, Op{Wn, PA, wns, (long long)cl * rrA, cl},
+               false, Op{PB, Wr, (long long)rcB * cl, wrs, rcB}, false, t.p, t.stride, t.ld, t.sr,
+               t.sc, 1, 1);
+          return;
+        }
+        if (Wn)
+          gemm(s, pp, kKindTarget, fnl, cl, cl, rcB, Op{Wn, nullptr, wns, 0, cl}, false, PBo, false,
+               t.p, t.stride, t.ld, t.sr, t.sc, 1, 1);
+        if (Wr)
+          gemm(s, pp, kKindTarget, fr, cl, cl, rrA, PAo, false, Op{Wr, nullptr, wrs, 0, rrA}, false,
+               t.p, t.stride, t.ld, t.sr, t.sc, 1, 1);
       }
     };
-    auto stage2 = [&](const TaskList& fnl, const TaskList& fr, const TaskList& fboth,
-                      const Buf& Wn, const Buf& Wr, const Tgt& t) {
-      if (rcB[l] == rrA[l] && Wn.bytes() && Wr.bytes()) {
-        // one pass over the targets: [W_nl | P^A_I] x [P^B_K ; W_r]
-        gemm(st, pp, kKindTarget, dl(fboth), cl, cl, rcB[l],
-             Op{Wn.p(), PA_l.p(), wns, (long long)cl * rrA[l], cl}, false,
-             Op{PB_l.p(), Wr.p(), (long long)rcB[l] * cl, wrs, rcB[l]}, false, t.p, t.stride, t.ld,
-             t.sr, t.sc, 1, 1);
-        return;
-      }
-      if (Wn.bytes())
-        gemm(st, pp, kKindTarget, dl(fnl), cl, cl, rcB[l], Op{Wn.p(), nullptr, wns, 0, cl}, false,
-             PBo, false, t.p, t.stride, t.ld, t.sr, t.sc, 1, 1);
-      if (Wr.bytes())
-        gemm(st, pp, kKindTarget, dl(fr), cl, cl, rrA[l], PAo, false,
-             Op{Wr.p(), nullptr, wrs, 0, rrA[l]}, false, t.p, t.stride, t.ld, t.sr, t.sc, 1, 1);
-    };
+    const Cases24 c24{ctx, bulk, cplx, eb, cl, rcB[l], rrA[l], rrB[l], rcA[l], AhatT, BhatT, SBo,
+                      SAo, PBo, PAo, PA_l.p(), PB_l.p(),
+                      (long long)cl * rcB[l], (long long)rrA[l] * cl};
     {
-      Buf Wn, Wr;
-      stage1(Q.w_nl_R, Q.w_r_R, Wn, Wr);
-      stage2(Q.f_nl_R, Q.f_r_R, Q.f_R, Wn, Wr, tR);
+      std::vector<Buf> keep;  // main-stream temporaries, freed in stream order
+      c24.run(st, pp, dl(Q.w_nl_B), dl(Q.w_r_B), dl(Q.f_nl_B), dl(Q.f_r_B), dl(Q.f_B), tB, keep);
     }
-    {
-      Buf Wn, Wr;
-      stage1(Q.w_nl_B, Q.w_r_B, Wn, Wr);
-      stage2(Q.f_nl_B, Q.f_r_B, Q.f_B, Wn, Wr, tB);
+    // admissible targets (final couplings of C) and non-leaf targets (read
+    // by the top-down split only): deferred
+    for (int r = 1; r >= 0; --r) {
+      const Tgt t = r ? tR : tNL;
+      const DevList *dn = &dl(r ? Q.w_nl_R : Q.w_nl_NL), *dr = &dl(r ? Q.w_r_R : Q.w_r_NL),
+                    *fnl = &dl(r ? Q.f_nl_R : Q.f_nl_NL), *fr = &dl(r ? Q.f_r_R : Q.f_r_NL),
+                    *fb = &dl(r ? Q.f_R : Q.f_NL);
+      later.push_back([=, &held] { c24.run(ax, pax, *dn, *dr, *fnl, *fr, *fb, t, held); });
     }
-    {
-      Buf Wn, Wr;
-      stage1(Q.w_nl_NL, Q.w_r_NL, Wn, Wr);
-      stage2(Q.f_nl_NL, Q.f_r_NL, Q.f_NL, Wn, Wr, tNL);
-    }
+    // this level's operands of the deferred products stay alive until the join
+    held.push_back(std::move(PA_ch));
+    held.push_back(std::move(PB_ch));
+    held.push_back(std::move(Ahat_ch));
+    held.push_back(std::move(Bhat_ch));
     PA_ch = std::move(PA_l);
     PB_ch = std::move(PB_l);
     Ahat_ch = std::move(Ahat_l);
     Bhat_ch = std::move(Bhat_l);
     Acc_ch = std::move(Acc_l);
   }
+
+  // join: the split reads the deferred products' targets
+  flush();
+  if (ax_wait.armed) {
+    H2_HIP(hipEventRecord(ctx->join_ev[0], ax));
+    H2_HIP(hipStreamWaitEvent(st, ctx->join_ev[0], 0));
+    ax_wait.armed = false;
+  }
+  held.clear();  // later users of these blocks are ordered after the join
+  prof.recs.insert(prof.recs.end(), prof_ax.recs.begin(), prof_ax.recs.end());
+  prof_ax.recs.clear();
 
   // ===================================================== top-down split
   for (int l = lmin; l < L; ++l) {
