@@ -583,7 +583,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     }
     // products into admissible and blue targets (leafcoup_simple)
     C->S[L] = Buf(ctx, (size_t)nnL * c * c * eb, bulk, cplx);
-    zero(st, C->S[L].p(), (long long)nnL * c * c);
+    later.push_back([=, out = C->S[L].p()] { zero(ax, out, (long long)nnL * c * c); });
     const int nbt = std::max(1, LP.n_blue_tiles);
     Acc_L = Buf(ctx, (size_t)nbt * 4 * c * c * eb, bulk, cplx);
     zero(st, Acc_L.p(), (long long)nbt * 4 * c * c);
@@ -599,8 +599,8 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   }
   // dense targets: exact leaf products with admissible factors densified
   FC = Buf(ctx, (size_t)nnL * nn2 * eb, bulk, cplx);
-  zero(st, FC.p(), nnL * nn2);
   later.push_back([=, &dl, &LP, &held, &rrA, &rcA, &rrB, &rcB, fc = FC.p()] {
+    zero(ax, fc, nnL * nn2);
     held.emplace_back(ctx, (size_t)nnL * nn2 * eb, bulk, cplx);
     void* DA = held.back().p();
     held.emplace_back(ctx, (size_t)nnL * nn2 * eb, bulk, cplx);
@@ -732,9 +732,12 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
          (long long)cl * 2 * rcA[l], 1, 0);
     // targets of this level
     C->S[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * eb, bulk, cplx);
-    zero(st, C->S[l].p(), (long long)std::max(1, nn) * cl * cl);
     SNL[l] = Buf(ctx, (size_t)std::max(1, nn) * cl * cl * eb, bulk, cplx);
-    zero(st, SNL[l].p(), (long long)std::max(1, nn) * cl * cl);
+    // both written only by deferred products: cleared on the helper stream
+    later.push_back([=, a = C->S[l].p(), b = SNL[l].p(), n = (long long)std::max(1, nn) * cl * cl] {
+      zero(ax, a, n);
+      zero(ax, b, n);
+    });
     const int nbt = std::max(1, Q.n_blue_tiles);
     Buf Acc_l(ctx, (size_t)nbt * 4 * cl * cl * eb, bulk, cplx);
     zero(st, Acc_l.p(), (long long)nbt * 4 * cl * cl);
