@@ -21,18 +21,28 @@ h2_status set_error(h2_status s, const std::string& msg) {
   return s;
 }
 
+static hipEvent_t take_event(std::vector<hipEvent_t>* pool) {
+  hipEvent_t e = nullptr;
+  if (pool && !pool->empty()) {
+    e = pool->back();
+    pool->pop_back();
+  } else {
+    hipEventCreate(&e);
+  }
+  return e;
+}
+
 void Profiler::begin(int kind, double flops, hipEvent_t* out_a) {
   (void)kind;
   (void)flops;
   if (!on) return;
-  hipEventCreate(out_a);
+  *out_a = take_event(pool);
   hipEventRecord(*out_a, stream);
 }
 
 void Profiler::end(hipEvent_t a, int kind, double flops) {
   if (!on) return;
-  hipEvent_t b;
-  hipEventCreate(&b);
+  hipEvent_t b = take_event(pool);
   hipEventRecord(b, stream);
   recs.push_back({a, b, kind, flops});
 }
@@ -49,8 +59,13 @@ void Profiler::collect(double* ms, long long* launches, double* flops) {
     ms[r.kind] += t;
     launches[r.kind] += 1;
     flops[r.kind] += r.flops;
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    if (pool) {
+      pool->push_back(r.a);
+      pool->push_back(r.b);
+    } else {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
   }
   recs.clear();
 }
@@ -736,6 +751,7 @@ h2_ctx_s::~h2_ctx_s() {
   }
   if (fork_ev) hipEventDestroy(fork_ev);
   if (rb_ev) hipEventDestroy(rb_ev);
+  for (hipEvent_t e : prof_events) hipEventDestroy(e);
   if (rb_host) hipHostFree(rb_host);
   if (stream) hipStreamDestroy(stream);
 }

@@ -87,6 +87,7 @@ struct h2_ctx_s {
   size_t rb_n = 0;
   hipEvent_t rb_ev = nullptr;
   int* readback(size_t n);  // at least n ints
+  std::vector<hipEvent_t> prof_events;  // timing events of the per-class split, reused
   bool profiling = false;
   // external supplier of device memory (h2_ctx_create); without one the
   // context calls hipMalloc and pools freed blocks
@@ -287,6 +288,8 @@ enum KernelKind {
 struct Profiler {
   bool on = false;
   hipStream_t stream = nullptr;
+  // timing events to reuse (the context's), else created and destroyed per launch
+  std::vector<hipEvent_t>* pool = nullptr;
   struct Rec {
     hipEvent_t a, b;
     int kind;

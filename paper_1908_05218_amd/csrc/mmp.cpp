@@ -362,6 +362,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   Profiler prof;
   prof.on = ctx->profiling;
   prof.stream = st;
+  prof.pool = &ctx->prof_events;
   Profiler* pp = &prof;
 
   // events around the numeric phase; handed to C at the end (destroyed here
@@ -454,6 +455,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   Profiler prof_ax;
   prof_ax.on = prof.on;
   prof_ax.stream = ax;
+  prof_ax.pool = &ctx->prof_events;
   Profiler* pax = &prof_ax;
   std::vector<std::function<void()>> later;
   std::vector<Buf> held;
