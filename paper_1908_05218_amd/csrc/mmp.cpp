@@ -484,6 +484,16 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   H2_HIP(hipMemcpyAsync(leaf_sizes.as<int>(), s.leaf_size.data(), nleaf * sizeof(int),
                         hipMemcpyHostToDevice, st));
   Buf Ur_L, Uc_L;
+  // FP32-bulk products read the new bases through float copies: the values
+  // their FP32 arithmetic rounds the FP64 bases to anyway, at half the bytes
+  std::vector<Buf> Urf(L + 1), Ucf(L + 1);
+  auto narrow = [&](const Buf& src, Buf& dst) {
+    const long long n = (long long)(src.bytes() / sizeof(double));
+    if (!bulk || n <= 0) return;
+    dst = Buf(ctx, (size_t)n * sizeof(float), true);
+    H2_HIP(h2k::launch_d2f(src.as<double>(), dst.as<float>(), n, st));
+  };
+  auto bas = [&](const Buf& f, const Buf& d) { return bulk ? f.p() : d.p(); };
   Buf PA_L, PB_L;       // projections at the leaves
   Buf Ahat_L, Bhat_L;   // collected leaf blocks, 2x2 grouped
   Buf Acc_L;            // blue accumulators of the leaf level
@@ -539,7 +549,9 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   c = read_ranks(L);
   cpad[L] = c;
   {
-    const Op VC{Ur_L.p(), nullptr, nn2, 0, np}, WC{Uc_L.p(), nullptr, nn2, 0, np};
+    narrow(Ur_L, Urf[L]);
+    narrow(Uc_L, Ucf[L]);
+    const Op VC{bas(Urf[L], Ur_L), nullptr, nn2, 0, np}, WC{bas(Ucf[L], Uc_L), nullptr, nn2, 0, np};
     const Op FA{Ad->F.p(), nullptr, nn2, 0, np}, FB{Bd->F.p(), nullptr, nn2, 0, np};
     // projections (leafproj)
     PA_L = Buf(ctx, (size_t)nleaf * c * rrA[L] * eb, bulk, cplx);
@@ -697,7 +709,9 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     }
     const int cl = read_ranks(l);
     cpad[l] = cl;
-    const Op TCr{Ur[l].p(), nullptr, K2, 0, K}, TCc{Uc[l].p(), nullptr, K2, 0, K};
+    narrow(Ur[l], Urf[l]);
+    narrow(Uc[l], Ucf[l]);
+    const Op TCr{bas(Urf[l], Ur[l]), nullptr, K2, 0, K}, TCc{bas(Ucf[l], Uc[l]), nullptr, K2, 0, K};
     // projections (nonleafproj)
     Buf PA_l(ctx, (size_t)ncl * cl * rrA[l] * eb, bulk, cplx);
     Buf PB_l(ctx, (size_t)ncl * rcB[l] * cl * eb, bulk, cplx);
@@ -867,10 +881,10 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
     if (SP.X.nout() == 0) continue;
     const long long xs = (long long)K * cl;
     Buf XS(ctx, (size_t)nn * xs * eb, bulk, cplx);
-    gemm(st, pp, kKindOther, dl(SP.X), K, cl, cl, Op{Ur[l].p(), nullptr, (long long)K * K, 0, K},
+    gemm(st, pp, kKindOther, dl(SP.X), K, cl, cl, Op{bas(Urf[l], Ur[l]), nullptr, (long long)K * K, 0, K},
          false, Op{SNL[l].p(), nullptr, (long long)cl * cl, 0, cl}, false, XS.p(), xs, K, 0, 0, 1, 0);
     const Op XSo{XS.p(), nullptr, xs, 0, K, cc, 0};
-    const Op TCc{Uc[l].p(), nullptr, (long long)K * K, 0, K, cc, 0};
+    const Op TCc{bas(Ucf[l], Uc[l]), nullptr, (long long)K * K, 0, K, cc, 0};
     gemm(st, pp, kKindOther, dl(SP.toR), cc, cc, cl, XSo, false, TCc, true, C->S[ch].p(),
          (long long)cc * cc, cc, 0, 0, 1, 1);
     if (ch < L)
@@ -881,11 +895,11 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
       Buf ZF(ctx, (size_t)nnL * np * cc * eb, bulk, cplx);
       gemm(st, pp, kKindOther, dl(SP.toF), cc, cc, cl, XSo, false, TCc, true, YF.p(),
            (long long)cc * cc, cc, 0, 0, 1, 0);
-      gemm(st, pp, kKindOther, dl(SP.F1), np, cc, cc, Op{Ur[L].p(), nullptr, nn2, 0, np}, false,
+      gemm(st, pp, kKindOther, dl(SP.F1), np, cc, cc, Op{bas(Urf[L], Ur[L]), nullptr, nn2, 0, np}, false,
            Op{YF.p(), nullptr, (long long)cc * cc, 0, cc}, false, ZF.p(), (long long)np * cc, np,
            0, 0, 1, 0);
       gemm(st, pp, kKindOther, dl(SP.F2), np, np, cc, Op{ZF.p(), nullptr, (long long)np * cc, 0, np},
-           false, Op{Uc[L].p(), nullptr, nn2, 0, np}, true, FC.p(), nn2, np, 0, 0, 1, 1);
+           false, Op{bas(Ucf[L], Uc[L]), nullptr, nn2, 0, np}, true, FC.p(), nn2, np, 0, 0, 1, 1);
     }
   }
   if (bulk) {
