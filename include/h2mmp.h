@@ -281,7 +281,10 @@ h2_status h2_release(h2_ctx ctx, uint64_t ticket);
  * stream: see the conventions above.  The call blocks the host once per
  * level to read back the kept ranks (they size the next level's launches);
  * the launches after the last level (the top-down split, the conversion of
- * FP32-bulk results) may still run when it returns.
+ * FP32-bulk results) may still run when it returns.  The products whose
+ * targets only the top-down split reads run on one of the context's helper
+ * streams, forked from the call's stream and joined back into it by events
+ * before the split, so the conventions above hold for the whole call.
  * Errors: H2_ERR_STRUCTURE, H2_ERR_ARG (eps < 0, bad mode/precision),
  * H2_ERR_UNSUPPORTED (a cluster whose Gram dimension exceeds the on-chip
  * eigensolver limit, reported in the message), H2_ERR_OOM, H2_ERR_NUMERIC. */
