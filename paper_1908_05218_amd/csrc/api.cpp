@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <exception>
 #include <memory>
@@ -643,6 +644,9 @@ void* h2_ctx_s::alloc(size_t bytes, bool is_f32, bool is_cplx) {
 }
 
 void* h2_ctx_s::alloc_raw(size_t bytes, bool is_f32) {
+  if (n_alloc++ == fail_alloc)
+    throw h2::Error(H2_ERR_OOM, "allocation " + std::to_string(fail_alloc) +
+                                    " refused (H2_FAIL_ALLOC)");
   bytes = size_class(bytes);
   // best fit among the cached blocks, wasting at most a quarter
   auto it = pool.lower_bound(bytes);
@@ -811,6 +815,7 @@ h2_status h2_ctx_create(int device, size_t hbm_budget, const h2_allocator* alloc
   auto* c = new h2_ctx_s();
   c->device = device;
   c->budget = hbm_budget;
+  if (const char* f = std::getenv("H2_FAIL_ALLOC")) c->fail_alloc = std::atoll(f);
   if (alloc) {
     c->hook = *alloc;
     c->has_hook = true;

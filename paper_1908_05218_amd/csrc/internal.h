@@ -93,6 +93,11 @@ struct h2_ctx_s {
   // context calls hipMalloc and pools freed blocks
   h2_allocator hook{};
   bool has_hook = false;
+  // failure injection for tests of the error paths: the allocation with
+  // this index (counted from the context's creation) raises H2_ERR_OOM once;
+  // set from the environment variable H2_FAIL_ALLOC at creation, -1: never
+  long long fail_alloc = -1;
+  long long n_alloc = 0;
   std::multimap<size_t, void*> pool;
   std::unordered_map<void*, size_t> live;
   // device regions a call uses that the context did not allocate (the

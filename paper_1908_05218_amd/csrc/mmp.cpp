@@ -328,14 +328,14 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   const auto t_sym0 = std::chrono::steady_clock::now();
   Shape& sh = *A->shape;
   const Structure& s = sh.s;
-  if (!sh.plan) {
-    sh.plan = std::make_unique<Plan>();
-    std::string err = build_plan(s, *sh.plan);
-    if (!err.empty()) {
-      sh.plan.reset();
-      throw Error(H2_ERR_INTERNAL, err);
-    }
-    sh.dplan = upload_plan(ctx, *sh.plan);
+  if (!sh.plan || !sh.dplan) {
+    // both or neither: a failed upload leaves the structure without a plan
+    auto plan = std::make_unique<Plan>();
+    std::string err = build_plan(s, *plan);
+    if (!err.empty()) throw Error(H2_ERR_INTERNAL, err);
+    auto dplan = upload_plan(ctx, *plan);
+    sh.plan = std::move(plan);
+    sh.dplan = std::move(dplan);
   }
   const double sym_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_sym0).count();
@@ -459,19 +459,23 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   Profiler* pax = &prof_ax;
   std::vector<std::function<void()>> later;
   std::vector<Buf> held;
-  // a failed product waits for the helper stream before `held` is released
+  // a failed product waits for the helper stream before the buffers its
+  // deferred products use are released: guards declared after `held` and
+  // after the non-leaf operands below
   struct AuxWait {
     hipStream_t s;
-    bool armed = false;
+    const bool* armed;
     ~AuxWait() {
-      if (armed) (void)hipStreamSynchronize(s);
+      if (*armed) (void)hipStreamSynchronize(s);
     }
-  } ax_wait{ax};
+  };
+  bool ax_armed = false;
+  const AuxWait ax_wait{ax, &ax_armed};
   auto flush = [&]() {
     if (later.empty()) return;
     H2_HIP(hipEventRecord(ctx->fork_ev, st));
     H2_HIP(hipStreamWaitEvent(ax, ctx->fork_ev, 0));
-    ax_wait.armed = true;
+    ax_armed = true;
     for (auto& f : later) f();
     later.clear();
   };
@@ -645,6 +649,7 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
   Uc[L] = std::move(Uc_L);
   Buf PA_ch = std::move(PA_L), PB_ch = std::move(PB_L);
   Buf Ahat_ch = std::move(Ahat_L), Bhat_ch = std::move(Bhat_L), Acc_ch = std::move(Acc_L);
+  const AuxWait ax_wait_nl{ax, &ax_armed};
   for (int l = L - 1; l >= lmin; --l) {
     const int ch = l + 1;
     const int cc = cpad[ch];
@@ -862,10 +867,10 @@ h2_status mmp_impl(h2_ctx ctx, h2_mat A, h2_mat B, double eps, int mode, int pre
 
   // join: the split reads the deferred products' targets
   flush();
-  if (ax_wait.armed) {
+  if (ax_armed) {
     H2_HIP(hipEventRecord(ctx->join_ev[0], ax));
     H2_HIP(hipStreamWaitEvent(st, ctx->join_ev[0], 0));
-    ax_wait.armed = false;
+    ax_armed = false;
   }
   held.clear();  // later users of these blocks are ordered after the join
   prof.recs.insert(prof.recs.end(), prof_ax.recs.begin(), prof_ax.recs.end());
