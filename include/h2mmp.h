@@ -100,8 +100,11 @@ typedef struct {
  * device memory the context may hold; 0 means no bound.  alloc (nullable,
  * copied): the supplier of every device allocation of the context and of its
  * serving slots; without one the context takes memory with hipMalloc and
- * keeps freed blocks in a pool of its own.  Errors: H2_ERR_DEVICE (no such
- * device), H2_ERR_ARG (out == NULL, or an allocator without alloc or free). */
+ * keeps freed blocks in a pool of its own.  For tests of the error paths,
+ * the environment variable H2_FAIL_ALLOC=n (read here) makes the context's
+ * allocation number n (counted from 0 over its lifetime) fail once with
+ * H2_ERR_OOM.  Errors: H2_ERR_DEVICE (no such device), H2_ERR_ARG
+ * (out == NULL, or an allocator without alloc or free). */
 h2_status h2_ctx_create(int device, size_t hbm_budget, const h2_allocator* alloc, h2_ctx* out);
 void h2_ctx_destroy(h2_ctx ctx);
 
