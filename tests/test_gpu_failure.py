@@ -110,3 +110,49 @@ def test_every_allocation_failure_of_a_product_is_recoverable():
         os.environ.pop("H2_FAIL_ALLOC", None)
     print(f"allocation sweep: the product stopped at each of {stopped} allocations", flush=True)
     assert stopped > 20
+
+
+def test_every_allocation_failure_of_a_recompression_is_recoverable():
+    """The same sweep over h2_recompress: each stopped call raises
+    H2_ERR_OOM and the context then recompresses A again, bit-identical to
+    an untouched context's result."""
+    import os
+    print("case allocation failure sweep recompress plates4096", flush=True)
+    A = cases.plates(4096)
+    keys = ("krow", "kcol", "V", "W", "Er", "Ec", "S", "F")
+    ref_ctx = h2.Context(0)
+    try:
+        rA = h2.load(ref_ctx, A.to_flat())
+        ref = h2.export(h2.recompress(ref_ctx, rA, 1e-4))
+    finally:
+        ref_ctx.close()
+    stopped = 0
+    idx = 0
+    try:
+        while True:
+            os.environ["H2_FAIL_ALLOC"] = str(idx)
+            ctx = h2.Context(0)
+            try:
+                try:
+                    dA = h2.load(ctx, A.to_flat())
+                except h2.H2Error as e:
+                    assert e.code == 3, e
+                    idx += 1
+                    continue
+                try:
+                    h2.recompress(ctx, dA, 1e-4).free()
+                    break
+                except h2.H2Error as e:
+                    assert e.code == 3 and "H2_FAIL_ALLOC" in str(e), e
+                stopped += 1
+                got = h2.export(h2.recompress(ctx, dA, 1e-4))
+                for k in keys:
+                    assert np.array_equal(np.asarray(got[k]), np.asarray(ref[k])), (idx, k)
+            finally:
+                ctx.close()
+            idx += 1
+            assert idx < 5000
+    finally:
+        os.environ.pop("H2_FAIL_ALLOC", None)
+    print(f"allocation sweep: the recompression stopped at each of {stopped} allocations", flush=True)
+    assert stopped > 10
