@@ -156,3 +156,44 @@ def test_every_allocation_failure_of_a_recompression_is_recoverable():
         os.environ.pop("H2_FAIL_ALLOC", None)
     print(f"allocation sweep: the recompression stopped at each of {stopped} allocations", flush=True)
     assert stopped > 10
+
+
+def test_every_allocation_failure_of_a_build_is_recoverable():
+    """The same sweep over h2_build with recompression: each stopped call
+    raises H2_ERR_OOM and the context then builds the matrix again,
+    bit-identical to an untouched context's."""
+    import os
+    from h2inputs import configs
+    print("case allocation failure sweep build+recompress plates4096", flush=True)
+    w = configs.plates_n(4096)
+    args = (w.pts, w.leaf_size, w.eta, w.order, w.kernel.self_value)
+    keys = ("krow", "kcol", "V", "W", "Er", "Ec", "S", "F")
+    ref_ctx = h2.Context(0)
+    try:
+        ref = h2.export(h2.build(ref_ctx, *args, recompress_eps=1e-5))
+    finally:
+        ref_ctx.close()
+    stopped = 0
+    idx = 0
+    try:
+        while True:
+            os.environ["H2_FAIL_ALLOC"] = str(idx)
+            ctx = h2.Context(0)
+            try:
+                try:
+                    h2.build(ctx, *args, recompress_eps=1e-5).free()
+                    break
+                except h2.H2Error as e:
+                    assert e.code == 3 and "H2_FAIL_ALLOC" in str(e), e
+                stopped += 1
+                got = h2.export(h2.build(ctx, *args, recompress_eps=1e-5))
+                for k in keys:
+                    assert np.array_equal(np.asarray(got[k]), np.asarray(ref[k])), (idx, k)
+            finally:
+                ctx.close()
+            idx += 1
+            assert idx < 5000
+    finally:
+        os.environ.pop("H2_FAIL_ALLOC", None)
+    print(f"allocation sweep: the build stopped at each of {stopped} allocations", flush=True)
+    assert stopped > 10
