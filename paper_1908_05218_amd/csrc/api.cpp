@@ -362,6 +362,10 @@ static inline long long cidx(int l, int c) { return (1LL << l) - 1 + c; }
 // the row tree, dense near field.  The host copy stays with the plan so that
 // the upload needs no host wait.
 void build_matvec_plan(h2_ctx ctx, h2_mat M) {
+  if (M->shape->mv) {
+    M->mv = M->shape->mv;
+    return;
+  }
   const Structure& s = M->st();
   const int L = s.L, nleaf = 1 << L, lo = s.lmin;
   auto mp = std::make_unique<MatvecPlan>();
@@ -455,7 +459,8 @@ void build_matvec_plan(h2_ctx ctx, h2_mat M) {
   }
   H2_HIP(hipMemcpyAsync(base, mp->host.data(), total * sizeof(int), hipMemcpyHostToDevice,
                         ctx->stream));
-  M->mv = std::move(mp);
+  M->shape->mv = std::move(mp);
+  M->mv = M->shape->mv;
 }
 
 // Device bytes of the mat-vec temporaries of M for nrhs right-hand sides

@@ -224,6 +224,9 @@ struct Shape {
   Structure s;
   std::unique_ptr<Plan> plan;
   std::unique_ptr<DevPlan> dplan;
+  // the exact mat-vec's task lists (they depend on the structure only),
+  // shared by the matrices of this structure
+  std::shared_ptr<MatvecPlan> mv;
   Buf d_perm, d_leaf_off;
 };
 
@@ -255,7 +258,7 @@ struct h2_mat_s {
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
   bool timing_pending = false;
   // task lists of the exact mat-vec (built when M is made)
-  std::unique_ptr<h2::MatvecPlan> mv;
+  std::shared_ptr<h2::MatvecPlan> mv;
   const h2::Structure& st() const { return shape->s; }
   // wait for the launches of the call that produced M; fills mmp_ms
   void finish();
